@@ -1,0 +1,250 @@
+/*
+ * pmeqeq -- periodic Coulomb potentials, forces and energies (Ewald / smooth
+ * particle-mesh Ewald) and charge equilibration (QEQ) on one AMD MI355X
+ * (gfx950). C ABI.
+ *
+ * Method: Kaymak, Lubbers, Negre, Wall, Niklasson, "GPU-Accelerated
+ * Charge-Equilibration for Shadow Molecular Dynamics in Python"
+ * (arXiv:2503.21176).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Units: Angstrom, elementary charge e, eV. The Coulomb constant
+ *   pq_coulomb_constant() = 14.3996454784 eV*A/e^2 multiplies every energy
+ *   and potential.
+ * - Array pointers are DEVICE pointers on the context's device (for example
+ *   torch tensor data pointers), FP64, C-contiguous: positions and forces are
+ *   n x 3 row-major (x, y, z per atom), per-atom vectors have n entries.
+ *   Pointers documented as "host" are host memory.
+ * - Calls are ordered on the context's HIP stream. A call returns after its
+ *   work is enqueued unless it documents a host synchronisation; outputs are
+ *   valid once the stream reaches that point. The caller owns every array it
+ *   passes; the library never keeps a caller pointer after a call returns.
+ * - Errors: every call returns a pq_status. Negative values are errors, in
+ *   which case outputs are unspecified; pq_last_error() returns a message
+ *   for the calling thread. No C++ exception crosses this boundary.
+ * - A context is not thread safe: one thread at a time per context.
+ */
+#ifndef PMEQEQ_H
+#define PMEQEQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PQ_ABI_VERSION 1
+
+typedef enum pq_status {
+    PQ_OK = 0,
+    PQ_WARN_NOT_CONVERGED = 1, /* solver stopped at max_it; outputs hold the last iterate */
+    PQ_ERR_INVALID = -1,       /* bad argument (null pointer, size, parameter range) */
+    PQ_ERR_BOX = -2,           /* box/cutoff/grid combination not supported */
+    PQ_ERR_CAPACITY = -3,      /* caller buffer too small; required size reported */
+    PQ_ERR_NOMEM = -4,         /* device allocation failed */
+    PQ_ERR_HIP = -5,           /* HIP runtime error */
+    PQ_ERR_TOO_LARGE = -6,     /* request larger than the server's memory budget */
+    PQ_ERR_NAN = -7,           /* non-finite value in an input */
+    PQ_ERR_STATE = -8,         /* call out of order (e.g. no system set) */
+    PQ_ERR_TIMEOUT = -9        /* server poll timed out; the request is still pending */
+} pq_status;
+
+enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1 };
+
+/* Parameters of one periodic system. The names follow the paper's problem
+ * statement for smooth PME (Algorithm "Smooth PME", input line: positions,
+ * charges, box, Ewald parameter, grid dimensions, spline order) and the
+ * regular Ewald sum (eqs. ewald_real, ewald_rec, ewald_self). */
+typedef struct pq_params {
+    double box[3];    /* orthorhombic box edges L_d in A, each > 0                   */
+    double cutoff;    /* real-space cutoff rc in A, > 0; the erfc sum keeps |d| < rc  */
+    double skin;      /* neighbour-list skin in A, >= 0 (list radius rc + skin)        */
+    double alpha;     /* Ewald splitting parameter in 1/A, > 0                         */
+    int32_t grid[3];  /* PME grid K_d: 2^a 3^b 5^c, 2*order <= K_d <= 1024             */
+    int32_t order;    /* PME B-spline order p, 3 <= p <= 8                             */
+    int32_t kmax[3];  /* direct Ewald: k = 2 pi n / L over |n_d| <= kmax_d, 0..64     */
+    int32_t method;   /* PQ_METHOD_PME (grid, order used) or PQ_METHOD_EWALD (kmax)   */
+    int32_t flags;    /* reserved, must be 0                                           */
+} pq_params;
+
+/* Outcome of a Krylov solve (host struct filled by the library). */
+typedef struct pq_solve_info {
+    int32_t iterations;   /* matrix-vector products with the Coulomb operator      */
+    int32_t restarts;     /* GMRES restarts performed                              */
+    double rel_residual;  /* ||b - M z|| / ||b|| of the bordered system at exit    */
+    double lambda;        /* Lagrange multiplier of the charge constraint          */
+} pq_solve_info;
+
+typedef struct pq_ctx pq_ctx;
+
+/* ---- library ------------------------------------------------------------ */
+int pq_abi_version(void);
+/* e^2 / (4 pi eps0) in eV*A. */
+double pq_coulomb_constant(void);
+/* Message of the last failed call on this thread ("" if none). Valid until
+ * the next call on the same thread. */
+const char* pq_last_error(void);
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on HIP device `device`; work is enqueued on `stream`
+ * (a hipStream_t, NULL = the device's null stream). The context owns its
+ * device workspaces (allocated on first use, grown on demand, freed by
+ * pq_destroy). */
+pq_status pq_create(pq_ctx** out, int device, void* stream);
+pq_status pq_set_stream(pq_ctx* ctx, void* stream);
+pq_status pq_destroy(pq_ctx* ctx);
+
+/* ---- system ------------------------------------------------------------- */
+/* Sets the atoms' positions (device, n x 3 FP64, any real values: they are
+ * wrapped into the box) and the parameters, and builds what depends on the
+ * positions only (Section "Cell based Neighbor List"): the wrapped
+ * coordinates, the cell (column) sort, the cluster-pair neighbour list
+ * with radius rc + skin, and the PME B-spline stencils. Every periodic image
+ * closer than rc is included, so boxes shorter than 2 rc are supported.
+ * Host-synchronising (the list size is read back). Re-call when positions
+ * move. n >= 1. */
+pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm);
+
+/* Number of neighbour pairs (i, j, n) with |w_j - w_i + n L| < rc + skin,
+ * each unordered pair once (i < j, or i == j with the image vector n
+ * lexicographically positive), evaluated with the canonical FP64 predicate
+ * d.d < (rc+skin)^2 on the wrapped positions. Host-synchronising.
+ * `pairs` (device int32, 5 x cap, row-major rows i, j, n0, n1, n2, in no
+ * particular order) may be NULL to query the count only; if cap is too small
+ * the call returns PQ_ERR_CAPACITY with *n_pairs (host) set to the count. */
+pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs);
+
+/* ---- Coulomb evaluation ------------------------------------------------- */
+/* Periodic Coulomb potential, force and energy of the charge vector q
+ * (device, n FP64; need not be neutral):
+ *   phi_i = dE_Coul/dq_i = KE [ sum_{(j,n) != (i,0), |d| < rc} q_j erfc(a|d|)/|d|
+ *                               + reciprocal(i) - 2 a/sqrt(pi) q_i - pi Q/(V a^2) ]
+ *   F_i   = -dE_Coul/dr_i,   E_Coul = 1/2 sum_i q_i phi_i,
+ * the Ewald split of the paper's eqs. ewald_general, ewald_real, ewald_rec and
+ * ewald_self, with the reciprocal part by smooth PME (Algorithm "Smooth PME",
+ * steps 1-5) or by the direct k-sum, and a neutralising background term
+ * (zero for neutral q). Outputs (device, FP64, each may be NULL):
+ *   phi[n], force[n*3], energy[4] = {E_Coul, E_real, E_rec, E_self+background}.
+ * Bulk arithmetic is FP32; energies and charge sums are reduced in FP64. */
+pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy);
+
+/* ---- phase timing ---------------------------------------------------------- */
+/* Phases of one Coulomb evaluation, timed with HIP events recorded on the
+ * context's stream around each phase's kernels (the time the device spends
+ * from the phase's first kernel start to its last kernel end). */
+enum {
+    PQ_PHASE_STAGE = 0,    /* charge staging and FP64 charge sum              */
+    PQ_PHASE_PAIR = 1,     /* real-space pair kernel                          */
+    PQ_PHASE_SPREAD = 2,   /* grid clear + B-spline spreading (PME)           */
+    PQ_PHASE_FFT = 3,      /* forward FFT, convolution, inverse FFT (PME)     */
+    PQ_PHASE_GATHER = 4,   /* gather (PME) or structure factors + k-sum (Ewald) */
+    PQ_PHASE_COMBINE = 5,  /* self/background terms, outputs, FP64 energies   */
+    PQ_PHASE_TOTAL = 6,    /* whole evaluation                                */
+    PQ_NPHASE = 7
+};
+/* Enables (on != 0) or disables event timing of pq_coulomb and of the
+ * evaluations inside the solvers. Adds two events per phase per evaluation. */
+pq_status pq_set_timing(pq_ctx* ctx, int on);
+/* Host-synchronising. Writes to ms[0..PQ_NPHASE) (host) the milliseconds
+ * summed over the evaluations timed since the last call, and to *count the
+ * number of those evaluations; then resets both. */
+pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count);
+
+/* ---- charge equilibration ----------------------------------------------- */
+/* Regular QEQ (Section "Regular Born-Oppenheimer MD for a Charge
+ * Equilibration Model"): minimise E(q) = sum q chi + 1/2 sum u q^2 + E_Coul(q)
+ * subject to sum q = q_tot, i.e. solve the bordered system of eq. linear_qeq
+ *   [[C, 1], [1^T, 0]] [q; lambda] = [-chi; q_tot],  C v = u o v + phi[v]
+ * matrix-free (the paper's Cv identity) by restarted GMRES(restart) with the
+ * Jacobi preconditioner diag(u, 1) applied on the right, FP64 Krylov vectors
+ * and FP64 orthogonalisation, each product one FP32-bulk Coulomb evaluation.
+ * Stops when the true relative residual ||b - M z||/||b|| <= tol or after
+ * max_it products (PQ_WARN_NOT_CONVERGED, last iterate returned).
+ *   chi, eta (= u): device n FP64; q0: device n FP64 start vector or NULL (0);
+ *   q: device n FP64 output; force: device n*3 FP64 output F = -dE/dR at the
+ *   solution, or NULL; energy: device FP64[1] output E(q), or NULL;
+ *   info: host, may be NULL. Host-synchronising (convergence checks). */
+pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot,
+                       double tol, int max_it, int restart, const double* q0,
+                       double* q, double* force, double* energy, pq_solve_info* info);
+
+/* One shadow-MD charge step (Section "Shadow Born-Oppenheimer MD"):
+ *   v = phi[n_vec]; q[n] from the quasi-diagonal system of eq. diag_linear_qeq
+ *   (lambda in closed form, FP64 reductions); the shadow force
+ *   F = -d/dR of the shadow energy (eq. qeq_energy) at fixed n and q[n],
+ *   computed as F[q] - F[q - n]; and the n_krylov-step GMRES iterate x from
+ *   x0 = 0 for J x = -(q[n] - n) (eq. Jnddot with omega^2 = 1),
+ *   J = -I - P D^-1 A, P = I - D^-1 1 1^T / (1^T D^-1 1), D = diag(u).
+ * Fixed work: 1 potential + 2 force evaluations + n_krylov products; no host
+ * synchronisation. Outputs (device FP64): q_n[n], force[n*3] (may be NULL),
+ * nddot[n] (may be NULL), energy[2] = {shadow energy, lambda} (may be NULL). */
+pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, double q_tot,
+                         const double* n_vec, int n_krylov,
+                         double* q_n, double* force, double* nddot, double* energy);
+
+/* Vector-Jacobian product through the regular QEQ solution q*(R, chi, u)
+ * (training through the solve, Section "Validation and Performance"):
+ * adjoint solve [[C,1],[1^T,0]] [a; mu] = [gbar; 0] (same GMRES, same tol),
+ * then dL/dchi = -a, dL/du_i = -a_i q*_i, dL/dR = F[a + q*] - F[a] - F[q*].
+ * With gbar == NULL the upstream is the QEQ energy itself and the envelope
+ * theorem gives dE/dR = -F[q*], dE/dchi = q*, dE/du = q*^2/2 (no solve).
+ * q_star: device n FP64 (the solution of pq_qeq_solve for this system).
+ * Outputs (device FP64, each may be NULL): d_pos[n*3], d_chi[n], d_eta[n]. */
+pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const double* q_star,
+                     const double* gbar, double tol, int max_it,
+                     double* d_pos, double* d_chi, double* d_eta);
+
+/* ---- continuous-batching QEQ server -------------------------------------- */
+/* A server owns `slots` contexts, each with its own HIP stream, on one
+ * device, and a scheduler thread. Submitted requests wait in FIFO order and
+ * are admitted when a slot is free and their estimated device-memory
+ * footprint fits the remaining budget; admitted requests advance one GMRES
+ * iteration per scheduler turn, so their kernels overlap on the device and new
+ * requests join while others are still running. */
+typedef struct pq_server pq_server;
+
+typedef struct pq_server_cfg {
+    int32_t device;
+    int32_t slots;            /* concurrent requests on the device, 1..64       */
+    double hbm_budget_bytes;  /* admission limit on summed request footprints   */
+} pq_server_cfg;
+
+/* A request: all pointers are HOST memory, copied at submit. */
+typedef struct pq_request {
+    int64_t n;
+    const double* pos;        /* n x 3 */
+    const double* chi;        /* n     */
+    const double* eta;        /* n     */
+    const double* q0;         /* n or NULL */
+    double q_tot;
+    double tol;
+    int32_t max_it;
+    int32_t restart;
+    pq_params params;
+} pq_request;
+
+/* Result: `q` is a HOST buffer of n doubles provided by the caller of poll. */
+typedef struct pq_result {
+    double* q;
+    double energy;
+    pq_solve_info info;
+    int32_t status;           /* pq_status of the solve */
+    double t_submit_s, t_start_s, t_done_s;   /* server clock, seconds */
+} pq_result;
+
+pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg);
+/* Copies the request; returns PQ_ERR_TOO_LARGE if its footprint exceeds
+ * the whole budget. *ticket identifies it for poll. Thread safe. */
+pq_status pq_server_submit(pq_server* s, const pq_request* req, uint64_t* ticket);
+/* Waits up to timeout_us (< 0: forever) for the request; on completion copies
+ * the result out (res->q must hold n doubles) and forgets the ticket. Returns
+ * PQ_ERR_TIMEOUT if still pending. Thread safe. */
+pq_status pq_server_poll(pq_server* s, uint64_t ticket, pq_result* res, int64_t timeout_us);
+/* Stops the scheduler after the requests already submitted complete. */
+pq_status pq_server_destroy(pq_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMEQEQ_H */

@@ -1,0 +1,349 @@
+"""Python binding of libpmeqeq: periodic Coulomb (Ewald / smooth PME) and
+charge equilibration on AMD MI355X.
+
+Argument marshalling only: every step runs in the HIP library behind the C
+ABI declared in include/pmeqeq.h. Tensors are torch CUDA (HIP) tensors,
+float64, contiguous, on the context's device; PyTorch provides device memory
+and the current stream. If the library is not built, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
+
+PQ_OK = 0
+PQ_WARN_NOT_CONVERGED = 1
+STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_ERR_BOX",
+          -3: "PQ_ERR_CAPACITY", -4: "PQ_ERR_NOMEM", -5: "PQ_ERR_HIP", -6: "PQ_ERR_TOO_LARGE",
+          -7: "PQ_ERR_NAN", -8: "PQ_ERR_STATE", -9: "PQ_ERR_TIMEOUT"}
+METHOD_PME, METHOD_EWALD = 0, 1
+
+EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create", "pq_set_stream",
+           "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
+           "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
+           "pq_server_poll", "pq_server_destroy"]
+PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
+
+
+class PQError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("box", ctypes.c_double * 3), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("grid", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
+                ("kmax", ctypes.c_int32 * 3), ("method", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("lambda_", ctypes.c_double)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("pos", ctypes.c_void_p), ("chi", ctypes.c_void_p),
+                ("eta", ctypes.c_void_p), ("q0", ctypes.c_void_p), ("q_tot", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("params", Params)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_void_p), ("energy", ctypes.c_double), ("info", SolveInfo),
+                ("status", ctypes.c_int32), ("t_submit_s", ctypes.c_double), ("t_start_s", ctypes.c_double),
+                ("t_done_s", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Loads libpmeqeq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_21176_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    sig = {
+        "pq_abi_version": (i32, []),
+        "pq_coulomb_constant": (dbl, []),
+        "pq_last_error": (ctypes.c_char_p, []),
+        "pq_create": (i32, [ctypes.POINTER(vp), i32, vp]),
+        "pq_set_stream": (i32, [vp, vp]),
+        "pq_destroy": (i32, [vp]),
+        "pq_set_system": (i32, [vp, i64, vp, ctypes.POINTER(Params)]),
+        "pq_neighbor_pairs": (i32, [vp, i64, vp, ctypes.POINTER(i64)]),
+        "pq_coulomb": (i32, [vp, vp, vp, vp, vp]),
+        "pq_set_timing": (i32, [vp, i32]),
+        "pq_timings": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "pq_qeq_solve": (i32, [vp, vp, vp, dbl, dbl, i32, i32, vp, vp, vp, vp, ctypes.POINTER(SolveInfo)]),
+        "pq_shadow_step": (i32, [vp, vp, vp, dbl, vp, i32, vp, vp, vp, vp]),
+        "pq_qeq_vjp": (i32, [vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp]),
+        "pq_server_create": (i32, [ctypes.POINTER(vp), ctypes.POINTER(ServerCfg)]),
+        "pq_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+        "pq_server_poll": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(Result), i64]),
+        "pq_server_destroy": (i32, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def _check(code: int, allow_warn: bool = False) -> int:
+    if code == PQ_OK or (allow_warn and code == PQ_WARN_NOT_CONVERGED):
+        return code
+    raise PQError(code, load().pq_last_error().decode(errors="replace"))
+
+
+def coulomb_constant() -> float:
+    return float(load().pq_coulomb_constant())
+
+
+def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, method="pme") -> Params:
+    p = Params()
+    b = [float(x) for x in (box if hasattr(box, "__len__") else (box, box, box))]
+    p.box[:] = b
+    p.cutoff, p.skin, p.alpha = float(cutoff), float(skin), float(alpha)
+    if method == "pme":
+        g = grid if hasattr(grid, "__len__") else (grid, grid, grid)
+        p.grid[:] = [int(x) for x in g]
+        p.order = int(order)
+        p.method = METHOD_PME
+    elif method == "ewald":
+        k = kmax if hasattr(kmax, "__len__") else (kmax, kmax, kmax)
+        p.kmax[:] = [int(x) for x in k]
+        p.method = METHOD_EWALD
+    else:
+        raise ValueError(method)
+    p.flags = 0
+    return p
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class QeqResult:
+    q: torch.Tensor
+    force: torch.Tensor | None
+    energy: torch.Tensor | None
+    iterations: int
+    restarts: int
+    rel_residual: float
+    lam: float
+    status: int
+
+
+class Context:
+    """One system on one device; calls are ordered on torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _check(self.lib.pq_create(ctypes.byref(h), device, None))
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pq_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        _check(self.lib.pq_set_stream(self.h, ctypes.c_void_p(s)))
+
+    def _vec(self, t, n, name, cols=None):
+        if t is None:
+            return None
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        shape = (n,) if cols is None else (n, cols)
+        if n > 0 and tuple(t.shape) != shape:   # n == 0: no system; the library reports it
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+        if t.device != self.device:
+            raise ValueError(f"{name} is on {t.device}, context is on {self.device}")
+        return t.contiguous()
+
+    def set_system(self, pos: torch.Tensor, params: Params):
+        n = int(pos.shape[0])
+        pos = self._vec(pos, n, "pos", 3)
+        self._sync_stream()
+        _check(self.lib.pq_set_system(self.h, n, _ptr(pos), ctypes.byref(params)))
+        self.n, self.params = n, params
+
+    def neighbor_count(self) -> int:
+        cnt = ctypes.c_int64()
+        self._sync_stream()
+        _check(self.lib.pq_neighbor_pairs(self.h, 0, None, ctypes.byref(cnt)))
+        return int(cnt.value)
+
+    def neighbor_pairs(self) -> torch.Tensor:
+        cnt = ctypes.c_int64()
+        self._sync_stream()
+        _check(self.lib.pq_neighbor_pairs(self.h, 0, None, ctypes.byref(cnt)))
+        out = torch.empty((max(1, cnt.value), 5), dtype=torch.int32, device=self.device)
+        _check(self.lib.pq_neighbor_pairs(self.h, cnt.value, _ptr(out), ctypes.byref(cnt)))
+        return out[:cnt.value]
+
+    def set_timing(self, on: bool = True):
+        _check(self.lib.pq_set_timing(self.h, 1 if on else 0))
+
+    def timings(self):
+        """Per-phase device milliseconds summed since the last call, and the count."""
+        ms = (ctypes.c_double * 7)()
+        cnt = ctypes.c_int64()
+        _check(self.lib.pq_timings(self.h, ms, ctypes.byref(cnt)))
+        return dict(zip(PHASES, list(ms))), cnt.value
+
+    def coulomb(self, q, phi=True, force=True, energy=True):
+        q = self._vec(q, self.n, "q")
+        o_phi = torch.empty(self.n, dtype=torch.float64, device=self.device) if phi else None
+        o_f = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if force else None
+        o_e = torch.empty(4, dtype=torch.float64, device=self.device) if energy else None
+        self._sync_stream()
+        _check(self.lib.pq_coulomb(self.h, _ptr(q), _ptr(o_phi), _ptr(o_f), _ptr(o_e)))
+        return o_phi, o_f, o_e
+
+    def qeq_solve(self, chi, eta, q_tot=0.0, tol=1e-6, max_it=500, restart=50, q0=None, force=False,
+                  energy=True) -> QeqResult:
+        chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")
+        q0 = self._vec(q0, self.n, "q0")
+        q = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        f = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if force else None
+        e = torch.empty(1, dtype=torch.float64, device=self.device) if energy else None
+        info = SolveInfo()
+        self._sync_stream()
+        st = _check(self.lib.pq_qeq_solve(self.h, _ptr(chi), _ptr(eta), float(q_tot), float(tol), int(max_it),
+                                          int(restart), _ptr(q0), _ptr(q), _ptr(f), _ptr(e), ctypes.byref(info)),
+                    allow_warn=True)
+        return QeqResult(q, f, e, info.iterations, info.restarts, info.rel_residual, info.lambda_, st)
+
+    def shadow_step(self, chi, eta, n_vec, q_tot=0.0, n_krylov=8, force=True, nddot=True, energy=True):
+        chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")
+        n_vec = self._vec(n_vec, self.n, "n_vec")
+        dev, N = self.device, self.n
+        q = torch.empty(N, dtype=torch.float64, device=dev)
+        f = torch.empty((N, 3), dtype=torch.float64, device=dev) if force else None
+        x = torch.empty(N, dtype=torch.float64, device=dev) if nddot else None
+        e = torch.empty(2, dtype=torch.float64, device=dev) if energy else None
+        self._sync_stream()
+        _check(self.lib.pq_shadow_step(self.h, _ptr(chi), _ptr(eta), float(q_tot), _ptr(n_vec), int(n_krylov),
+                                       _ptr(q), _ptr(f), _ptr(x), _ptr(e)))
+        return q, f, x, e
+
+    def qeq_vjp(self, chi, eta, q_star, gbar=None, tol=1e-8, max_it=1000):
+        chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")
+        q_star = self._vec(q_star, self.n, "q_star")
+        gbar = self._vec(gbar, self.n, "gbar")
+        dev, N = self.device, self.n
+        dpos = torch.empty((N, 3), dtype=torch.float64, device=dev)
+        dchi = torch.empty(N, dtype=torch.float64, device=dev)
+        deta = torch.empty(N, dtype=torch.float64, device=dev)
+        self._sync_stream()
+        _check(self.lib.pq_qeq_vjp(self.h, _ptr(chi), _ptr(eta), _ptr(q_star), _ptr(gbar), float(tol),
+                                   int(max_it), _ptr(dpos), _ptr(dchi), _ptr(deta)), allow_warn=True)
+        return dpos, dchi, deta
+
+
+class QEQEnergy(torch.autograd.Function):
+    """E(R, chi, u) = min_q E(R, q) on sum q = q_tot, with the hand-written
+    adjoint (envelope theorem) as backward: dE/dR = -F[q*], dE/dchi = q*,
+    dE/du = q*^2/2. The context must hold the system at positions `pos`."""
+
+    @staticmethod
+    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8):
+        r = context.qeq_solve(chi.detach(), eta.detach(), q_tot=q_tot, tol=tol, energy=True)
+        ctx.context = context
+        ctx.save_for_backward(chi.detach(), eta.detach(), r.q)
+        return r.energy[0].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        chi, eta, q = ctx.saved_tensors
+        dpos, dchi, deta = ctx.context.qeq_vjp(chi, eta, q, None)
+        return g * dpos, g * dchi, g * deta, None, None, None
+
+
+class QEQCharges(torch.autograd.Function):
+    """q*(R, chi, u); backward solves the adjoint bordered system."""
+
+    @staticmethod
+    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8):
+        r = context.qeq_solve(chi.detach(), eta.detach(), q_tot=q_tot, tol=tol, energy=False)
+        ctx.context, ctx.tol = context, tol
+        ctx.save_for_backward(chi.detach(), eta.detach(), r.q)
+        return r.q.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        chi, eta, q = ctx.saved_tensors
+        dpos, dchi, deta = ctx.context.qeq_vjp(chi, eta, q, g.contiguous(), tol=ctx.tol)
+        return dpos, dchi, deta, None, None, None
+
+
+class Server:
+    """Continuous-batching QEQ server (host arrays in, host charges out)."""
+
+    def __init__(self, device=0, slots=8, hbm_budget_bytes=64e9):
+        self.lib = load()
+        cfg = ServerCfg(device, slots, float(hbm_budget_bytes))
+        h = ctypes.c_void_p()
+        _check(self.lib.pq_server_create(ctypes.byref(h), ctypes.byref(cfg)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, pos, chi, eta, params: Params, q0=None, q_tot=0.0, tol=1e-5, max_it=200, restart=50) -> int:
+        import numpy as np
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (pos, chi, eta)]
+        q0a = None if q0 is None else np.ascontiguousarray(q0, dtype=np.float64)
+        n = arrs[1].shape[0]
+        req = Request(n, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                      None if q0a is None else q0a.ctypes.data, float(q_tot), float(tol), int(max_it), int(restart),
+                      params)
+        t = ctypes.c_uint64()
+        _check(self.lib.pq_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = n
+        return t.value
+
+    def poll(self, ticket: int, timeout_us: int = -1):
+        import numpy as np
+        n = self._keep[ticket]
+        q = np.empty(n, dtype=np.float64)
+        res = Result()
+        res.q = q.ctypes.data
+        code = self.lib.pq_server_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(res), int(timeout_us))
+        if code == -9:
+            return None
+        _check(code)
+        del self._keep[ticket]
+        return dict(q=q, energy=res.energy, iterations=res.info.iterations, rel_residual=res.info.rel_residual,
+                    status=res.status, t_submit=res.t_submit_s, t_start=res.t_start_s, t_done=res.t_done_s)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self.lib.pq_server_destroy(self.h))
+            self.h = None

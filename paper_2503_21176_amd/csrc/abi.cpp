@@ -1,0 +1,268 @@
+// C ABI of the pmeqeq library: contexts, systems and Coulomb evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "pmeqeq.h"
+#include "pq_internal.h"
+#include "vec.h"
+
+namespace pq {
+
+thread_local std::string g_err;
+
+void set_error(const std::string& m) { g_err = m; }
+
+Ctx::~Ctx() {
+    if (pinned) (void)hipHostFree(pinned);
+    for (auto& v : ev_pending)
+        for (auto e : v) (void)hipEventDestroy(e);
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
+}
+
+static bool smooth235(int k) {
+    if (k <= 0) return false;
+    for (int p : {2, 3, 5})
+        while (k % p == 0) k /= p;
+    return k == 1;
+}
+
+static void validate(int64_t n, const pq_params* p) {
+    PQ_REQUIRE(p != nullptr, PQ_ERR_INVALID, "params is NULL");
+    PQ_REQUIRE(n >= 1 && n <= (int64_t)1 << 27, PQ_ERR_INVALID, "n must be in [1, 2^27]");
+    for (int d = 0; d < 3; ++d)
+        PQ_REQUIRE(std::isfinite(p->box[d]) && p->box[d] > 0.0, PQ_ERR_INVALID, "box edges must be finite and > 0");
+    PQ_REQUIRE(std::isfinite(p->cutoff) && p->cutoff > 0.0, PQ_ERR_INVALID, "cutoff must be > 0");
+    PQ_REQUIRE(std::isfinite(p->skin) && p->skin >= 0.0, PQ_ERR_INVALID, "skin must be >= 0");
+    PQ_REQUIRE(std::isfinite(p->alpha) && p->alpha > 0.0, PQ_ERR_INVALID, "alpha must be > 0");
+    PQ_REQUIRE(p->flags == 0, PQ_ERR_INVALID, "flags must be 0");
+    PQ_REQUIRE(p->method == PQ_METHOD_PME || p->method == PQ_METHOD_EWALD, PQ_ERR_INVALID, "unknown method");
+    if (p->method == PQ_METHOD_PME) {
+        PQ_REQUIRE(p->order >= 3 && p->order <= 8, PQ_ERR_INVALID, "order must be in 3..8");
+        for (int d = 0; d < 3; ++d) {
+            PQ_REQUIRE(p->grid[d] >= 2 * p->order && p->grid[d] <= 1024, PQ_ERR_BOX,
+                       "grid must satisfy 2*order <= K <= 1024");
+            PQ_REQUIRE(smooth235(p->grid[d]), PQ_ERR_BOX, "grid sizes must be 2^a 3^b 5^c");
+        }
+    } else {
+        for (int d = 0; d < 3; ++d)
+            PQ_REQUIRE(p->kmax[d] >= 0 && p->kmax[d] <= 64, PQ_ERR_INVALID, "kmax must be in 0..64");
+    }
+}
+
+void ensure_eval(Ctx& c) {
+    const size_t n = (size_t)c.n;
+    c.phi_r.ensure(n);
+    c.phi_k.ensure(n);
+    c.f_r.ensure(n);
+    c.f_k.ensure(n);
+    c.scal.ensure(64);
+    // reduction partials: sized once for every reduction the solvers issue
+    c.part.ensure((size_t)RED_BLOCKS * 520 + 4096);
+}
+
+// Phase events of one timed evaluation (null when timing is off).
+struct PhaseEvents {
+    Ctx& c;
+    hipStream_t s;
+    std::vector<hipEvent_t> ev;
+    PhaseEvents(Ctx& cc, hipStream_t ss) : c(cc), s(ss) {
+        if (!c.timing) return;
+        ev.resize(2 * PQ_NPHASE);
+        for (auto& e : ev) {
+            if (!c.ev_pool.empty()) {
+                e = c.ev_pool.back();
+                c.ev_pool.pop_back();
+            } else {
+                PQ_HIP(hipEventCreate(&e));
+            }
+        }
+    }
+    void begin(int ph) {
+        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph], s));
+    }
+    void end(int ph) {
+        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph + 1], s));
+    }
+    void commit() {
+        if (!ev.empty()) c.ev_pending.push_back(std::move(ev));
+    }
+};
+
+void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s) {
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    ensure_eval(c);
+    const bool fo = force != nullptr;
+    PhaseEvents E(c, s);
+    E.begin(PQ_PHASE_TOTAL);
+    E.begin(PQ_PHASE_STAGE);
+    stage_charges(c, q, s);
+    sum_vector(c, q, c.n, c.scal.p + 0, s);
+    E.end(PQ_PHASE_STAGE);
+    E.begin(PQ_PHASE_PAIR);
+    pair_sum(c, fo, c.phi_r.p, c.f_r.p, s);
+    E.end(PQ_PHASE_PAIR);
+    if (c.prm.method == PQ_METHOD_PME) {
+        pme_eval(c, q, fo, c.phi_k.p, c.f_k.p, E.ev.empty() ? nullptr : E.ev.data(), s);
+    } else {
+        E.begin(PQ_PHASE_SPREAD);
+        E.end(PQ_PHASE_SPREAD);
+        E.begin(PQ_PHASE_FFT);
+        E.end(PQ_PHASE_FFT);
+        E.begin(PQ_PHASE_GATHER);
+        ewald_eval(c, q, fo, c.phi_k.p, c.f_k.p, s);
+        E.end(PQ_PHASE_GATHER);
+    }
+    E.begin(PQ_PHASE_COMBINE);
+    combine(c, q, c.scal.p + 0, phi, force, energy, s);
+    E.end(PQ_PHASE_COMBINE);
+    E.end(PQ_PHASE_TOTAL);
+    E.commit();
+}
+
+}  // namespace pq
+
+using namespace pq;
+
+#define PQ_API_BEGIN try {
+#define PQ_API_END                              \
+    }                                           \
+    catch (const pq::Error& e) {                \
+        pq::set_error(e.what());                \
+        return e.code;                          \
+    }                                           \
+    catch (const std::exception& e) {           \
+        pq::set_error(e.what());                \
+        return PQ_ERR_INVALID;                  \
+    }                                           \
+    catch (...) {                               \
+        pq::set_error("unknown error");         \
+        return PQ_ERR_INVALID;                  \
+    }
+
+extern "C" {
+
+int pq_abi_version(void) { return PQ_ABI_VERSION; }
+
+double pq_coulomb_constant(void) { return KE; }
+
+const char* pq_last_error(void) { return pq::g_err.c_str(); }
+
+pq_status pq_create(pq_ctx** out, int device, void* stream) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(out != nullptr, PQ_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    PQ_HIP(hipGetDeviceCount(&ndev));
+    PQ_REQUIRE(device >= 0 && device < ndev, PQ_ERR_INVALID, "no such HIP device");
+    PQ_HIP(hipSetDevice(device));
+    Ctx* c = new Ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        throw Error(PQ_ERR_NOMEM, "pinned host allocation failed");
+    }
+    *out = reinterpret_cast<pq_ctx*>(c);
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_set_stream(pq_ctx* ctx, void* stream) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
+    reinterpret_cast<Ctx*>(ctx)->stream = static_cast<hipStream_t>(stream);
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_destroy(pq_ctx* ctx) {
+    PQ_API_BEGIN
+    if (!ctx) return PQ_OK;
+    Ctx* c = reinterpret_cast<Ctx*>(ctx);
+    PQ_HIP(hipSetDevice(c->device));
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && pos != nullptr, PQ_ERR_INVALID, "ctx or pos is NULL");
+    validate(n, prm);
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_HIP(hipSetDevice(c.device));
+    c.have_system = false;
+    c.n = n;
+    c.prm = *prm;
+    nbr_build(c, pos);
+    if (prm->method == PQ_METHOD_PME)
+        pme_setup(c);
+    else
+        ewald_setup(c);
+    ensure_eval(c);
+    c.have_system = true;
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && n_pairs != nullptr, PQ_ERR_INVALID, "ctx or n_pairs is NULL");
+    PQ_REQUIRE(cap >= 0, PQ_ERR_INVALID, "cap must be >= 0");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    const int64_t tot = nbr_export_pairs(c, pairs ? cap : 0, pairs);
+    *n_pairs = tot;
+    if (pairs && tot > cap) {
+        set_error("pair buffer too small: " + std::to_string(tot) + " pairs");
+        return PQ_ERR_CAPACITY;
+    }
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_set_timing(pq_ctx* ctx, int on) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
+    reinterpret_cast<Ctx*>(ctx)->timing = on != 0;
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && ms != nullptr && count != nullptr, PQ_ERR_INVALID, "NULL argument");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_HIP(hipSetDevice(c.device));
+    for (int k = 0; k < PQ_NPHASE; ++k) ms[k] = 0.0;
+    *count = (int64_t)c.ev_pending.size();
+    for (auto& v : c.ev_pending) {
+        PQ_HIP(hipEventSynchronize(v[2 * PQ_PHASE_TOTAL + 1]));
+        for (int k = 0; k < PQ_NPHASE; ++k) {
+            float t = 0.0f;
+            PQ_HIP(hipEventElapsedTime(&t, v[2 * k], v[2 * k + 1]));
+            ms[k] += t;
+        }
+        for (auto e : v) c.ev_pool.push_back(e);
+    }
+    c.ev_pending.clear();
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_HIP(hipSetDevice(c.device));
+    coulomb_eval(c, q, phi, force, energy, c.stream);
+    return PQ_OK;
+    PQ_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Device helpers shared by the kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pq {
+
+// Canonical wrap into [0, L): w = x - L*floor(x*(1/L)), three separately
+// rounded FP64 operations (no contraction), so the host-side definition of
+// the neighbour predicate can be reproduced bit for bit.
+__device__ __forceinline__ double canon_wrap(double x, double L, double invL) {
+#pragma clang fp contract(off)
+    double t = x * invL;
+    double f = floor(t);
+    double m = L * f;
+    return x - m;
+}
+
+// Canonical squared distance between w_i and the image n of w_j:
+// d = (w_j - w_i) + n*L per axis, d.d = (dx*dx + dy*dy) + dz*dz, no contraction.
+__device__ __forceinline__ double canon_d2(const double* __restrict__ wi, const double* __restrict__ wj,
+                                           int n0, int n1, int n2, double L0, double L1, double L2) {
+#pragma clang fp contract(off)
+    double dx = (wj[0] - wi[0]) + (double)n0 * L0;
+    double dy = (wj[1] - wi[1]) + (double)n1 * L1;
+    double dz = (wj[2] - wi[2]) + (double)n2 * L2;
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+// Image vector packed as three signed 10-bit fields.
+__host__ __device__ __forceinline__ int pack_img(int n0, int n1, int n2) {
+    return (n0 & 1023) | ((n1 & 1023) << 10) | ((n2 & 1023) << 20);
+}
+__host__ __device__ __forceinline__ void unpack_img(int p, int& n0, int& n1, int& n2) {
+    n0 = (p << 22) >> 22;
+    n1 = (p << 12) >> 22;
+    n2 = (p << 2) >> 22;
+}
+__host__ __device__ __forceinline__ bool lex_positive(int n0, int n1, int n2) {
+    return n0 > 0 || (n0 == 0 && (n1 > 0 || (n1 == 0 && n2 > 0)));
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+// FP64 sum over the 64 lanes of a wavefront (result in every lane).
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// FP64 sum over a block of NT threads; returns the total in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* lds /* NT/64 */) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) t += lds[k];
+    __syncthreads();
+    return t;
+}
+
+}  // namespace pq

@@ -1,0 +1,183 @@
+// Direct reciprocal Ewald sum (the paper's eq. ewald_rec and its derivatives),
+// computed blockwise without materialising the N x k phase matrix, as the
+// paper's blockwise variant does.
+//
+// Half space of k = 2 pi n / L (n != 0, |n_d| <= kmax_d, first nonzero
+// component positive); the other half follows from S(-k) = conj S(k).
+//   S(k)  = sum_j q_j exp(i k.r_j)                       (FP64 sums of FP32 phases)
+//   E_rec = sum_half c_k |S(k)|^2,  c_k = (4 pi/V) exp(-k^2/4a^2)/k^2
+//   phi_i = 2 sum_half c_k Re(exp(-i k.r_i) S(k))
+//   F_i   = 2 q_i sum_half c_k k Im(conj(S(k)) exp(i k.r_i))
+// Phases: k.r = 2 pi (n . s), s = r/L; the fractional part of n . s is taken
+// in FP64, then sin/cos of 2 pi f in FP32 (phase error ~2e-7 rad).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "dev.h"
+#include "pq_internal.h"
+
+namespace pq {
+
+constexpr int EW_TILE = 256;
+
+__device__ __forceinline__ void phase(const int4 nk, double s0, double s1, double s2, float& sn, float& cs) {
+    double t = (double)nk.x * s0 + (double)nk.y * s1 + (double)nk.z * s2;
+    t -= rint(t);
+    sincospif(2.0f * (float)t, &sn, &cs);
+}
+
+// Structure factors: one thread per k vector, atoms staged through LDS.
+__global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __restrict__ kn,
+                                                 const double* __restrict__ kc, const double* __restrict__ w64,
+                                                 double inv0, double inv1, double inv2, const double* __restrict__ q,
+                                                 double2* __restrict__ sfac, double* __restrict__ epart) {
+    __shared__ double s_s[EW_TILE * 3];
+    __shared__ double s_q[EW_TILE];
+    __shared__ double red[EW_TILE / 64];
+    const int kidx = blockIdx.x * EW_TILE + threadIdx.x;
+    const bool valid = kidx < nk;
+    const int4 nv = valid ? kn[kidx] : make_int4(0, 0, 0, 0);
+    double re = 0.0, im = 0.0;
+    for (int j0 = 0; j0 < n; j0 += EW_TILE) {
+        const int j = j0 + threadIdx.x;
+        if (j < n) {
+            s_s[3 * threadIdx.x + 0] = w64[3 * (size_t)j + 0] * inv0;
+            s_s[3 * threadIdx.x + 1] = w64[3 * (size_t)j + 1] * inv1;
+            s_s[3 * threadIdx.x + 2] = w64[3 * (size_t)j + 2] * inv2;
+            s_q[threadIdx.x] = q[j];
+        }
+        __syncthreads();
+        const int m = min(EW_TILE, n - j0);
+        if (valid)
+            for (int t = 0; t < m; ++t) {
+                float sn, cs;
+                phase(nv, s_s[3 * t], s_s[3 * t + 1], s_s[3 * t + 2], sn, cs);
+                re += s_q[t] * (double)cs;
+                im += s_q[t] * (double)sn;
+            }
+        __syncthreads();
+    }
+    double e = 0.0;
+    if (valid) {
+        sfac[kidx] = make_double2(re, im);
+        e = kc[kidx] * (re * re + im * im);
+    }
+    e = block_sum<EW_TILE>(e, red);
+    if (threadIdx.x == 0) epart[blockIdx.x] = e;
+}
+
+// Potentials and forces: one thread per atom, k vectors staged through LDS.
+template <bool FORCE>
+__global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* __restrict__ kn,
+                                                    const double* __restrict__ kc,
+                                                    const double2* __restrict__ sfac, const double* __restrict__ w64,
+                                                    double inv0, double inv1, double inv2,
+                                                    const double* __restrict__ q, float* __restrict__ phi_out,
+                                                    float4* __restrict__ f_out) {
+    __shared__ int4 s_n[EW_TILE];
+    __shared__ double s_c[EW_TILE];
+    __shared__ double2 s_S[EW_TILE];
+    const int i = blockIdx.x * EW_TILE + threadIdx.x;
+    const bool valid = i < n;
+    double s0 = 0, s1 = 0, s2 = 0;
+    if (valid) {
+        s0 = w64[3 * (size_t)i] * inv0;
+        s1 = w64[3 * (size_t)i + 1] * inv1;
+        s2 = w64[3 * (size_t)i + 2] * inv2;
+    }
+    double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int k0 = 0; k0 < nk; k0 += EW_TILE) {
+        const int k = k0 + threadIdx.x;
+        if (k < nk) {
+            s_n[threadIdx.x] = kn[k];
+            s_c[threadIdx.x] = kc[k];
+            s_S[threadIdx.x] = sfac[k];
+        }
+        __syncthreads();
+        const int m = min(EW_TILE, nk - k0);
+        if (valid)
+            for (int t = 0; t < m; ++t) {
+                float sn, cs;
+                const int4 nv = s_n[t];
+                phase(nv, s0, s1, s2, sn, cs);
+                const double2 S = s_S[t];
+                const double c = s_c[t];
+                phi += c * ((double)cs * S.x + (double)sn * S.y);
+                if (FORCE) {
+                    const double im = c * (S.x * (double)sn - S.y * (double)cs);
+                    g0 += im * nv.x;
+                    g1 += im * nv.y;
+                    g2 += im * nv.z;
+                }
+            }
+        __syncthreads();
+    }
+    if (valid) {
+        phi_out[i] = (float)(2.0 * phi);
+        if (FORCE) {
+            const double qi = q[i];
+            const double f = 2.0 * qi * 2.0 * PI;
+            f_out[i] = make_float4((float)(f * g0 * inv0), (float)(f * g1 * inv1), (float)(f * g2 * inv2), 0.0f);
+        }
+    }
+}
+
+__global__ void k_sum_part_e(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    v = block_sum<256>(v, red);
+    if (threadIdx.x == 0) *out = v;
+}
+
+void ewald_setup(Ctx& c) {
+    const int* km = c.prm.kmax;
+    const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
+    const double a = c.prm.alpha;
+    std::vector<int4> nv;
+    std::vector<double> cv;
+    for (int x = 0; x <= km[0]; ++x)
+        for (int y = -km[1]; y <= km[1]; ++y)
+            for (int z = -km[2]; z <= km[2]; ++z) {
+                if (!(x > 0 || (x == 0 && (y > 0 || (y == 0 && z > 0))))) continue;
+                const double kx = 2.0 * PI * x / c.prm.box[0], ky = 2.0 * PI * y / c.prm.box[1],
+                             kz = 2.0 * PI * z / c.prm.box[2];
+                const double k2 = kx * kx + ky * ky + kz * kz;
+                nv.push_back(make_int4(x, y, z, 0));
+                cv.push_back(4.0 * PI / V * std::exp(-k2 / (4.0 * a * a)) / k2);
+            }
+    c.nk = (int)nv.size();
+    c.kn.ensure(std::max(1, c.nk));
+    c.kc.ensure(std::max(1, c.nk));
+    c.sfac.ensure(std::max(1, c.nk));
+    if (c.nk) {
+        PQ_HIP(hipMemcpy(c.kn.p, nv.data(), nv.size() * sizeof(int4), hipMemcpyHostToDevice));
+        PQ_HIP(hipMemcpy(c.kc.p, cv.data(), cv.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+}
+
+// phi, f (original order, without KE); E_rec (without KE) into c.scal[1]
+void ewald_eval(Ctx& c, const double* q, bool force, float* phi, float4* f, hipStream_t s) {
+    const int n = (int)c.n;
+    const double i0 = 1.0 / c.prm.box[0], i1 = 1.0 / c.prm.box[1], i2 = 1.0 / c.prm.box[2];
+    if (c.nk == 0) {
+        PQ_HIP(hipMemsetAsync(phi, 0, sizeof(float) * n, s));
+        if (force) PQ_HIP(hipMemsetAsync(f, 0, sizeof(float4) * n, s));
+        PQ_HIP(hipMemsetAsync(c.scal.p + 1, 0, sizeof(double), s));
+        return;
+    }
+    const int nb = cdiv(c.nk, EW_TILE);
+    c.part.ensure(nb + 16);
+    PQ_LAUNCH(k_sfac, nb, EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.w64.p, i0, i1, i2, q, c.sfac.p, c.part.p);
+    PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.part.p, nb, c.scal.p + 1);
+    if (force)
+        PQ_LAUNCH(k_kgather<true>, cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
+                  i1, i2, q, phi, f);
+    else
+        PQ_LAUNCH(k_kgather<false>, cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
+                  i1, i2, q, phi, f);
+}
+
+}  // namespace pq

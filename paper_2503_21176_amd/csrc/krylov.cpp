@@ -1,0 +1,322 @@
+// Charge equilibration on the device: restarted GMRES on the bordered QEQ
+// system (eq. linear_qeq, matrix-free through the Cv identity), the shadow
+// step (eqs. diag_linear_qeq and Jnddot) and vector-Jacobian products through
+// the QEQ solve. Krylov vectors, inner products and orthogonalisation are
+// FP64 on the device; each operator product is one FP32-bulk Coulomb
+// potential evaluation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <functional>
+#include <string>
+
+#include "pmeqeq.h"
+#include "pq_internal.h"
+#include "vec.h"
+
+namespace pq {
+
+void set_error(const std::string& m);
+
+namespace {
+
+size_t round_ld(int64_t n) { return (size_t)((n + 63) / 64 * 64); }
+
+// Work vectors of the solvers (each ld doubles).
+enum { W_B = 0, W_X, W_R, W_W, W_T, W_PHI, W_PHI2, W_D, W_N };
+
+struct Work {
+    Ctx& c;
+    size_t ld;
+    int m;
+    double* V;
+    double* st;
+    double* w(int k) { return c.kw.p + (size_t)k * ld; }
+    double* sc(int k) { return c.scal.p + 16 + k; }   // device scalars 16..63
+    Work(Ctx& cc, int mm) : c(cc), ld(round_ld(cc.n + 1)), m(mm) {
+        c.kw.ensure(ld * W_N);
+        c.kv.ensure(ld * (size_t)(m + 1));
+        c.kh.ensure(gs_size(m) + 8);
+        c.scal.ensure(64);
+        V = c.kv.p;
+        st = c.kh.p;
+    }
+};
+
+using OpFn = std::function<void(const double* x, double* y)>;
+
+struct GmresOut {
+    int products = 0;
+    int restarts = 0;
+    double relres = 0.0;
+    bool converged = false;
+};
+
+double read_scalar(Ctx& c, const double* dev, hipStream_t s) {
+    PQ_HIP(hipMemcpyAsync(c.pinned, dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    return c.pinned[0];
+}
+
+// GMRES(m) for A x = b with vectors of length nv, x in/out (x_zero: x = 0 on
+// entry). fixed: exactly m products from x = 0, no host synchronisation.
+GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, bool x_zero, double tol, int max_it,
+               bool fixed) {
+    Ctx& c = W.c;
+    hipStream_t s = c.stream;
+    const int m = W.m;
+    const size_t ld = W.ld;
+    double* r = W.w(W_R);
+    double* w = W.w(W_W);
+    GmresOut out;
+    double bnorm = 1.0;
+    if (!fixed) {
+        dot_vector(c, b, b, nv, W.sc(0), s);
+        bnorm = std::sqrt(read_scalar(c, W.sc(0), s));
+        if (bnorm == 0.0) {
+            axpby(nv, 0.0, b, 0.0, nullptr, x, s);
+            out.converged = true;
+            return out;
+        }
+    }
+    if (x_zero) {
+        axpby(nv, 0.0, b, 0.0, nullptr, x, s);
+        axpby(nv, 1.0, b, 0.0, nullptr, r, s);
+    } else {
+        op(x, w);
+        out.products++;
+        axpby(nv, 1.0, b, -1.0, w, r, s);
+    }
+    dot_vector(c, r, r, nv, W.sc(1), s);
+    if (!fixed) {
+        out.relres = std::sqrt(read_scalar(c, W.sc(1), s)) / bnorm;
+        if (out.relres <= tol) {
+            out.converged = true;
+            return out;
+        }
+    }
+    for (;;) {
+        gmres_start(W.st, m, W.sc(1), s);
+        normalize(nv, r, W.sc(1), nullptr, W.V, s);
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            op(W.V + (size_t)j * ld, w);
+            out.products++;
+            orthogonalize(c, nv, W.V, ld, j + 1, w, W.st + (size_t)j * (m + 1), W.st + gs_t(m), s);
+            dot_vector(c, w, w, nv, W.sc(2), s);
+            normalize(nv, w, W.sc(2), W.st + (size_t)j * (m + 1) + j + 1, W.V + (size_t)(j + 1) * ld, s);
+            givens(W.st, m, j, W.sc(3), s);
+            jdone = j + 1;
+            if (!fixed) {
+                const double est = read_scalar(c, W.sc(3), s) / bnorm;
+                if (est <= tol || out.products >= max_it) break;
+            }
+        }
+        backsolve(W.st, m, jdone, s);
+        xupdate(nv, W.V, ld, jdone, W.st + gs_y(m), x, s);
+        if (fixed) return out;
+        // true residual
+        op(x, w);
+        out.products++;
+        axpby(nv, 1.0, b, -1.0, w, r, s);
+        dot_vector(c, r, r, nv, W.sc(1), s);
+        out.relres = std::sqrt(read_scalar(c, W.sc(1), s)) / bnorm;
+        if (out.relres <= tol) {
+            out.converged = true;
+            return out;
+        }
+        if (out.products >= max_it) return out;
+        out.restarts++;
+    }
+}
+
+void check_finite_host(double v, const char* what) {
+    PQ_REQUIRE(std::isfinite(v), PQ_ERR_INVALID, std::string(what) + " must be finite");
+}
+
+// bordered QEQ product with right Jacobi preconditioning diag(u, 1):
+//   out = [y_q + phi[y_q/u] + y_l ; sum y_q/u]
+OpFn bordered_op(Work& W, const double* eta) {
+    return [&W, eta](const double* y, double* out) {
+        Ctx& c = W.c;
+        hipStream_t s = c.stream;
+        const int64_t n = c.n;
+        double* t = W.w(W_T);
+        double* phi = W.w(W_PHI2);
+        vdiv(n, y, eta, t, s);
+        coulomb_eval(c, t, phi, nullptr, nullptr, s);
+        reduce(c, t, nullptr, n, 0, 1.0, W.sc(4), s);
+        bordered_out(n, y, phi, W.sc(4), out, s);
+    };
+}
+
+// bordered solve for right-hand side [rhs_q; rhs_l]; the solution z = P^-1 x is
+// left as q = x_q/u in qout and lambda in *lam_dev.
+GmresOut bordered_solve(Work& W, const double* eta, const double* rhs_q, double rhs_l, bool negate_rhs,
+                        const double* q0, double tol, int max_it, double* qout) {
+    Ctx& c = W.c;
+    hipStream_t s = c.stream;
+    const int64_t n = c.n;
+    double* b = W.w(W_B);
+    double* x = W.w(W_X);
+    axpby(n, negate_rhs ? -1.0 : 1.0, rhs_q, 0.0, nullptr, b, s);
+    set_scalar(b + n, rhs_l, s);
+    bool xz = true;
+    if (q0) {
+        vmul(n, q0, eta, 1.0, x, s);
+        set_scalar(x + n, 0.0, s);
+        xz = false;
+    }
+    OpFn op = bordered_op(W, eta);
+    GmresOut o = gmres(W, op, n + 1, b, x, xz, tol, max_it, false);
+    vdiv(n, x, eta, qout, s);
+    return o;
+}
+
+}  // namespace
+}  // namespace pq
+
+using namespace pq;
+
+#define PQ_API_BEGIN try {
+#define PQ_API_END                    \
+    }                                 \
+    catch (const pq::Error& e) {      \
+        pq::set_error(e.what());      \
+        return e.code;                \
+    }                                 \
+    catch (const std::exception& e) { \
+        pq::set_error(e.what());      \
+        return PQ_ERR_INVALID;        \
+    }                                 \
+    catch (...) {                     \
+        pq::set_error("unknown error"); \
+        return PQ_ERR_INVALID;        \
+    }
+
+extern "C" {
+
+pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot, double tol, int max_it,
+                       int restart, const double* q0, double* q, double* force, double* energy, pq_solve_info* info) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx && chi && eta && q, PQ_ERR_INVALID, "ctx, chi, eta and q must not be NULL");
+    PQ_REQUIRE(tol > 0.0 && max_it >= 1 && restart >= 1 && restart <= 512, PQ_ERR_INVALID,
+               "need tol > 0, max_it >= 1, 1 <= restart <= 512");
+    check_finite_host(q_tot, "q_tot");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    hipStream_t s = c.stream;
+    Work W(c, restart);
+    GmresOut o = bordered_solve(W, eta, chi, q_tot, true, q0, tol, max_it, q);
+    double lam = read_scalar(c, W.w(W_X) + c.n, s);
+    if (force || energy) {
+        double* phi = W.w(W_PHI);
+        coulomb_eval(c, q, phi, force, nullptr, s);
+        if (energy) qeq_energy(c, c.n, q, chi, eta, q, phi, energy, s);
+    }
+    if (info) {
+        info->iterations = o.products;
+        info->restarts = o.restarts;
+        info->rel_residual = o.relres;
+        info->lambda = lam;
+    }
+    PQ_HIP(hipStreamSynchronize(s));
+    return o.converged ? PQ_OK : PQ_WARN_NOT_CONVERGED;
+    PQ_API_END
+}
+
+pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, double q_tot, const double* n_vec,
+                         int n_krylov, double* q_n, double* force, double* nddot, double* energy) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx && chi && eta && n_vec && q_n, PQ_ERR_INVALID, "ctx, chi, eta, n_vec and q_n must not be NULL");
+    PQ_REQUIRE(n_krylov >= 1 && n_krylov <= 512, PQ_ERR_INVALID, "n_krylov must be in 1..512");
+    check_finite_host(q_tot, "q_tot");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    hipStream_t s = c.stream;
+    const int64_t n = c.n;
+    Work W(c, n_krylov);
+    c.kf.ensure((size_t)n * 3);
+    // v = A n ; q[n] and lambda in closed form
+    double* phin = W.w(W_PHI);
+    coulomb_eval(c, n_vec, phin, nullptr, nullptr, s);
+    shadow_sums(c, n, chi, phin, eta, W.sc(5), s);
+    shadow_q(n, chi, phin, eta, W.sc(5), q_tot, q_n, W.sc(7), s);
+    // shadow force F[q] - F[q - n]
+    if (force) {
+        double* d = W.w(W_D);
+        coulomb_eval(c, q_n, nullptr, force, nullptr, s);
+        axpby(n, 1.0, q_n, -1.0, n_vec, d, s);
+        coulomb_eval(c, d, nullptr, c.kf.p, nullptr, s);
+        axpby(3 * n, 1.0, force, -1.0, c.kf.p, force, s);
+    }
+    if (energy) {
+        double* a = W.w(W_D);
+        axpby(n, 2.0, q_n, -1.0, n_vec, a, s);
+        qeq_energy(c, n, q_n, chi, eta, a, phin, energy, s);
+        copy_scalar(W.sc(7), energy + 1, s);
+    }
+    if (nddot) {
+        // J x = -x - P D^-1 A x,  P y = y - D^-1 1 (1^T y) / (1^T D^-1 1)
+        OpFn op = [&W, eta](const double* x, double* out) {
+            Ctx& cc = W.c;
+            hipStream_t ss = cc.stream;
+            const int64_t nn = cc.n;
+            double* phi = W.w(W_PHI2);
+            double* t = W.w(W_T);
+            coulomb_eval(cc, x, phi, nullptr, nullptr, ss);
+            vdiv(nn, phi, eta, t, ss);
+            shadow_sums(cc, nn, nullptr, phi, eta, W.sc(8), ss);
+            jac_out(nn, x, t, eta, W.sc(8), out, ss);
+        };
+        double* b = W.w(W_B);
+        axpby(n, 1.0, n_vec, -1.0, q_n, b, s);   // -(q[n] - n)
+        gmres(W, op, n, b, nddot, true, 0.0, n_krylov, true);
+    }
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const double* q_star, const double* gbar,
+                     double tol, int max_it, double* d_pos, double* d_chi, double* d_eta) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx && chi && eta && q_star, PQ_ERR_INVALID, "ctx, chi, eta and q_star must not be NULL");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    hipStream_t s = c.stream;
+    const int64_t n = c.n;
+    if (!gbar) {
+        // envelope theorem: dE/dR = -F[q*], dE/dchi = q*, dE/du = q*^2 / 2
+        if (d_pos) {
+            coulomb_eval(c, q_star, nullptr, d_pos, nullptr, s);
+            axpby(3 * n, -1.0, d_pos, 0.0, nullptr, d_pos, s);
+        }
+        if (d_chi) axpby(n, 1.0, q_star, 0.0, nullptr, d_chi, s);
+        if (d_eta) vmul(n, q_star, q_star, 0.5, d_eta, s);
+        return PQ_OK;
+    }
+    PQ_REQUIRE(tol > 0.0 && max_it >= 1, PQ_ERR_INVALID, "need tol > 0 and max_it >= 1");
+    Work W(c, 50);
+    c.kf.ensure((size_t)n * 3);
+    double* a = W.w(W_D);
+    GmresOut o = bordered_solve(W, eta, gbar, 0.0, false, nullptr, tol, max_it, a);
+    if (d_chi) axpby(n, -1.0, a, 0.0, nullptr, d_chi, s);
+    if (d_eta) vmul(n, a, q_star, -1.0, d_eta, s);
+    if (d_pos) {
+        double* aq = W.w(W_PHI);
+        axpby(n, 1.0, a, 1.0, q_star, aq, s);
+        coulomb_eval(c, aq, nullptr, d_pos, nullptr, s);
+        coulomb_eval(c, a, nullptr, c.kf.p, nullptr, s);
+        axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
+        coulomb_eval(c, q_star, nullptr, c.kf.p, nullptr, s);
+        axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
+    }
+    PQ_HIP(hipStreamSynchronize(s));
+    return o.converged ? PQ_OK : PQ_WARN_NOT_CONVERGED;
+    PQ_API_END
+}
+
+}  // extern "C"

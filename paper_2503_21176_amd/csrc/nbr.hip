@@ -1,0 +1,364 @@
+// Cell (column) sort, cluster build and cluster-pair neighbour list.
+//
+// Section "Cell based Neighbor List" of the paper bins atoms into cells of
+// about the cutoff size and searches neighbouring cells under periodic
+// boundaries. Here the cells are x-y columns sized so that 8 consecutive
+// z-sorted atoms of a column form a compact cluster; the list holds pairs of
+// clusters (i-cluster, j-cluster, image vector n) whose bounding boxes are
+// closer than the list radius, which is what the wave64 pair kernel consumes
+// (8 i-atoms x 8 j-atoms per wavefront step). Every periodic image is
+// enumerated, so boxes shorter than twice the cutoff are handled.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "dev.h"
+#include "pq_internal.h"
+
+namespace pq {
+
+__global__ void k_fill_int(int* __restrict__ a, int n, int v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// Wrap positions into the box, pick each atom's column, count per column.
+__global__ void k_wrap_count(int n, const double* __restrict__ pos, Geom g, double* __restrict__ w64,
+                             int* __restrict__ col_of, int* __restrict__ col_cnt, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double w[3];
+    bool ok = true;
+    for (int d = 0; d < 3; ++d) {
+        double x = pos[3 * (size_t)i + d];
+        ok = ok && isfinite(x);
+        w[d] = canon_wrap(x, g.L[d], g.invL[d]);
+        w64[3 * (size_t)i + d] = w[d];
+    }
+    if (!ok) {
+        atomicOr(flag, 1);
+        w[0] = w[1] = w[2] = 0.0;
+    }
+    int cx = (int)floor(w[0] * ((double)g.ncx * g.invL[0]));
+    int cy = (int)floor(w[1] * ((double)g.ncy * g.invL[1]));
+    cx = min(max(cx, 0), g.ncx - 1);
+    cy = min(max(cy, 0), g.ncy - 1);
+    int c = cx + g.ncx * cy;
+    col_of[i] = c;
+    atomicAdd(&col_cnt[c], 1);
+}
+
+// Exclusive scan of a small integer array by one workgroup (OP 1: scan of
+// ceil(x/8)). out[n] receives the total.
+template <int OP>
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ in, int* __restrict__ out, int n) {
+    __shared__ int buf[1024];
+    __shared__ int carry;
+    const int t = threadIdx.x;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        int i = base + t;
+        int v = 0;
+        if (i < n) v = (OP == 1) ? (in[i] + CL - 1) / CL : in[i];
+        buf[t] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int x = (t >= off) ? buf[t - off] : 0;
+            __syncthreads();
+            buf[t] += x;
+            __syncthreads();
+        }
+        if (i < n) out[i] = carry + buf[t] - v;
+        __syncthreads();
+        if (t == 1023) carry += buf[1023];
+        __syncthreads();
+    }
+    if (t == 0) out[n] = carry;
+}
+
+__global__ void k_bin(int n, const int* __restrict__ col_of, const int* __restrict__ col_start,
+                      int* __restrict__ col_fill, int* __restrict__ tmp) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = col_of[i];
+    tmp[col_start[c] + atomicAdd(&col_fill[c], 1)] = i;
+}
+
+// Rank of each atom inside its column by (z, index): a deterministic sort.
+__global__ void k_rank(int n, const int* __restrict__ col_of, const int* __restrict__ col_start,
+                       const int* __restrict__ col_cl, const int* __restrict__ tmp,
+                       const double* __restrict__ w64, int* __restrict__ orig) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = col_of[i];
+    double zi = w64[3 * (size_t)i + 2];
+    int r = 0;
+    for (int k = col_start[c]; k < col_start[c + 1]; ++k) {
+        int j = tmp[k];
+        double zj = w64[3 * (size_t)j + 2];
+        r += (zj < zi) || (zj == zi && j < i);
+    }
+    orig[(size_t)col_cl[c] * CL + r] = i;
+}
+
+__global__ void k_cluster_col(int ncol, const int* __restrict__ col_cl, int* __restrict__ cl_col) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncol) return;
+    for (int k = col_cl[c]; k < col_cl[c + 1]; ++k) cl_col[k] = c;
+}
+
+// Bounding box, reference point and FP32 offsets of each cluster.
+__global__ void k_cluster(int ncl, const int* __restrict__ orig, const double* __restrict__ w64,
+                          double* __restrict__ ref, double* __restrict__ lo, double* __restrict__ hi,
+                          float4* __restrict__ xyzq) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncl) return;
+    double l[3] = {1e300, 1e300, 1e300}, h[3] = {-1e300, -1e300, -1e300};
+    for (int a = 0; a < CL; ++a) {
+        int i = orig[(size_t)c * CL + a];
+        if (i < 0) continue;
+        for (int d = 0; d < 3; ++d) {
+            double w = w64[3 * (size_t)i + d];
+            l[d] = fmin(l[d], w);
+            h[d] = fmax(h[d], w);
+        }
+    }
+    double r[3];
+    for (int d = 0; d < 3; ++d) {
+        r[d] = 0.5 * (l[d] + h[d]);
+        ref[3 * (size_t)c + d] = r[d];
+        lo[3 * (size_t)c + d] = l[d];
+        hi[3 * (size_t)c + d] = h[d];
+    }
+    for (int a = 0; a < CL; ++a) {
+        size_t s = (size_t)c * CL + a;
+        int i = orig[s];
+        float4 v;
+        if (i >= 0) {
+            v.x = (float)(w64[3 * (size_t)i + 0] - r[0]);
+            v.y = (float)(w64[3 * (size_t)i + 1] - r[1]);
+            v.z = (float)(w64[3 * (size_t)i + 2] - r[2]);
+        } else {
+            // padding: far from everything, zero charge
+            v.x = v.y = v.z = 1.0e4f;
+        }
+        v.w = 0.0f;
+        xyzq[s] = v;
+    }
+}
+
+__device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, double hi_i) {
+    return fmax(0.0, fmax(lo_j - hi_i, lo_i - hi_j));
+}
+
+// Cluster-pair list: one wavefront per i-cluster; lanes scan the clusters of
+// each candidate column and every z image. FILL = false counts, FILL = true
+// writes at lstart[ic] in the same deterministic order.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
+                                              const int* __restrict__ col_cl, const double* __restrict__ ref,
+                                              const double* __restrict__ lo, const double* __restrict__ hi,
+                                              int* __restrict__ lcount, const int* __restrict__ lstart,
+                                              int2* __restrict__ lj, float4* __restrict__ ls) {
+    const int lane = lane_id();
+    const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ic >= ncl) return;
+    const double rl2 = g.rlist * g.rlist * (1.0 + 1e-9) + 1e-12;
+    const double eps = 1e-6;
+    const int coli = cl_col[ic];
+    const int cxi = coli % g.ncx, cyi = coli / g.ncx;
+    const double loi0 = lo[3 * ic], loi1 = lo[3 * ic + 1], loi2 = lo[3 * ic + 2];
+    const double hii0 = hi[3 * ic], hii1 = hi[3 * ic + 1], hii2 = hi[3 * ic + 2];
+    const double ri0 = ref[3 * ic], ri1 = ref[3 * ic + 1], ri2 = ref[3 * ic + 2];
+    int cnt = 0;
+    const int base = FILL ? lstart[ic] : 0;
+    for (int dy = -g.Ry; dy <= g.Ry; ++dy) {
+        int cy = cyi + dy;
+        int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
+        int cyw = cy - ny * g.ncy;
+        double sy = (double)ny * g.L[1];
+        double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
+        if (gy > 0.0 && gy * gy >= rl2) continue;
+        for (int dx = -g.Rx; dx <= g.Rx; ++dx) {
+            int cx = cxi + dx;
+            int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
+            int cxw = cx - nx * g.ncx;
+            double sx = (double)nx * g.L[0];
+            double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
+            if (gx > 0.0 && gx * gx >= rl2) continue;
+            const int col = cxw + g.ncx * cyw;
+            const int j0 = col_cl[col], j1 = col_cl[col + 1];
+            for (int jb = j0; jb < j1; jb += 64) {
+                const int jc = jb + lane;
+                const bool valid = jc < j1;
+                double dxy2 = 0.0, loj2 = 0.0, hij2 = 0.0, rj0 = 0.0, rj1 = 0.0, rj2 = 0.0;
+                if (valid) {
+                    double gxx = gap1(lo[3 * jc] + sx, hi[3 * jc] + sx, loi0, hii0);
+                    double gyy = gap1(lo[3 * jc + 1] + sy, hi[3 * jc + 1] + sy, loi1, hii1);
+                    dxy2 = gxx * gxx + gyy * gyy;
+                    loj2 = lo[3 * jc + 2];
+                    hij2 = hi[3 * jc + 2];
+                    rj0 = ref[3 * jc];
+                    rj1 = ref[3 * jc + 1];
+                    rj2 = ref[3 * jc + 2];
+                }
+                for (int nz = -g.Rz; nz <= g.Rz; ++nz) {
+                    double sz = (double)nz * g.L[2];
+                    double gz = gap1(loj2 + sz, hij2 + sz, loi2, hii2);
+                    bool pass = valid && (dxy2 + gz * gz < rl2);
+                    unsigned long long m = __ballot(pass);
+                    if (FILL && pass) {
+                        int pos = base + cnt + lanes_below(m);
+                        lj[pos] = make_int2(jc, pack_img(nx, ny, nz));
+                        ls[pos] = make_float4((float)((rj0 + sx) - ri0), (float)((rj1 + sy) - ri1),
+                                              (float)((rj2 + sz) - ri2), 0.0f);
+                    }
+                    cnt += __popcll(m);
+                }
+            }
+        }
+    }
+    if (!FILL && lane == 0) lcount[ic] = cnt;
+}
+
+// Export of the atom pairs closer than the list radius, by the canonical FP64
+// predicate; each unordered pair once. Rows are reserved with a global
+// counter; rows beyond `cap` are not written but still counted.
+__global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lstart,
+                                                const int2* __restrict__ lj, const int* __restrict__ orig,
+                                                const double* __restrict__ w64, int64_t cap,
+                                                int32_t* __restrict__ out, unsigned long long* __restrict__ counter) {
+    const int lane = lane_id();
+    const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ic >= ncl) return;
+    const int a = lane >> 3, b = lane & 7;
+    const int i = orig[(size_t)ic * CL + a];
+    const double rl2 = g.rlist * g.rlist;
+    for (int e = lstart[ic]; e < lstart[ic + 1]; ++e) {
+        const int2 je = lj[e];
+        const int j = orig[(size_t)je.x * CL + b];
+        int n0, n1, n2;
+        unpack_img(je.y, n0, n1, n2);
+        bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
+        if (ok) ok = canon_d2(w64 + 3 * (size_t)i, w64 + 3 * (size_t)j, n0, n1, n2, g.L[0], g.L[1], g.L[2]) < rl2;
+        unsigned long long m = __ballot(ok);
+        if (m == 0ull) continue;
+        unsigned long long basepos = 0;
+        if (lane == 0) basepos = atomicAdd(counter, (unsigned long long)__popcll(m));
+        basepos = __shfl(basepos, 0, 64);
+        if (ok) {
+            unsigned long long pos = basepos + lanes_below(m);
+            if ((int64_t)pos < cap && out) {
+                int32_t* r = out + 5 * pos;
+                r[0] = i;
+                r[1] = j;
+                r[2] = n0;
+                r[3] = n1;
+                r[4] = n2;
+            }
+        }
+    }
+}
+
+void scan_ints(const int* in, int* out, int n, bool ceil8, hipStream_t s) {
+    if (ceil8)
+        PQ_LAUNCH(k_scan<1>, 1, 1024, 0, s, in, out, n);
+    else
+        PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, in, out, n);
+}
+
+// ---------------------------------------------------------------------------
+void nbr_build(Ctx& c, const double* pos) {
+    const int n = (int)c.n;
+    hipStream_t s = c.stream;
+    Geom& g = c.g;
+    const pq_params& p = c.prm;
+    for (int d = 0; d < 3; ++d) {
+        g.L[d] = p.box[d];
+        g.invL[d] = 1.0 / p.box[d];
+    }
+    g.rc = p.cutoff;
+    g.rlist = p.cutoff + p.skin;
+    // columns sized for ~8 atoms per cubic cluster
+    const double V = p.box[0] * p.box[1] * p.box[2];
+    const double rho = (double)n / V;
+    const double a = std::cbrt((double)CL / rho);
+    g.ncx = std::max(1, (int)std::lround(p.box[0] / a));
+    g.ncy = std::max(1, (int)std::lround(p.box[1] / a));
+    g.wx = p.box[0] / g.ncx;
+    g.wy = p.box[1] / g.ncy;
+    g.Rx = (int)std::floor((g.rlist + 1e-6) / g.wx) + 1;
+    g.Ry = (int)std::floor((g.rlist + 1e-6) / g.wy) + 1;
+    g.Rz = (int)std::floor(g.rlist / p.box[2]) + 1;
+    c.ncol = g.ncx * g.ncy;
+    PQ_REQUIRE(2 * g.Rx + 1 <= 511 && 2 * g.Ry + 1 <= 511 && g.Rz <= 255, PQ_ERR_BOX,
+               "cutoff too large for the box (more than 255 periodic images)");
+
+    c.w64.ensure((size_t)n * 3);
+    c.col_of.ensure(n);
+    c.col_cnt.ensure(c.ncol);
+    c.col_fill.ensure(c.ncol);
+    c.col_start.ensure(c.ncol + 1);
+    c.col_cl.ensure(c.ncol + 1);
+    c.tmp_atoms.ensure(n);
+    c.flag.ensure(4);
+    c.counter.ensure(1);
+
+    PQ_HIP(hipMemsetAsync(c.col_cnt.p, 0, sizeof(int) * c.ncol, s));
+    PQ_HIP(hipMemsetAsync(c.col_fill.p, 0, sizeof(int) * c.ncol, s));
+    PQ_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int) * 4, s));
+    PQ_LAUNCH(k_wrap_count, cdiv(n, 256), 256, 0, s, n, pos, g, c.w64.p, c.col_of.p, c.col_cnt.p, c.flag.p);
+    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.col_cnt.p, c.col_start.p, c.ncol);
+    PQ_LAUNCH(k_scan<1>, 1, 1024, 0, s, c.col_cnt.p, c.col_cl.p, c.ncol);
+    int hv[2];
+    PQ_HIP(hipMemcpyAsync(&hv[0], c.col_cl.p + c.ncol, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipMemcpyAsync(&hv[1], c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    PQ_REQUIRE(hv[1] == 0, PQ_ERR_NAN, "non-finite position");
+    c.ncl = hv[0];
+    const int ncl = c.ncl;
+    const size_t nslot = (size_t)ncl * CL;
+    c.orig.ensure(nslot);
+    c.xyzq.ensure(nslot);
+    c.cl_ref.ensure((size_t)ncl * 3);
+    c.cl_lo.ensure((size_t)ncl * 3);
+    c.cl_hi.ensure((size_t)ncl * 3);
+    c.cl_col.ensure(ncl);
+    c.lcount.ensure(ncl + 1);
+    c.lstart.ensure(ncl + 1);
+
+    PQ_LAUNCH(k_bin, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_fill.p, c.tmp_atoms.p);
+    PQ_LAUNCH(k_fill_int, cdiv(nslot, 256), 256, 0, s, c.orig.p, (int)nslot, -1);
+    PQ_LAUNCH(k_rank, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_cl.p, c.tmp_atoms.p,
+              c.w64.p, c.orig.p);
+    PQ_LAUNCH(k_cluster_col, cdiv(c.ncol, 256), 256, 0, s, c.ncol, c.col_cl.p, c.cl_col.p);
+    PQ_LAUNCH(k_cluster, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
+              c.cl_hi.p, c.xyzq.p);
+    PQ_LAUNCH(k_list<false>, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p, c.cl_lo.p,
+              c.cl_hi.p, c.lcount.p, (const int*)nullptr, (int2*)nullptr, (float4*)nullptr);
+    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.lcount.p, c.lstart.p, ncl);
+    int tot = 0;
+    PQ_HIP(hipMemcpyAsync(&tot, c.lstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    PQ_REQUIRE(tot >= 0, PQ_ERR_BOX, "cluster-pair list overflow");
+    c.nlist = tot;
+    c.lj.ensure(std::max(1, tot));
+    c.ls.ensure(std::max(1, tot));
+    PQ_LAUNCH(k_list<true>, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p, c.cl_lo.p,
+              c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, c.ls.p);
+}
+
+int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {
+    hipStream_t s = c.stream;
+    PQ_HIP(hipMemsetAsync(c.counter.p, 0, sizeof(unsigned long long), s));
+    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+              pairs ? cap : (int64_t)0, pairs, c.counter.p);
+    unsigned long long tot = 0;
+    PQ_HIP(hipMemcpyAsync(&tot, c.counter.p, sizeof(tot), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    return (int64_t)tot;
+}
+
+}  // namespace pq

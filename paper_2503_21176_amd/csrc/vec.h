@@ -1,0 +1,44 @@
+// FP64 vector and small-dense helpers of the Krylov solvers (vec.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pq_internal.h"
+
+namespace pq {
+
+// Layout of the small GMRES state for restart length m (all FP64):
+// H (m+1) x m column-major, then g[m+1], cs[m], sn[m], y[m], h2[m+1].
+__host__ __device__ inline size_t gs_g(int m) { return (size_t)(m + 1) * m; }
+__host__ __device__ inline size_t gs_c(int m) { return gs_g(m) + m + 1; }
+__host__ __device__ inline size_t gs_s(int m) { return gs_c(m) + m; }
+__host__ __device__ inline size_t gs_y(int m) { return gs_s(m) + m; }
+__host__ __device__ inline size_t gs_t(int m) { return gs_y(m) + m; }
+__host__ __device__ inline size_t gs_size(int m) { return gs_t(m) + m + 2; }
+
+// mode 0: sum x; 1: sum x*y; 2: sum x/y. out = alpha * result (device scalar)
+void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, double alpha, double* out, hipStream_t s);
+void axpby(int64_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s);
+void vdiv(int64_t n, const double* x, const double* u, double* z, hipStream_t s);
+void vmul(int64_t n, const double* x, const double* u, double sc, double* z, hipStream_t s);
+void bordered_out(int64_t n, const double* y, const double* phi, const double* tsum, double* out, hipStream_t s);
+void jac_out(int64_t n, const double* x, const double* t, const double* u, const double* sums, double* out,
+             hipStream_t s);
+void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const double* u, double* out2, hipStream_t s);
+void shadow_q(int64_t n, const double* chi, const double* v, const double* u, const double* sums, double qtot,
+              double* q, double* lam, hipStream_t s);
+void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
+                   hipStream_t s);
+void normalize(int64_t n, const double* w, const double* nrm2, double* hsub, double* out, hipStream_t s);
+void givens(double* st, int m, int j, double* resid, hipStream_t s);
+void gmres_start(double* st, int m, const double* nrm2, hipStream_t s);
+void backsolve(double* st, int m, int k, hipStream_t s);
+void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, hipStream_t s);
+void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const double* u, const double* a,
+                const double* phi, double* out, hipStream_t s);
+void copy_scalar(const double* a, double* b, hipStream_t s);
+void set_scalar(double* b, double v, hipStream_t s);
+
+}  // namespace pq

@@ -1,0 +1,369 @@
+// FP64 reductions and vector kernels: energy assembly (self and background
+// terms, the paper's eq. ewald_self plus the neutralising background), and the
+// building blocks of the Krylov solvers (dot products, classical Gram-Schmidt
+// with one re-orthogonalisation, Givens rotations of the Hessenberg matrix).
+// Every reduction uses fixed block partials summed in a fixed order, so the
+// results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dev.h"
+#include "pq_internal.h"
+#include "vec.h"
+
+namespace pq {
+
+constexpr int VB = 256;   // threads per block of the vector kernels
+
+// ---- reductions -----------------------------------------------------------
+__global__ __launch_bounds__(VB) void k_part_sum(const double* __restrict__ x, const double* __restrict__ y,
+                                                 int64_t n, int mode, double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double a = x[i];
+        v += (mode == 0) ? a : (mode == 1 ? a * y[i] : a / y[i]);
+    }
+    v = block_sum<VB>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// out[k] = alpha * sum of part[k*nb .. k*nb+nb-1] (+ beta * out2 optional)
+__global__ __launch_bounds__(VB) void k_part_final(const double* __restrict__ part, int nb, int nk, double alpha,
+                                                   double* __restrict__ out) {
+    __shared__ double red[VB / 64];
+    for (int k = 0; k < nk; ++k) {
+        double v = 0.0;
+        for (int i = threadIdx.x; i < nb; i += VB) v += part[(size_t)k * nb + i];
+        v = block_sum<VB>(v, red);
+        if (threadIdx.x == 0) out[k] = alpha * v;
+        __syncthreads();
+    }
+}
+
+static int red_blocks(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(RED_BLOCKS, (n + VB - 1) / VB)); }
+
+void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, double alpha, double* out, hipStream_t s) {
+    const int nb = red_blocks(n);
+    c.part.ensure(nb + 16);
+    PQ_LAUNCH(k_part_sum, nb, VB, 0, s, x, y, n, mode, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, alpha, out);
+}
+
+void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s) { reduce(c, x, nullptr, n, 0, 1.0, out, s); }
+void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
+    reduce(c, x, y, n, 1, 1.0, out, s);
+}
+
+// ---- energy assembly --------------------------------------------------------
+// phi_i = KE (phi_real + phi_rec + self_i + background), F_i = KE (F_real + F_rec)
+// part: 3 partial sums per block of q_i * (real, rec, self+bg) potentials.
+__global__ __launch_bounds__(VB) void k_combine(int64_t n, const double* __restrict__ q, const double* __restrict__ Q,
+                                                const float* __restrict__ pr, const float4* __restrict__ fr,
+                                                const float* __restrict__ pk, const float4* __restrict__ fk,
+                                                double cself, double cbg, double* __restrict__ phi,
+                                                double* __restrict__ force, double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    const double Qs = *Q;
+    double e0 = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double qi = q[i];
+        const double a = KE * (double)pr[i];
+        const double b = KE * (double)pk[i];
+        const double sb = KE * (cself * qi + cbg * Qs);
+        if (phi) phi[i] = (a + b) + sb;
+        if (force) {
+            const float4 x = fr[i], y = fk[i];
+            force[3 * i + 0] = KE * ((double)x.x + (double)y.x);
+            force[3 * i + 1] = KE * ((double)x.y + (double)y.y);
+            force[3 * i + 2] = KE * ((double)x.z + (double)y.z);
+        }
+        e0 += qi * a;
+        e1 += qi * b;
+        e2 += qi * sb;
+    }
+    e0 = block_sum<VB>(e0, red);
+    e1 = block_sum<VB>(e1, red);
+    e2 = block_sum<VB>(e2, red);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x + 0] = e0;
+        part[3 * blockIdx.x + 1] = e1;
+        part[3 * blockIdx.x + 2] = e2;
+    }
+}
+
+// energy = {total, real, rec, self+bg}; rec from the spectral sum (erec, no KE)
+__global__ void k_energy_final(const double* __restrict__ part, int nb, const double* __restrict__ erec,
+                               double* __restrict__ energy) {
+    __shared__ double red[VB / 64];
+    double v[3];
+    for (int k = 0; k < 3; ++k) {
+        double t = 0.0;
+        for (int i = threadIdx.x; i < nb; i += VB) t += part[3 * i + k];
+        v[k] = block_sum<VB>(t, red);
+    }
+    if (threadIdx.x == 0) {
+        const double er = 0.5 * v[0], ek = KE * (*erec), es = 0.5 * v[2];
+        energy[0] = er + ek + es;
+        energy[1] = er;
+        energy[2] = ek;
+        energy[3] = es;
+    }
+}
+
+void combine(Ctx& c, const double* q, const double* Q, double* phi, double* force, double* energy, hipStream_t s) {
+    const int64_t n = c.n;
+    const int nb = red_blocks(n);
+    c.part.ensure(3 * nb + 16);
+    const double a = c.prm.alpha;
+    const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
+    const double cself = -2.0 * a / std::sqrt(PI);
+    const double cbg = -PI / (V * a * a);
+    PQ_LAUNCH(k_combine, nb, VB, 0, s, n, q, Q, c.phi_r.p, c.f_r.p, c.phi_k.p, c.f_k.p, cself, cbg, phi, force,
+              c.part.p);
+    if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.part.p, nb, c.scal.p + 1, energy);
+}
+
+// ---- elementwise kernels ----------------------------------------------------
+__global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ z) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        z[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+void axpby(int64_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s) {
+    PQ_LAUNCH(k_axpby, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, a, x, b, y, z);
+}
+
+__global__ void k_div(int64_t n, const double* __restrict__ x, const double* __restrict__ u, double* __restrict__ z) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) z[i] = x[i] / u[i];
+}
+void vdiv(int64_t n, const double* x, const double* u, double* z, hipStream_t s) {
+    PQ_LAUNCH(k_div, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, x, u, z);
+}
+
+__global__ void k_mul(int64_t n, const double* __restrict__ x, const double* __restrict__ u, double sc,
+                      double* __restrict__ z) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) z[i] = sc * x[i] * u[i];
+}
+void vmul(int64_t n, const double* x, const double* u, double sc, double* z, hipStream_t s) {
+    PQ_LAUNCH(k_mul, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, x, u, sc, z);
+}
+
+// bordered product (right-preconditioned): out_q = y_q + phi + y_l, out_l = t_sum
+__global__ void k_bordered_out(int64_t n, const double* __restrict__ y, const double* __restrict__ phi,
+                               const double* __restrict__ tsum, double* __restrict__ out) {
+    const double yl = y[n];
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        out[i] = y[i] + phi[i] + yl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *tsum;
+}
+void bordered_out(int64_t n, const double* y, const double* phi, const double* tsum, double* out, hipStream_t s) {
+    PQ_LAUNCH(k_bordered_out, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, y, phi, tsum, out);
+}
+
+// shadow Jacobian product: out = -x - (t - dinv * c),  t = phi/u, c = sum(t)/sum(1/u)
+__global__ void k_jac_out(int64_t n, const double* __restrict__ x, const double* __restrict__ t,
+                          const double* __restrict__ u, const double* __restrict__ sums, double* __restrict__ out) {
+    const double c = sums[0] / sums[1];
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        out[i] = -x[i] - (t[i] - c / u[i]);
+}
+void jac_out(int64_t n, const double* x, const double* t, const double* u, const double* sums, double* out,
+             hipStream_t s) {
+    PQ_LAUNCH(k_jac_out, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, x, t, u, sums, out);
+}
+
+// shadow charges: lambda = -(Qtot + sum (chi+v)/u) / sum(1/u);  q = -(chi + v + lambda)/u
+__global__ void k_shadow_q(int64_t n, const double* __restrict__ chi, const double* __restrict__ v,
+                           const double* __restrict__ u, const double* __restrict__ sums, double qtot,
+                           double* __restrict__ q, double* __restrict__ lam_out) {
+    const double lam = -(qtot + sums[0]) / sums[1];
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        q[i] = -(chi[i] + v[i] + lam) / u[i];
+    if (blockIdx.x == 0 && threadIdx.x == 0 && lam_out) *lam_out = lam;
+}
+void shadow_q(int64_t n, const double* chi, const double* v, const double* u, const double* sums, double qtot,
+              double* q, double* lam, hipStream_t s) {
+    PQ_LAUNCH(k_shadow_q, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, chi, v, u, sums, qtot, q, lam);
+}
+
+// (chi + v)/u and 1/u summed in one pass: part[0..nb) and part[nb..2nb)
+__global__ __launch_bounds__(VB) void k_part_shadow(int64_t n, const double* __restrict__ chi,
+                                                    const double* __restrict__ v, const double* __restrict__ u,
+                                                    double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double iu = 1.0 / u[i];
+        a += ((chi ? chi[i] : 0.0) + v[i]) * iu;
+        b += iu;
+    }
+    a = block_sum<VB>(a, red);
+    b = block_sum<VB>(b, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = a;
+        part[gridDim.x + blockIdx.x] = b;
+    }
+}
+void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const double* u, double* out2,
+                 hipStream_t s) {
+    const int nb = red_blocks(n);
+    c.part.ensure(2 * nb + 16);
+    PQ_LAUNCH(k_part_shadow, nb, VB, 0, s, n, chi, v, u, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 2, 1.0, out2);
+}
+
+// ---- Gram-Schmidt -----------------------------------------------------------
+// part[k*nb + b] = partial of V_k . w for k <= j
+__global__ __launch_bounds__(VB) void k_mdot(int64_t n, const double* __restrict__ V, size_t ld, int nk,
+                                             const double* __restrict__ w, double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    for (int k = 0; k < nk; ++k) {
+        double v = 0.0;
+        const double* Vk = V + (size_t)k * ld;
+        for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) v += Vk[i] * w[i];
+        v = block_sum<VB>(v, red);
+        if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = v;
+        __syncthreads();
+    }
+}
+// w -= sum_k h[k] V_k ; hacc[k] += h[k] (optional)
+__global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const double* __restrict__ h,
+                          double* __restrict__ w) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        double acc = w[i];
+        for (int k = 0; k < nk; ++k) acc -= h[k] * V[(size_t)k * ld + i];
+        w[i] = acc;
+    }
+}
+__global__ void k_hadd(int nk, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+    for (int k = threadIdx.x; k < nk; k += blockDim.x) out[k] = a[k] + b[k];
+}
+
+void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
+                   hipStream_t s) {
+    const int nb = red_blocks(n);
+    c.part.ensure((size_t)nk * nb + 16);
+    const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
+    // pass 1
+    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, w, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, hcol);
+    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, hcol, w);
+    // pass 2 (re-orthogonalisation)
+    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, w, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, tmp2);
+    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, tmp2, w);
+    PQ_LAUNCH(k_hadd, 1, 64, 0, s, nk, hcol, tmp2, hcol);
+}
+
+// V_{j+1} = w / h, h = sqrt(nrm2) stored into H(j+1, j); zero vector if h == 0
+__global__ void k_normalize(int64_t n, const double* __restrict__ w, const double* __restrict__ nrm2,
+                            double* __restrict__ hsub, double* __restrict__ out) {
+    const double h = sqrt(fmax(*nrm2, 0.0));
+    const double inv = h > 0.0 ? 1.0 / h : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) out[i] = w[i] * inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && hsub) *hsub = h;
+}
+void normalize(int64_t n, const double* w, const double* nrm2, double* hsub, double* out, hipStream_t s) {
+    PQ_LAUNCH(k_normalize, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, w, nrm2, hsub, out);
+}
+
+// ---- small dense GMRES state (one thread) ------------------------------------
+// Layout of st (m = restart length): H (m+1) x m column-major at 0,
+// g[m+1] at GS_G, cs[m] at GS_C, sn[m] at GS_S, y[m] at GS_Y, scalars at GS_X.
+__global__ void k_givens(double* __restrict__ st, int m, int j, double* __restrict__ resid_out) {
+    if (threadIdx.x != 0) return;
+    double* H = st;
+    double* g = st + gs_g(m);
+    double* cs = st + gs_c(m);
+    double* sn = st + gs_s(m);
+    double* col = H + (size_t)j * (m + 1);
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    if (resid_out) *resid_out = fabs(g[j + 1]);
+}
+void givens(double* st, int m, int j, double* resid, hipStream_t s) { PQ_LAUNCH(k_givens, 1, 64, 0, s, st, m, j, resid); }
+
+// start of a cycle: g = (beta, 0, ...), beta = sqrt(nrm2)
+__global__ void k_gmres_start(double* __restrict__ st, int m, const double* __restrict__ nrm2) {
+    if (threadIdx.x != 0) return;
+    double* g = st + gs_g(m);
+    for (int i = 0; i <= m; ++i) g[i] = 0.0;
+    g[0] = sqrt(fmax(*nrm2, 0.0));
+}
+void gmres_start(double* st, int m, const double* nrm2, hipStream_t s) { PQ_LAUNCH(k_gmres_start, 1, 64, 0, s, st, m, nrm2); }
+
+// y = R^-1 g for the first k columns
+__global__ void k_backsolve(double* __restrict__ st, int m, int k) {
+    if (threadIdx.x != 0) return;
+    const double* H = st;
+    const double* g = st + gs_g(m);
+    double* y = st + gs_y(m);
+    for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+        const double d = H[(size_t)i * (m + 1) + i];
+        y[i] = d != 0.0 ? t / d : 0.0;
+    }
+}
+void backsolve(double* st, int m, int k, hipStream_t s) { PQ_LAUNCH(k_backsolve, 1, 64, 0, s, st, m, k); }
+
+// x += sum_k y[k] V_k
+__global__ void k_xupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const double* __restrict__ y,
+                          double* __restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        double acc = x[i];
+        for (int k = 0; k < nk; ++k) acc += y[k] * V[(size_t)k * ld + i];
+        x[i] = acc;
+    }
+}
+void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, hipStream_t s) {
+    PQ_LAUNCH(k_xupdate, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, V, ld, nk, y, x);
+}
+
+// QEQ energy: E = sum q chi + 1/2 sum u q^2 + 1/2 sum q phi  (shadow: 1/2 sum (2q - n) phi_n)
+__global__ __launch_bounds__(VB) void k_part_energy(int64_t n, const double* __restrict__ q,
+                                                    const double* __restrict__ chi, const double* __restrict__ u,
+                                                    const double* __restrict__ a, const double* __restrict__ phi,
+                                                    double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double qi = q[i];
+        v += qi * chi[i] + 0.5 * u[i] * qi * qi + 0.5 * a[i] * phi[i];
+    }
+    v = block_sum<VB>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const double* u, const double* a,
+                const double* phi, double* out, hipStream_t s) {
+    const int nb = red_blocks(n);
+    c.part.ensure(nb + 16);
+    PQ_LAUNCH(k_part_energy, nb, VB, 0, s, n, q, chi, u, a, phi, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, out);
+}
+
+__global__ void k_copy_scalar(const double* __restrict__ a, double* __restrict__ b) {
+    if (threadIdx.x == 0) *b = *a;
+}
+void copy_scalar(const double* a, double* b, hipStream_t s) { PQ_LAUNCH(k_copy_scalar, 1, 64, 0, s, a, b); }
+
+__global__ void k_set_scalar(double* __restrict__ b, double v) {
+    if (threadIdx.x == 0) *b = v;
+}
+void set_scalar(double* b, double v, hipStream_t s) { PQ_LAUNCH(k_set_scalar, 1, 64, 0, s, b, v); }
+
+}  // namespace pq

@@ -1,0 +1,53 @@
+"""Host-side checks of the C ABI (no GPU compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmeqeq.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pq_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_documented_entry_points():
+    names = _declared()
+    for n in ["pq_create", "pq_set_system", "pq_coulomb", "pq_neighbor_pairs", "pq_qeq_solve",
+              "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit", "pq_server_poll"]:
+        assert n in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    import paper_2503_21176_amd as P
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libpmeqeq.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(P.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert sorted(P.EXPORTS) == _declared()
+    L = P.load()
+    assert L.pq_abi_version() == 1
+    assert L.pq_coulomb_constant() == 14.3996454784
+
+
+def test_params_struct_layout_matches_header():
+    import paper_2503_21176_amd as P
+    # box[3], cutoff, skin, alpha (6 doubles) + grid[3], order, kmax[3], method, flags (9 int32)
+    assert ctypes.sizeof(P.Params) == 6 * 8 + 9 * 4 + 4   # padded to 8-byte alignment
+    assert P.Params.grid.offset == 48 and P.Params.flags.offset == 80
+    assert ctypes.sizeof(P.SolveInfo) == 24
+
+
+def test_make_params_validation_on_host():
+    import paper_2503_21176_amd as P
+    p = P.make_params(20.0, 8.0, 0.35, grid=32, order=4)
+    assert p.method == P.METHOD_PME and list(p.grid) == [32, 32, 32]
+    p = P.make_params([20.0, 21.0, 22.0], 8.0, 0.35, kmax=8, method="ewald")
+    assert p.method == P.METHOD_EWALD and list(p.kmax) == [8, 8, 8]
+    with pytest.raises(ValueError):
+        P.make_params(20.0, 8.0, 0.35, method="p3m")

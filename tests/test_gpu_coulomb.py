@@ -1,0 +1,229 @@
+"""Parity of the HIP Coulomb path (C ABI) with the FP64 oracle.
+
+Tolerances (FP32 bulk arithmetic, FP64 reductions), against the oracle run
+with the same alpha, cutoff, grid and order, so only rounding differs:
+  ||dphi||_2 / ||phi||_2 <= 1e-5,  ||dF||_rms / ||F||_rms <= 1e-5,  |dE|/|E| <= 1e-6.
+Neighbour pair sets must match exactly.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_PHI = 1e-5
+TOL_F = 1e-5
+TOL_E = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2503_21176_amd as P
+    P.load()
+    return P
+
+
+def gpu(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def rel2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def rms_rel(a, b):
+    return float(np.sqrt(np.mean(np.sum((a - b) ** 2, 1))) / np.sqrt(np.mean(np.sum(b ** 2, 1))))
+
+
+def run(P, s, params, q=None):
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), params)
+    phi, F, E = ctx.coulomb(gpu(s.q if q is None else q))
+    torch.cuda.synchronize()
+    out = phi.cpu().numpy(), F.cpu().numpy(), E.cpu().numpy()
+    ctx.close()
+    return out
+
+
+def check(name, phi, F, E, ref, rows=None, e_tol=TOL_E, energies=True):
+    rp = ref["phi"]
+    rf = ref["F"]
+    if rows is not None:
+        phi, F = phi[rows], F[rows]
+    ephi, ef = rel2(phi, rp), rms_rel(F, rf)
+    say(f"[{name}] phi rel {ephi:.2e}  F rms rel {ef:.2e}  max|dphi| {np.abs(phi - rp).max():.2e}")
+    assert ephi <= TOL_PHI
+    assert ef <= TOL_F
+    if energies:
+        # relative to the magnitude of the three parts: for non-neutral or
+        # strongly screened systems the total is a difference of large terms
+        scale = abs(ref["E_real"]) + abs(ref["E_rec"]) + abs(ref["E_selfbg"])
+        eE = abs(E[0] - ref["E"]) / scale
+        say(f"[{name}] E {E[0]:.10g} vs {ref['E']:.10g} rel(parts) {eE:.2e}; parts {E[1:]} vs "
+            f"{[ref['E_real'], ref['E_rec'], ref['E_selfbg']]}")
+        assert eE <= e_tol
+        for k, key in ((1, "E_real"), (2, "E_rec"), (3, "E_selfbg")):
+            assert abs(E[k] - ref[key]) <= e_tol * scale
+
+
+def test_nacl_ewald_madelung(P):
+    s = W.nacl()
+    say("[nacl-ewald] n=512 L=22.56 rc=8 alpha=0.35 kmax=8")
+    prm = P.make_params(s.box, 8.0, 0.35, kmax=8, method="ewald")
+    phi, F, E = run(P, s, prm)
+    ref = O.ewald_direct(s.pos, s.q, s.box, 0.35, 8.0, 8)
+    M = -float(np.mean(s.q * phi)) * 2.82 / O.KE
+    say(f"[nacl-ewald] Madelung {M:.9f}")
+    assert abs(M - (-float(np.mean(s.q * ref['phi'])) * 2.82 / O.KE)) < 1e-6
+    assert abs(M / 1.747564594633 - 1) < 1.5e-4
+    assert rel2(phi, ref["phi"]) <= TOL_PHI
+    # the perfect crystal has zero force on every ion
+    assert np.abs(F).max() < 1e-4
+    assert abs(E[0] - ref["E"]) / abs(ref["E"]) <= TOL_E
+
+
+def test_nacl_pme(P):
+    s = W.nacl(shuffle_seed=1)
+    say("[nacl-pme] n=512 grid 32 order 4, shuffled order")
+    prm = P.make_params(s.box, 8.0, 0.35, grid=32, order=4)
+    phi, F, E = run(P, s, prm)
+    ref = O.spme_full(s.pos, s.q, s.box, 0.35, 8.0, 32, 4)
+    assert rel2(phi, ref["phi"]) <= TOL_PHI
+    assert np.abs(F).max() < 1e-4
+    assert abs(E[0] - ref["E"]) / abs(ref["E"]) <= TOL_E
+
+
+@pytest.mark.parametrize("n,order,K", [(64, 5, 10), (150, 5, 12), (300, 6, 16)])
+def test_small_boxes_multi_image_pme(P, n, order, K):
+    # boxes shorter than twice the cutoff: every periodic image within rc counts
+    L = (n / 0.1) ** (1 / 3)
+    s = W.small_random(n, L, seed=100 + n)
+    a, rc = W.ALPHA_RC9, 9.0
+    say(f"[small-pme] n={n} L={L:.3f} rc={rc} K={K} p={order}")
+    phi, F, E = run(P, s, P.make_params(s.box, rc, a, grid=K, order=order))
+    ref = O.spme_full(s.pos, s.q, s.box, a, rc, K, order)
+    check(f"small-pme n={n}", phi, F, E, ref)
+
+
+@pytest.mark.parametrize("n,kmax", [(64, 6), (200, 7)])
+def test_small_boxes_multi_image_ewald(P, n, kmax):
+    L = (n / 0.1) ** (1 / 3)
+    s = W.small_random(n, L, seed=200 + n)
+    a, rc = 0.35, 9.0
+    say(f"[small-ewald] n={n} L={L:.3f} rc={rc} kmax={kmax}")
+    phi, F, E = run(P, s, P.make_params(s.box, rc, a, kmax=kmax, method="ewald"))
+    ref = O.ewald_direct(s.pos, s.q, s.box, a, rc, kmax)
+    check(f"small-ewald n={n}", phi, F, E, ref)
+
+
+def test_non_neutral_charges_and_anisotropic_box(P):
+    rng = np.random.default_rng(7)
+    box = np.array([17.0, 21.0, 25.0])
+    n = 700
+    pos = rng.uniform(-30, 60, size=(n, 3))        # unwrapped on purpose
+    q = rng.normal(0.3, 1.0, size=n)               # net charge != 0
+    s = W.System("aniso", pos, q, box)
+    a, rc = 0.4, 7.5
+    say(f"[aniso] n={n} box={box} K=(20,24,30) p=6, non-neutral")
+    phi, F, E = run(P, s, P.make_params(box, rc, a, grid=(20, 24, 30), order=6))
+    ref = O.spme_full(pos, q, box, a, rc, (20, 24, 30), 6)
+    check("aniso", phi, F, E, ref)
+
+
+def test_random_ionic_3000(P):
+    s = W.random_ionic(n=3000, seed=9, grid=None, order=6)
+    K = 32
+    say(f"[ionic-3000] L={s.box[0]:.3f} rc=10 K={K} p=6")
+    phi, F, E = run(P, s, P.make_params(s.box, 10.0, W.ALPHA_RC10, grid=K, order=6))
+    ref = O.spme_full(s.pos, s.q, s.box, W.ALPHA_RC10, 10.0, K, 6)
+    check("ionic-3000", phi, F, E, ref)
+
+
+def test_water_box_sampled(P):
+    s = W.water_box()
+    a = W.ALPHA_RC10
+    say("[water] n=9000 L=31 rc=10 grid 64 order 6 (256 sampled atoms)")
+    phi, F, E = run(P, s, P.make_params(s.box, 10.0, a, grid=64, order=6))
+    rows = np.random.default_rng(0).choice(s.n, 256, replace=False)
+    ref = O.spme_full(s.pos, s.q, s.box, a, 10.0, 64, 6, rows=rows)
+    check("water", phi, F, E, ref, rows=rows, energies=False)
+    # the reciprocal energy needs no rows: spectral sum of the full grid
+    _, _, erec = O.spme_reciprocal(s.pos, s.q, s.box, a, 64, 6, rows=rows[:1])
+    say(f"[water] E_rec {E[2]:.10g} vs {erec:.10g}")
+    assert abs(E[2] - erec) <= 1e-5 * abs(erec)
+
+
+@pytest.mark.slow
+def test_random_ionic_300k_sampled(P):
+    s = W.random_ionic()          # 300,000 atoms, 144^3, order 6
+    a = W.ALPHA_RC10
+    say("[ionic-300k] n=300000 L=144.225 rc=10 grid 144 order 6 (48 sampled atoms)")
+    phi, F, E = run(P, s, P.make_params(s.box, 10.0, a, grid=144, order=6))
+    rows = np.random.default_rng(1).choice(s.n, 48, replace=False)
+    ref = O.spme_full(s.pos, s.q, s.box, a, 10.0, 144, 6, rows=rows)
+    check("ionic-300k", phi, F, E, ref, rows=rows, energies=False)
+    say(f"[ionic-300k] E_rec {E[2]:.10g} vs {ref['E_rec']:.10g}")
+    assert abs(E[2] - ref["E_rec"]) <= 1e-5 * abs(ref["E_rec"])
+    # total charge is zero, so E = 1/2 sum q phi and the parts must add up
+    assert abs(E[0] - E[1:].sum()) <= 1e-12 * abs(E[0])
+
+
+# ---------------------------------------------------------------------------
+# neighbour pairs: exact set equality
+# ---------------------------------------------------------------------------
+def gpu_pairs(P, s, rc, skin):
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), P.make_params(s.box, rc, 0.3, skin=skin, kmax=1, method="ewald"))
+    pr = ctx.neighbor_pairs().cpu().numpy().astype(np.int64)
+    ctx.close()
+    order = np.lexsort((pr[:, 4], pr[:, 3], pr[:, 2], pr[:, 1], pr[:, 0]))
+    return pr[order]
+
+
+@pytest.mark.parametrize("case", ["nacl", "nacl-shuffled", "tiny-multi", "small-multi", "ionic-2000"])
+def test_neighbor_pairs_exact(P, case):
+    if case == "nacl":
+        s, rc, skin = W.nacl(), 8.0, 0.0
+    elif case == "nacl-shuffled":
+        s, rc, skin = W.nacl(shuffle_seed=3), 5.64, 0.0     # many pairs exactly at the cutoff
+    elif case == "tiny-multi":
+        s, rc, skin = W.small_random(5, 3.0, seed=3, dmin=0.3), 4.0, 0.0
+    elif case == "small-multi":
+        s, rc, skin = W.small_random(64, 8.62, seed=4), 9.0, 0.0
+    else:
+        s, rc, skin = W.random_ionic(n=2000, seed=11, grid=None), 10.0, 1.0
+    say(f"[pairs-{case}] n={s.n} L={s.box[0]:.3f} cut={rc + skin}")
+    got = gpu_pairs(P, s, rc, skin)
+    want = O.neighbor_pairs(s.pos, s.box, rc + skin)
+    say(f"[pairs-{case}] gpu {len(got)} oracle {len(want)}")
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_invalid_arguments_raise(P):
+    s = W.small_random(20, 6.0, seed=5)
+    ctx = P.Context(0)
+    with pytest.raises(P.PQError):
+        ctx.set_system(gpu(s.pos), P.make_params(s.box, 3.0, 0.5, grid=14, order=4))   # 14 = 2*7
+    with pytest.raises(P.PQError):
+        ctx.set_system(gpu(s.pos), P.make_params(s.box, 3.0, 0.5, grid=16, order=9))
+    with pytest.raises(P.PQError):
+        ctx.set_system(gpu(s.pos), P.make_params(s.box, -1.0, 0.5, grid=16, order=4))
+    bad = s.pos.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(P.PQError):
+        ctx.set_system(gpu(bad), P.make_params(s.box, 3.0, 0.5, grid=16, order=4))
+    with pytest.raises(P.PQError):          # no system set after the failures
+        ctx.coulomb(gpu(s.q))
+    ctx.close()
