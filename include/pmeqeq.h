@@ -143,8 +143,11 @@ enum {
     PQ_PHASE_TOTAL = 6,    /* whole evaluation                                */
     PQ_NPHASE = 7
 };
-/* Enables (on != 0) or disables event timing of pq_coulomb and of the
- * evaluations inside the solvers. Adds two events per phase per evaluation. */
+/* Event timing of pq_coulomb and of the evaluations inside the solvers:
+ * on = 0 off; 1 on (the real-space phase overlaps the reciprocal phases on a
+ * second stream as usual, so their intervals overlap); 2 on with the phases
+ * serialised on the context's stream, so each phase is timed alone. Adds two
+ * events per phase per evaluation. */
 pq_status pq_set_timing(pq_ctx* ctx, int on);
 /* Host-synchronising. Writes to ms[0..PQ_NPHASE) (host) the milliseconds
  * summed over the evaluations timed since the last call, and to *count the

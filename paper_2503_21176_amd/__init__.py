@@ -209,8 +209,9 @@ class Context:
         _check(self.lib.pq_neighbor_pairs(self.h, cnt.value, _ptr(out), ctypes.byref(cnt)))
         return out[:cnt.value]
 
-    def set_timing(self, on: bool = True):
-        _check(self.lib.pq_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, mode=1):
+        """0 off, 1 phase events (phases overlap as in production), 2 phases serialised."""
+        _check(self.lib.pq_set_timing(self.h, int(mode)))
 
     def timings(self):
         """Per-phase device milliseconds summed since the last call, and the count."""

@@ -16,7 +16,11 @@ thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
 Ctx::~Ctx() {
+    if (side) (void)hipStreamSynchronize(side);
     if (pinned) (void)hipHostFree(pinned);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     for (auto& v : ev_pending)
         for (auto e : v) (void)hipEventDestroy(e);
     for (auto e : ev_pool) (void)hipEventDestroy(e);
@@ -80,11 +84,11 @@ struct PhaseEvents {
             }
         }
     }
-    void begin(int ph) {
-        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph], s));
+    void begin(int ph, hipStream_t on = nullptr) {
+        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph], on ? on : s));
     }
-    void end(int ph) {
-        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph + 1], s));
+    void end(int ph, hipStream_t on = nullptr) {
+        if (!ev.empty()) PQ_HIP(hipEventRecord(ev[2 * ph + 1], on ? on : s));
     }
     void commit() {
         if (!ev.empty()) c.ev_pending.push_back(std::move(ev));
@@ -101,9 +105,20 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     stage_charges(c, q, s);
     sum_vector(c, q, c.n, c.scal.p + 0, s);
     E.end(PQ_PHASE_STAGE);
-    E.begin(PQ_PHASE_PAIR);
-    pair_sum(c, fo, c.phi_r.p, c.f_r.p, s);
-    E.end(PQ_PHASE_PAIR);
+    // the real-space pair kernel (ALU bound) runs on the context's second
+    // stream, concurrently with the memory-bound reciprocal-space chain
+    if (!c.side) {
+        PQ_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+        PQ_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+        PQ_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    }
+    hipStream_t ps = c.serial ? s : c.side;
+    PQ_HIP(hipEventRecord(c.ev_fork, s));
+    PQ_HIP(hipStreamWaitEvent(ps, c.ev_fork, 0));
+    E.begin(PQ_PHASE_PAIR, ps);
+    pair_sum(c, fo, c.phi_r.p, c.f_r.p, ps);
+    E.end(PQ_PHASE_PAIR, ps);
+    PQ_HIP(hipEventRecord(c.ev_join, ps));
     if (c.prm.method == PQ_METHOD_PME) {
         pme_eval(c, q, fo, c.phi_k.p, c.f_k.p, E.ev.empty() ? nullptr : E.ev.data(), s);
     } else {
@@ -115,6 +130,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
         ewald_eval(c, q, fo, c.phi_k.p, c.f_k.p, s);
         E.end(PQ_PHASE_GATHER);
     }
+    PQ_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
     E.begin(PQ_PHASE_COMBINE);
     combine(c, q, c.scal.p + 0, phi, force, energy, s);
     E.end(PQ_PHASE_COMBINE);
@@ -229,7 +245,9 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
 pq_status pq_set_timing(pq_ctx* ctx, int on) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
+    PQ_REQUIRE(on >= 0 && on <= 2, PQ_ERR_INVALID, "timing mode must be 0, 1 or 2");
     reinterpret_cast<Ctx*>(ctx)->timing = on != 0;
+    reinterpret_cast<Ctx*>(ctx)->serial = on == 2;
     return PQ_OK;
     PQ_API_END
 }

@@ -3,10 +3,11 @@
 //
 // Atoms are sorted by the "brick" (B x B x B block of grid points) that holds
 // their base grid point floor(u). One workgroup owns one brick:
-//  * spreading accumulates q_i M_p(u_x - k_x) M_p(u_y - k_y) M_p(u_z - k_z)
-//    into an LDS copy of the brick plus its (p-1)-point halo with LDS atomics,
-//    then flushes the non-zero points to the global grid with FP32 atomics
-//    (one global atomic per brick point instead of one per atom and point);
+//  * spreading accumulates each brick's atoms into LDS copies of the brick
+//    plus its (p-1)-point halo (one atom per wavefront step, one stencil row
+//    per lane: conflict-free plain updates, no atomics), stores that region to
+//    a staging buffer, and a second pass sums, per grid point, the (at most 8)
+//    regions that overlap it: deterministic, no clearing pass;
 //  * gathering stages the same region of the convolved grid in LDS and
 //    reads each atom's p^3 stencil from there.
 // Eight lanes serve one atom; lane y < p walks the (z, x) plane of stencil row y.
@@ -95,61 +96,127 @@ __global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const flo
     pme_frac[pos] = frac_tmp[i];
 }
 
-__global__ void k_zero_f(float* __restrict__ a, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t st = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += st) a[i] = 0.0f;
+// B-spline weights of every atom (brick order), computed once per set of
+// positions: pme_w[k] = {M_p(f_x + t)}_t, {M_p(f_y + t)}_t, {M_p(f_z + t)}_t,
+// each padded to 8 entries.
+template <int P>
+__global__ void k_pme_weights(int n, const float4* __restrict__ pme_frac, float* __restrict__ pme_w) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float4 f4 = pme_frac[k];
+    float w[P], dd[P];
+    float* out = pme_w + (size_t)k * 24;
+    const float fr[3] = {f4.x, f4.y, f4.z};
+    for (int d = 0; d < 3; ++d) {
+        bspline<P>(fr[d], w, dd);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) out[8 * d + t] = (t < P) ? w[t] : 0.0f;
+    }
 }
 
+// Spreading, pass 1: the workgroup of brick b accumulates
+// q_i M_p(u_x - k_x) M_p(u_y - k_y) M_p(u_z - k_z) of its own atoms over the
+// region [b*B - (p-1), b*B + B - 1]^3 (the brick plus its halo on the low
+// side) and stores the region to a per-brick staging slot with plain
+// coalesced stores. Each wavefront keeps a private LDS copy of the region and
+// takes one atom per step, lane (y, z) updating stencil row (y, z): the
+// updates of one step hit distinct addresses, so plain read-modify-writes
+// replace atomics; the copies are summed at the end. No atomics at all.
 template <int P>
-__global__ __launch_bounds__(256) void k_spread(PmeGeo G, const int* __restrict__ brick_start,
-                                                const int* __restrict__ pme_idx, const float4* __restrict__ pme_frac,
-                                                const double* __restrict__ q, float* __restrict__ grid) {
+__global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __restrict__ brick_start,
+                                                      const int* __restrict__ pme_idx,
+                                                      const float4* __restrict__ pme_frac,
+                                                      const float* __restrict__ pme_w,
+                                                      const double* __restrict__ q, float* __restrict__ stage) {
     constexpr int R = PME_B + P - 1;
-    __shared__ float lds[R * R * R];
+    constexpr int R3 = R * R * R;
+    __shared__ float lds[4][R3];
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
-    if (s0 == s1) return;
-    for (int t = threadIdx.x; t < R * R * R; t += 256) lds[t] = 0.0f;
+    for (int t = threadIdx.x; t < 4 * R3; t += 256) (&lds[0][0])[t] = 0.0f;
     __syncthreads();
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
-    const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
-    for (int k = s0 + grp; k < s1; k += 32) {
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ty = lane & 7, tz = lane >> 3;
+    const bool active = (ty < P) && (tz < P);
+    float* my = lds[wv];
+    for (int k = s0 + wv; k < s1; k += 4) {
         const float4 f4 = pme_frac[k];
         const float qq = (float)q[pme_idx[k]];
+        const float* wk = pme_w + (size_t)k * 24;
         const int pk = __float_as_int(f4.w);
         const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
-        float wx[P], wy[P], wz[P], dd[P];
-        bspline<P>(f4.x, wx, dd);
-        bspline<P>(f4.y, wy, dd);
-        bspline<P>(f4.z, wz, dd);
-        if (sub < P) {
-            const int ly = gy - sub - y0;
-            const float qy = qq * pick<P>(wy, sub);
+        float wx[P];
 #pragma unroll
-            for (int tz = 0; tz < P; ++tz) {
-                const int lz = gz - tz - z0;
-                const float qyz = qy * wz[tz];
-                float* row = lds + (lz * R + ly) * R + (gx - x0);
+        for (int t = 0; t < P; ++t) wx[t] = wk[t];
+        if (active) {
+            const float c = qq * wk[8 + ty] * wk[16 + tz];
+            float* row = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
+            float v[P];
 #pragma unroll
-                for (int tx = 0; tx < P; ++tx) atomicAdd(row - tx, qyz * wx[tx]);
+            for (int tx = 0; tx < P; ++tx) v[tx] = row[-tx];
+#pragma unroll
+            for (int tx = 0; tx < P; ++tx) row[-tx] = fmaf(c, wx[tx], v[tx]);
+        }
+        // the next atom may update the same rows
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    float* out = stage + (size_t)bid * R3;
+    for (int t = threadIdx.x; t < R3; t += 256) out[t] = (lds[0][t] + lds[1][t]) + (lds[2][t] + lds[3][t]);
+}
+
+// Bricks b (and local coordinates l in [0, R)) whose region holds grid
+// coordinate g along one axis: b*B - (p-1) + l == g (mod K).
+template <int P>
+__device__ __forceinline__ int region_hits(int g, int K, int nb, int* bb, int* ll) {
+    constexpr int R = PME_B + P - 1;
+    int cnt = 0;
+    for (int m = -1; m <= 1; ++m) {
+        const int gp = g + m * K;
+        // b*B - (P-1) <= gp <= b*B + B - 1
+        int blo = gp - PME_B + 1;
+        blo = (blo >= 0) ? (blo + PME_B - 1) / PME_B : -((-blo) / PME_B);
+        const int bhi_num = gp + P - 1;
+        const int bhi = (bhi_num >= 0) ? bhi_num / PME_B : -((-bhi_num + PME_B - 1) / PME_B);
+        for (int b = max(blo, 0); b <= min(bhi, nb - 1); ++b) {
+            const int l = gp - b * PME_B + (P - 1);
+            if (l >= 0 && l < R && cnt < 6) {
+                bb[cnt] = b;
+                ll[cnt] = l;
+                ++cnt;
             }
         }
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < R * R * R; t += 256) {
-        const float v = lds[t];
-        if (v == 0.0f) continue;
-        const int lx = t % R, ly = (t / R) % R, lz = t / (R * R);
-        int X = x0 + lx, Y = y0 + ly, Z = z0 + lz;
-        X += (X < 0) ? G.K0 : 0;
-        X -= (X >= G.K0) ? G.K0 : 0;
-        Y += (Y < 0) ? G.K1 : 0;
-        Y -= (Y >= G.K1) ? G.K1 : 0;
-        Z += (Z < 0) ? G.K2 : 0;
-        Z -= (Z >= G.K2) ? G.K2 : 0;
-        atomicAdd(&grid[((size_t)Z * G.K1 + Y) * G.K0 + X], v);
+    return cnt;
+}
+
+// Spreading, pass 2: each grid point sums the staged regions that hold it
+// (fixed order: deterministic).
+template <int P>
+__global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const float* __restrict__ stage,
+                                                       float* __restrict__ grid) {
+    constexpr int R = PME_B + P - 1;
+    constexpr int R3 = R * R * R;
+    const size_t ng = (size_t)G.K0 * G.K1 * G.K2;
+    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < ng; idx += (size_t)gridDim.x * 256) {
+        const int gx = (int)(idx % G.K0);
+        const int gy = (int)((idx / G.K0) % G.K1);
+        const int gz = (int)(idx / ((size_t)G.K0 * G.K1));
+        int bx[6], lx[6], by[6], ly[6], bz[6], lz[6];
+        const int nx = region_hits<P>(gx, G.K0, G.nb0, bx, lx);
+        const int ny = region_hits<P>(gy, G.K1, G.nb1, by, ly);
+        const int nz = region_hits<P>(gz, G.K2, G.nb2, bz, lz);
+        float v = 0.0f;
+        for (int iz = 0; iz < nz; ++iz)
+            for (int iy = 0; iy < ny; ++iy)
+                for (int ix = 0; ix < nx; ++ix) {
+                    const int b = bx[ix] + G.nb0 * (by[iy] + G.nb1 * bz[iz]);
+                    v += stage[(size_t)b * R3 + (lz[iz] * R + ly[iy]) * R + lx[ix]];
+                }
+        grid[idx] = v;
     }
 }
 
@@ -268,6 +335,8 @@ void pme_setup(Ctx& c) {
     c.f_k.ensure(n);   // temporary for the unsorted fractional parts
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     c.grid.ensure(ng);
+    const int R = PME_B + c.P - 1;
+    c.stage.ensure((size_t)c.nbrick * R * R * R);
     c.spec.ensure((size_t)(c.K[0] / 2 + 1) * c.K[1] * c.K[2]);
     PmeGeo G = geo(c);
     PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
@@ -276,6 +345,16 @@ void pme_setup(Ctx& c) {
     scan_ints(c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
     PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.f_k.p, c.brick_start.p, c.brick_fill.p,
               c.pme_idx.p, c.pme_frac.p);
+    c.pme_w.ensure((size_t)n * 24);
+    switch (c.P) {
+        case 3: PQ_LAUNCH(k_pme_weights<3>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        case 4: PQ_LAUNCH(k_pme_weights<4>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        case 5: PQ_LAUNCH(k_pme_weights<5>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        case 6: PQ_LAUNCH(k_pme_weights<6>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        case 7: PQ_LAUNCH(k_pme_weights<7>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        case 8: PQ_LAUNCH(k_pme_weights<8>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
+        default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
+    }
     fft_setup(c);
 }
 
@@ -284,8 +363,9 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, float* phi, float4* 
     PmeGeo G = geo(c);
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
-    PQ_LAUNCH(k_zero_f, std::min<size_t>(cdiv(ng, 256), 4096), 256, 0, s, c.grid.p, ng);
-    PQ_LAUNCH(k_spread<P>, c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, c.pme_frac.p, q, c.grid.p);
+    PQ_LAUNCH(k_spread_stage<P>, c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, c.pme_frac.p, c.pme_w.p,
+              q, c.stage.p);
+    PQ_LAUNCH(k_spread_reduce<P>, std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, c.stage.p, c.grid.p);
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT], s));
     fft_convolve(c, s);

@@ -141,7 +141,9 @@ struct Ctx {
     DBuf<int> brick_of, brick_cnt, brick_start, brick_fill;
     DBuf<int> pme_idx;       // brick-ordered original indices
     DBuf<float4> pme_frac;   // fractional parts + packed base index
+    DBuf<float> pme_w;       // B-spline weights per atom, 3 x 8 (brick order)
     DBuf<float> grid;        // real grid K1*K2*K3 (x fastest)
+    DBuf<float> stage;       // per-brick spreading regions (B+p-1)^3
     DBuf<float2> spec;       // half spectrum (K1/2+1)*K2*K3
     DBuf<float2> twid;       // FFT twiddles of the three axes
     DBuf<double> inftab;     // T and S tables (FP64)
@@ -161,8 +163,13 @@ struct Ctx {
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
 
+    // --- second stream: the pair kernel overlaps the PME chain ---
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
     // --- phase timing ---
     bool timing = false;
+    bool serial = false;     // run the pair kernel on the main stream (phase timing mode 2)
     std::vector<hipEvent_t> ev_pool;          // free events
     std::vector<std::vector<hipEvent_t>> ev_pending;   // PQ_NPHASE*2 events per timed evaluation
 
