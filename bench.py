@@ -36,6 +36,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per pair-kernel launch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2503_21176_amd", "csrc", "pair.hip")
+    summ = os.path.join(ROOT, "profiles", "coulomb_300k_hbm_counters.md")
+    if not os.path.exists(summ):
+        return None
+    m = re.search(r"TRAFFIC k_pair<true> pair_hip_sha256_16=(\w+) bytes_per_launch=(\d+)", open(summ).read())
+    if not m:
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return int(m.group(2)) if sha == m.group(1) else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -46,6 +62,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -65,6 +83,14 @@ def main():
     a, rc, K, p = W.ALPHA_RC10, 10.0, 144, 6
     prm = P.make_params(s.box, rc, a, grid=K, order=p)
     pos, q, chi, eta = t(s.pos), t(s.q), t(s.chi), t(s.eta)
+
+    if args.calib_copy:
+        # a plain copy of known size: 256 MiB read + 256 MiB written
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     ctx = P.Context(0)
     # cold: neighbour build + one evaluation
@@ -113,7 +139,7 @@ def main():
     pair_s = phase_ms["pair"] / 1e3
     achieved = npairs * PAIR_FLOPS / pair_s
     roof = {"kernel": "k_pair<force>", "bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32, "traffic": measured_traffic(),
             "algorithmic_flops_per_launch": npairs * PAIR_FLOPS, "half_pairs": int(npairs),
             "avg_launch_ms": phase_ms["pair"]}
     log(f"[bench] pair kernel {phase_ms['pair']:.3f} ms, {npairs} half pairs, "
