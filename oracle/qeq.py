@@ -67,6 +67,62 @@ def coulomb_matrix(pos, box, coul: dict) -> np.ndarray:
     return 0.5 * (A + A.T)
 
 
+def coulomb_matrix_blocked(pos, box, coul: dict, chunk: int = 32) -> np.ndarray:
+    """The same A as coulomb_matrix, assembled term by term for larger N:
+    the real-space pair potentials erfc(a|d|)/|d| summed over images (the
+    terms of eq. ewald_real), the smooth-PME reciprocal potential of unit
+    charges computed for a block of columns at once (same steps as
+    spme_reciprocal), and the self and background terms on every entry."""
+    from .ewald import image_shifts, wrap
+    from .spme import _stencil, influence
+    from scipy.special import erfc
+    box = np.asarray(box, np.float64)
+    n = len(pos)
+    a, rc = coul["alpha"], coul["rc"]
+    w = wrap(np.asarray(pos, np.float64), box)
+    shifts = image_shifts(box, rc)
+    sL = shifts * box
+    zero = np.all(shifts == 0, axis=1)
+    A = np.zeros((n, n))
+    step = max(1, 2_000_000 // max(1, n * len(shifts)))
+    for s in range(0, n, step):
+        I = np.arange(s, min(n, s + step))
+        dd = (w[None, :, :] - w[I][:, None, :])[:, :, None, :] + sL[None, None, :, :]
+        r2 = dd[..., 0] * dd[..., 0] + dd[..., 1] * dd[..., 1] + dd[..., 2] * dd[..., 2]
+        mask = (r2 < rc * rc) & ~((I[:, None] == np.arange(n)[None, :])[:, :, None] & zero[None, None, :])
+        r = np.sqrt(np.where(mask, r2, 1.0))
+        A[I] = KE * np.where(mask, erfc(a * r) / r, 0.0).sum(2)
+    if coul["method"] == "ewald":
+        from .ewald import kvectors
+        _, k = kvectors(box, coul["kmax"])
+        k2 = np.sum(k * k, 1)
+        V = float(np.prod(box))
+        ck = 4.0 * np.pi / V * np.exp(-k2 / (4 * a * a)) / k2
+        ph = w @ k.T
+        C, S = np.cos(ph), np.sin(ph)
+        A += KE * ((C * ck) @ C.T + (S * ck) @ S.T)
+    else:
+        K = np.broadcast_to(np.asarray(coul["grid"]), (3,)).astype(int)
+        idx, W, _ = _stencil(pos, box, K, coul["order"])
+        flat = ((idx[:, 0, :, None, None] * K[1] + idx[:, 1, None, :, None]) * K[2]
+                + idx[:, 2, None, None, :]).reshape(n, -1)
+        wt = (W[:, 0, :, None, None] * W[:, 1, None, :, None] * W[:, 2, None, None, :]).reshape(n, -1)
+        G = influence(box, a, K, coul["order"])
+        nk = int(np.prod(K))
+        for j0 in range(0, n, chunk):
+            J = np.arange(j0, min(n, j0 + chunk))
+            Q = np.zeros((len(J), nk))
+            for t, j in enumerate(J):
+                Q[t] = np.bincount(flat[j], weights=wt[j], minlength=nk)
+            FQ = np.fft.fftn(Q.reshape(len(J), *K), axes=(1, 2, 3))
+            psi = np.real(np.fft.ifftn(G[None] * FQ, axes=(1, 2, 3))).reshape(len(J), nk) * nk
+            A[:, J] += np.einsum("ip,jip->ij", wt, psi[:, flat])   # G carries KE
+    V = float(np.prod(box))
+    A += -KE * np.pi / (V * a * a)
+    A[np.diag_indices(n)] += -KE * 2.0 * a / np.sqrt(np.pi)
+    return 0.5 * (A + A.T)
+
+
 # --------------------------------------------------------------------------
 # regular QEQ
 # --------------------------------------------------------------------------

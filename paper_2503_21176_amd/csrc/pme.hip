@@ -92,8 +92,24 @@ __global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const flo
     if (i >= n) return;
     int br = brick_of[i];
     int pos = brick_start[br] + atomicAdd(&brick_fill[br], 1);
-    pme_idx[pos] = i;
-    pme_frac[pos] = frac_tmp[i];
+    pme_idx[pos] = i;   // unordered within the brick; k_pme_order fixes the order
+    (void)frac_tmp;
+    (void)pme_frac;
+}
+
+// Deterministic order inside each brick (by atom index), so every
+// accumulation order, and hence every result, is reproducible bit for bit.
+__global__ void k_pme_order(int n, const int* __restrict__ brick_of, const int* __restrict__ brick_start,
+                            const int* __restrict__ unordered, const float4* __restrict__ frac_tmp,
+                            int* __restrict__ pme_idx, float4* __restrict__ pme_frac) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int br = brick_of[i];
+    const int s0 = brick_start[br], s1 = brick_start[br + 1];
+    int r = 0;
+    for (int k = s0; k < s1; ++k) r += unordered[k] < i;
+    pme_idx[s0 + r] = i;
+    pme_frac[s0 + r] = frac_tmp[i];
 }
 
 // B-spline weights of every atom (brick order), computed once per set of
@@ -343,7 +359,10 @@ void pme_setup(Ctx& c) {
     PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
     PQ_LAUNCH(k_pme_setup, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, c.f_k.p, c.brick_cnt.p);
     scan_ints(c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
+    c.tmp_atoms.ensure(n);
     PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.f_k.p, c.brick_start.p, c.brick_fill.p,
+              c.tmp_atoms.p, c.pme_frac.p);
+    PQ_LAUNCH(k_pme_order, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.tmp_atoms.p, c.f_k.p,
               c.pme_idx.p, c.pme_frac.p);
     c.pme_w.ensure((size_t)n * 24);
     switch (c.P) {

@@ -1,0 +1,113 @@
+"""Continuous-batching QEQ server: every result is the same alone and in the
+mix, and matches the dense FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import qeq as Q
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2503_21176_amd as P
+    P.load()
+    return P
+
+
+def requests():
+    out = []
+    for k, n in enumerate([64, 90, 150, 200, 300, 120, 500, 80, 256, 400]):
+        L = (n / 0.1) ** (1 / 3)
+        s = W.small_random(n, L, seed=500 + k)
+        # hardness above the largest pair coupling: a well-posed QEQ problem
+        s.eta = np.random.default_rng(900 + k).uniform(20.0, 25.0, n)
+        K = W.smooth_grid(L, 1.0, 5)
+        out.append((s, K))
+    return out
+
+
+def params(P, s, K):
+    return P.make_params(s.box, 9.0, W.ALPHA_RC9, grid=K, order=5)
+
+
+def test_alone_vs_mix_bitwise_and_oracle(P):
+    reqs = requests()
+    tol, restart = 1e-7, 50
+    # alone: one context, one request at a time
+    alone = []
+    ctx = P.Context(0)
+    for s, K in reqs:
+        ctx.set_system(torch.as_tensor(s.pos, device="cuda"), params(P, s, K))
+        r = ctx.qeq_solve(torch.as_tensor(s.chi, device="cuda"), torch.as_tensor(s.eta, device="cuda"),
+                          tol=tol, max_it=400, restart=restart, q0=torch.as_tensor(s.q, device="cuda"))
+        alone.append(r.q.cpu().numpy())
+    ctx.close()
+    # mix: all submitted at once to 4 slots, results polled in reverse order
+    srv = P.Server(0, slots=4, hbm_budget_bytes=8e9)
+    tickets = [srv.submit(s.pos, s.chi, s.eta, params(P, s, K), q0=s.q, tol=tol, max_it=400, restart=restart)
+               for s, K in reqs]
+    res = {tk: srv.poll(tk) for tk in reversed(tickets)}
+    srv.close()
+    for k, ((s, K), tk) in enumerate(zip(reqs, tickets)):
+        r = res[tk]
+        say(f"[serve] req {k} n={s.n} K={K} status={r['status']} its={r['iterations']} "
+            f"relres={r['rel_residual']:.2e} wait={1e3 * (r['t_start'] - r['t_submit']):.1f} ms "
+            f"run={1e3 * (r['t_done'] - r['t_start']):.1f} ms")
+        assert r["status"] == 0
+        assert r["t_submit"] <= r["t_start"] <= r["t_done"]
+        assert np.array_equal(r["q"], alone[k]), f"request {k} differs alone vs in the mix"
+    # oracle parity on three requests
+    for k in (0, 2, 5):
+        s, K = reqs[k]
+        coul = dict(method="pme", alpha=W.ALPHA_RC9, rc=9.0, grid=K, order=5)
+        A = Q.coulomb_matrix_blocked(s.pos, s.box, coul)
+        qd, _ = Q.qeq_dense(A, s.chi, s.eta, 0.0)
+        err = np.linalg.norm(res[tickets[k]]["q"] - qd) / np.linalg.norm(qd)
+        say(f"[serve] req {k} vs oracle {err:.2e}")
+        assert err < 1e-5
+
+
+def test_admission_by_memory_budget(P):
+    reqs = requests()[:4]
+    s, K = reqs[0]
+    # a budget below one request's footprint rejects it at submit
+    srv = P.Server(0, slots=2, hbm_budget_bytes=1e5)
+    with pytest.raises(P.PQError) as e:
+        srv.submit(s.pos, s.chi, s.eta, params(P, s, K))
+    assert e.value.code == -6
+    srv.close()
+    # a budget that fits one request at a time (each of these estimates
+    # 1.1-1.4 MB): requests run one after another
+    srv = P.Server(0, slots=4, hbm_budget_bytes=1.9e6)
+    tickets = [srv.submit(s.pos, s.chi, s.eta, params(P, s, K), tol=1e-6, max_it=300) for s, K in reqs]
+    res = [srv.poll(tk) for tk in tickets]
+    srv.close()
+    for a, b in zip(res, res[1:]):
+        say(f"[admission] done {a['t_done']:.4f} next start {b['t_start']:.4f}")
+        assert b["t_start"] >= a["t_done"] - 1e-6
+    assert all(r["status"] == 0 for r in res)
+
+
+def test_evaluations_are_bitwise_reproducible(P):
+    s = W.random_ionic(n=3000, seed=12, grid=None)
+    prm = P.make_params(s.box, 10.0, W.ALPHA_RC10, grid=32, order=6)
+    outs = []
+    for _ in range(2):
+        ctx = P.Context(0)
+        ctx.set_system(torch.as_tensor(s.pos, device="cuda"), prm)
+        for _ in range(2):
+            phi, F, E = ctx.coulomb(torch.as_tensor(s.q, device="cuda"))
+            outs.append((phi.cpu().numpy(), F.cpu().numpy(), E.cpu().numpy()))
+        ctx.close()
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))

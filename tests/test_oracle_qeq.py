@@ -124,3 +124,11 @@ def test_vjp_vs_finite_differences():
     assert np.abs(fdR - dR.reshape(-1)[idx]).max() < 1e-6 * max(1, np.abs(fdR).max())
     assert np.abs(G.central_difference(lambda c: loss(chi=c), s.chi, 1e-5, [0, 2]) - dchi[[0, 2]]).max() < 1e-8
     assert np.abs(G.central_difference(lambda u: loss(eta=u), s.eta, 1e-5, [3, 4]) - deta[[3, 4]]).max() < 1e-8
+
+
+def test_blocked_matrix_equals_column_by_column():
+    s = W.small_random(37, 7.5, seed=35)
+    for coul in (COUL, dict(method="pme", alpha=0.45, rc=7.0, grid=15, order=5)):
+        A1 = Q.coulomb_matrix(s.pos, s.box, coul)
+        A2 = Q.coulomb_matrix_blocked(s.pos, s.box, coul, chunk=8)
+        assert np.abs(A1 - A2).max() < 1e-10 * np.abs(A1).max()
