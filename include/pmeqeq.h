@@ -52,6 +52,15 @@ typedef enum pq_status {
 
 enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1 };
 
+/* pq_params.flags bits.
+ * PQ_FLAG_FP64: the per-atom bulk arithmetic (pair sum, spreading, FFT,
+ *   convolution, gathering, direct-Ewald phases) runs in FP64 instead of the
+ *   default FP32; every reduction is FP64 in both forms. The paper times
+ *   everything but the neighbour search in double precision (Section
+ *   "Performance"); this flag gives that form on the same kernels, for
+ *   callers that need relative accuracy well below 1e-6. */
+#define PQ_FLAG_FP64 1
+
 /* Parameters of one periodic system. The names follow the paper's problem
  * statement for smooth PME (Algorithm "Smooth PME", input line: positions,
  * charges, box, Ewald parameter, grid dimensions, spline order) and the
@@ -65,7 +74,7 @@ typedef struct pq_params {
     int32_t order;    /* PME B-spline order p, 3 <= p <= 8                             */
     int32_t kmax[3];  /* direct Ewald: k = 2 pi n / L over |n_d| <= kmax_d, 0..64     */
     int32_t method;   /* PQ_METHOD_PME (grid, order used) or PQ_METHOD_EWALD (kmax)   */
-    int32_t flags;    /* reserved, must be 0                                           */
+    int32_t flags;    /* 0 or PQ_FLAG_FP64; other bits are rejected (PQ_ERR_INVALID)  */
 } pq_params;
 
 /* Outcome of a Krylov solve (host struct filled by the library). */

@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 
 PQ_OK = 0
+FLAG_FP64 = 1
 PQ_WARN_NOT_CONVERGED = 1
 STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_ERR_BOX",
           -3: "PQ_ERR_CAPACITY", -4: "PQ_ERR_NOMEM", -5: "PQ_ERR_HIP", -6: "PQ_ERR_TOO_LARGE",
@@ -114,7 +115,10 @@ def coulomb_constant() -> float:
     return float(load().pq_coulomb_constant())
 
 
-def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, method="pme") -> Params:
+def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, method="pme",
+                fp64=False) -> Params:
+    """Parameters of one periodic system. ``fp64`` selects FP64 bulk arithmetic
+    (PQ_FLAG_FP64) instead of the default FP32 bulk with FP64 reductions."""
     p = Params()
     b = [float(x) for x in (box if hasattr(box, "__len__") else (box, box, box))]
     p.box[:] = b
@@ -130,7 +134,7 @@ def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, met
         p.method = METHOD_EWALD
     else:
         raise ValueError(method)
-    p.flags = 0
+    p.flags = FLAG_FP64 if fp64 else 0
     return p
 
 

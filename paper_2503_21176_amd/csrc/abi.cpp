@@ -41,7 +41,7 @@ static void validate(int64_t n, const pq_params* p) {
     PQ_REQUIRE(std::isfinite(p->cutoff) && p->cutoff > 0.0, PQ_ERR_INVALID, "cutoff must be > 0");
     PQ_REQUIRE(std::isfinite(p->skin) && p->skin >= 0.0, PQ_ERR_INVALID, "skin must be >= 0");
     PQ_REQUIRE(std::isfinite(p->alpha) && p->alpha > 0.0, PQ_ERR_INVALID, "alpha must be > 0");
-    PQ_REQUIRE(p->flags == 0, PQ_ERR_INVALID, "flags must be 0");
+    PQ_REQUIRE((p->flags & ~PQ_FLAG_FP64) == 0, PQ_ERR_INVALID, "unknown bits in flags");
     PQ_REQUIRE(p->method == PQ_METHOD_PME || p->method == PQ_METHOD_EWALD, PQ_ERR_INVALID, "unknown method");
     if (p->method == PQ_METHOD_PME) {
         PQ_REQUIRE(p->order >= 3 && p->order <= 8, PQ_ERR_INVALID, "order must be in 3..8");
@@ -58,10 +58,10 @@ static void validate(int64_t n, const pq_params* p) {
 
 void ensure_eval(Ctx& c) {
     const size_t n = (size_t)c.n;
-    c.phi_r.ensure(n);
-    c.phi_k.ensure(n);
-    c.f_r.ensure(n);
-    c.f_k.ensure(n);
+    c.phi_r.ensure(n * rsz(c));
+    c.phi_k.ensure(n * rsz(c));
+    c.f_r.ensure(n * 4 * rsz(c));
+    c.f_k.ensure(n * 4 * rsz(c));
     c.scal.ensure(64);
     // reduction partials: sized once for every reduction the solvers issue
     c.part.ensure((size_t)RED_BLOCKS * 520 + 4096);
@@ -116,18 +116,18 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     PQ_HIP(hipEventRecord(c.ev_fork, s));
     PQ_HIP(hipStreamWaitEvent(ps, c.ev_fork, 0));
     E.begin(PQ_PHASE_PAIR, ps);
-    pair_sum(c, fo, c.phi_r.p, c.f_r.p, ps);
+    pair_sum(c, fo, ps);
     E.end(PQ_PHASE_PAIR, ps);
     PQ_HIP(hipEventRecord(c.ev_join, ps));
     if (c.prm.method == PQ_METHOD_PME) {
-        pme_eval(c, q, fo, c.phi_k.p, c.f_k.p, E.ev.empty() ? nullptr : E.ev.data(), s);
+        pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s);
     } else {
         E.begin(PQ_PHASE_SPREAD);
         E.end(PQ_PHASE_SPREAD);
         E.begin(PQ_PHASE_FFT);
         E.end(PQ_PHASE_FFT);
         E.begin(PQ_PHASE_GATHER);
-        ewald_eval(c, q, fo, c.phi_k.p, c.f_k.p, s);
+        ewald_eval(c, q, fo, s);
         E.end(PQ_PHASE_GATHER);
     }
     PQ_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
@@ -214,6 +214,7 @@ pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_para
     c.have_system = false;
     c.n = n;
     c.prm = *prm;
+    c.fp64 = (prm->flags & PQ_FLAG_FP64) != 0;
     nbr_build(c, pos);
     if (prm->method == PQ_METHOD_PME)
         pme_setup(c);

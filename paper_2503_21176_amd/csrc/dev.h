@@ -45,6 +45,48 @@ __host__ __device__ __forceinline__ bool lex_positive(int n0, int n1, int n2) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Vector types of the bulk precision T (float: the production form, double:
+// the same kernels in FP64).
+template <class T>
+struct VecT;
+template <>
+struct VecT<float> {
+    using v2 = float2;
+    using v4 = float4;
+};
+template <>
+struct VecT<double> {
+    using v2 = double2;
+    using v4 = double4;
+};
+template <class T>
+using V2 = typename VecT<T>::v2;
+template <class T>
+using V4 = typename VecT<T>::v4;
+
+template <class T>
+__host__ __device__ __forceinline__ V4<T> mk4(T x, T y, T z, T w) {
+    V4<T> r;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.w = w;
+    return r;
+}
+template <class T>
+__host__ __device__ __forceinline__ V2<T> mk2(T x, T y) {
+    V2<T> r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+
+// A packed grid base index stored in the 4th component of a V4<T>.
+__device__ __forceinline__ float pack_base(int b, float) { return __int_as_float(b); }
+__device__ __forceinline__ double pack_base(int b, double) { return (double)b; }
+__device__ __forceinline__ int unpack_base(float w) { return __float_as_int(w); }
+__device__ __forceinline__ int unpack_base(double w) { return (int)w; }
+
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ int lanes_below(unsigned long long mask) {
     return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),

@@ -9,7 +9,8 @@
 //   phi_i = 2 sum_half c_k Re(exp(-i k.r_i) S(k))
 //   F_i   = 2 q_i sum_half c_k k Im(conj(S(k)) exp(i k.r_i))
 // Phases: k.r = 2 pi (n . s), s = r/L; the fractional part of n . s is taken
-// in FP64, then sin/cos of 2 pi f in FP32 (phase error ~2e-7 rad).
+// in FP64, then sin/cos of 2 pi f in the bulk precision T (FP32: phase error
+// ~2e-7 rad; FP64).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -27,8 +28,14 @@ __device__ __forceinline__ void phase(const int4 nk, double s0, double s1, doubl
     t -= rint(t);
     sincospif(2.0f * (float)t, &sn, &cs);
 }
+__device__ __forceinline__ void phase(const int4 nk, double s0, double s1, double s2, double& sn, double& cs) {
+    double t = (double)nk.x * s0 + (double)nk.y * s1 + (double)nk.z * s2;
+    t -= rint(t);
+    sincospi(2.0 * t, &sn, &cs);
+}
 
 // Structure factors: one thread per k vector, atoms staged through LDS.
+template <class T>
 __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __restrict__ kn,
                                                  const double* __restrict__ kc, const double* __restrict__ w64,
                                                  double inv0, double inv1, double inv2, const double* __restrict__ q,
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __r
         const int m = min(EW_TILE, n - j0);
         if (valid)
             for (int t = 0; t < m; ++t) {
-                float sn, cs;
+                T sn, cs;
                 phase(nv, s_s[3 * t], s_s[3 * t + 1], s_s[3 * t + 2], sn, cs);
                 re += s_q[t] * (double)cs;
                 im += s_q[t] * (double)sn;
@@ -69,13 +76,13 @@ __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __r
 }
 
 // Potentials and forces: one thread per atom, k vectors staged through LDS.
-template <bool FORCE>
+template <bool FORCE, class T>
 __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* __restrict__ kn,
                                                     const double* __restrict__ kc,
                                                     const double2* __restrict__ sfac, const double* __restrict__ w64,
                                                     double inv0, double inv1, double inv2,
-                                                    const double* __restrict__ q, float* __restrict__ phi_out,
-                                                    float4* __restrict__ f_out) {
+                                                    const double* __restrict__ q, T* __restrict__ phi_out,
+                                                    V4<T>* __restrict__ f_out) {
     __shared__ int4 s_n[EW_TILE];
     __shared__ double s_c[EW_TILE];
     __shared__ double2 s_S[EW_TILE];
@@ -99,7 +106,7 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* 
         const int m = min(EW_TILE, nk - k0);
         if (valid)
             for (int t = 0; t < m; ++t) {
-                float sn, cs;
+                T sn, cs;
                 const int4 nv = s_n[t];
                 phase(nv, s0, s1, s2, sn, cs);
                 const double2 S = s_S[t];
@@ -115,11 +122,11 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* 
         __syncthreads();
     }
     if (valid) {
-        phi_out[i] = (float)(2.0 * phi);
+        phi_out[i] = (T)(2.0 * phi);
         if (FORCE) {
             const double qi = q[i];
             const double f = 2.0 * qi * 2.0 * PI;
-            f_out[i] = make_float4((float)(f * g0 * inv0), (float)(f * g1 * inv1), (float)(f * g2 * inv2), 0.0f);
+            f_out[i] = mk4<T>((T)(f * g0 * inv0), (T)(f * g1 * inv1), (T)(f * g2 * inv2), T(0));
         }
     }
 }
@@ -158,26 +165,47 @@ void ewald_setup(Ctx& c) {
     }
 }
 
-// phi, f (original order, without KE); E_rec (without KE) into c.scal[1]
-void ewald_eval(Ctx& c, const double* q, bool force, float* phi, float4* f, hipStream_t s) {
+__global__ void k_zero_bytes(unsigned char* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+template <class T>
+static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
     const int n = (int)c.n;
     const double i0 = 1.0 / c.prm.box[0], i1 = 1.0 / c.prm.box[1], i2 = 1.0 / c.prm.box[2];
+    T* phi = as<T>(c.phi_k);
+    V4<T>* f = as<V4<T>>(c.f_k);
     if (c.nk == 0) {
-        PQ_HIP(hipMemsetAsync(phi, 0, sizeof(float) * n, s));
-        if (force) PQ_HIP(hipMemsetAsync(f, 0, sizeof(float4) * n, s));
-        PQ_HIP(hipMemsetAsync(c.scal.p + 1, 0, sizeof(double), s));
+        // no k vectors: the reciprocal part vanishes (fill kernels, no memsets,
+        // so the evaluation stays capturable in a graph)
+        const size_t nb = (size_t)n * sizeof(T);
+        PQ_LAUNCH(k_zero_bytes, std::max(1u, std::min(cdiv(nb, 256), 4096u)), 256, 0, s, c.phi_k.p, nb);
+        if (force) {
+            const size_t fb = (size_t)n * sizeof(V4<T>);
+            PQ_LAUNCH(k_zero_bytes, std::max(1u, std::min(cdiv(fb, 256), 4096u)), 256, 0, s, c.f_k.p, fb);
+        }
+        PQ_LAUNCH(k_zero_bytes, 1, 64, 0, s, reinterpret_cast<unsigned char*>(c.scal.p + 1), sizeof(double));
         return;
     }
     const int nb = cdiv(c.nk, EW_TILE);
     c.part.ensure(nb + 16);
-    PQ_LAUNCH(k_sfac, nb, EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.w64.p, i0, i1, i2, q, c.sfac.p, c.part.p);
+    PQ_LAUNCH(k_sfac<T>, nb, EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.w64.p, i0, i1, i2, q, c.sfac.p, c.part.p);
     PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.part.p, nb, c.scal.p + 1);
+    if (n == 0) return;
     if (force)
-        PQ_LAUNCH(k_kgather<true>, cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
-                  i1, i2, q, phi, f);
+        PQ_LAUNCH((k_kgather<true, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p,
+                  i0, i1, i2, q, phi, f);
     else
-        PQ_LAUNCH(k_kgather<false>, cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
-                  i1, i2, q, phi, f);
+        PQ_LAUNCH((k_kgather<false, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p,
+                  i0, i1, i2, q, phi, f);
+}
+
+// phi, f (original order, without KE) into c.phi_k, c.f_k; E_rec (without KE) into c.scal[1]
+void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s) {
+    if (c.fp64)
+        ewald_eval_t<double>(c, q, force, s);
+    else
+        ewald_eval_t<float>(c, q, force, s);
 }
 
 }  // namespace pq

@@ -109,10 +109,11 @@ __global__ void k_cluster_col(int ncol, const int* __restrict__ col_cl, int* __r
     for (int k = col_cl[c]; k < col_cl[c + 1]; ++k) cl_col[k] = c;
 }
 
-// Bounding box, reference point and FP32 offsets of each cluster.
+// Bounding box, reference point and offsets (bulk precision T) of each cluster.
+template <class T>
 __global__ void k_cluster(int ncl, const int* __restrict__ orig, const double* __restrict__ w64,
                           double* __restrict__ ref, double* __restrict__ lo, double* __restrict__ hi,
-                          float4* __restrict__ xyzq) {
+                          V4<T>* __restrict__ xyzq) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncl) return;
     double l[3] = {1e300, 1e300, 1e300}, h[3] = {-1e300, -1e300, -1e300};
@@ -135,16 +136,16 @@ __global__ void k_cluster(int ncl, const int* __restrict__ orig, const double* _
     for (int a = 0; a < CL; ++a) {
         size_t s = (size_t)c * CL + a;
         int i = orig[s];
-        float4 v;
+        V4<T> v;
         if (i >= 0) {
-            v.x = (float)(w64[3 * (size_t)i + 0] - r[0]);
-            v.y = (float)(w64[3 * (size_t)i + 1] - r[1]);
-            v.z = (float)(w64[3 * (size_t)i + 2] - r[2]);
+            v.x = (T)(w64[3 * (size_t)i + 0] - r[0]);
+            v.y = (T)(w64[3 * (size_t)i + 1] - r[1]);
+            v.z = (T)(w64[3 * (size_t)i + 2] - r[2]);
         } else {
             // padding: far from everything, zero charge
-            v.x = v.y = v.z = 1.0e4f;
+            v.x = v.y = v.z = (T)1.0e4;
         }
-        v.w = 0.0f;
+        v.w = (T)0;
         xyzq[s] = v;
     }
 }
@@ -156,12 +157,12 @@ __device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, do
 // Cluster-pair list: one wavefront per i-cluster; lanes scan the clusters of
 // each candidate column and every z image. FILL = false counts, FILL = true
 // writes at lstart[ic] in the same deterministic order.
-template <bool FILL>
+template <bool FILL, class T>
 __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
                                               const int* __restrict__ col_cl, const double* __restrict__ ref,
                                               const double* __restrict__ lo, const double* __restrict__ hi,
                                               int* __restrict__ lcount, const int* __restrict__ lstart,
-                                              int2* __restrict__ lj, float4* __restrict__ ls) {
+                                              int2* __restrict__ lj, V4<T>* __restrict__ ls) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
@@ -212,8 +213,8 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
                     if (FILL && pass) {
                         int pos = base + cnt + lanes_below(m);
                         lj[pos] = make_int2(jc, pack_img(nx, ny, nz));
-                        ls[pos] = make_float4((float)((rj0 + sx) - ri0), (float)((rj1 + sy) - ri1),
-                                              (float)((rj2 + sz) - ri2), 0.0f);
+                        ls[pos] = mk4<T>((T)((rj0 + sx) - ri0), (T)((rj1 + sy) - ri1), (T)((rj2 + sz) - ri2),
+                                         (T)0);
                     }
                     cnt += __popcll(m);
                 }
@@ -321,7 +322,7 @@ void nbr_build(Ctx& c, const double* pos) {
     const int ncl = c.ncl;
     const size_t nslot = (size_t)ncl * CL;
     c.orig.ensure(nslot);
-    c.xyzq.ensure(nslot);
+    c.xyzq.ensure(nslot * 4 * rsz(c));
     c.cl_ref.ensure((size_t)ncl * 3);
     c.cl_lo.ensure((size_t)ncl * 3);
     c.cl_hi.ensure((size_t)ncl * 3);
@@ -334,10 +335,14 @@ void nbr_build(Ctx& c, const double* pos) {
     PQ_LAUNCH(k_rank, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_cl.p, c.tmp_atoms.p,
               c.w64.p, c.orig.p);
     PQ_LAUNCH(k_cluster_col, cdiv(c.ncol, 256), 256, 0, s, c.ncol, c.col_cl.p, c.cl_col.p);
-    PQ_LAUNCH(k_cluster, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
-              c.cl_hi.p, c.xyzq.p);
-    PQ_LAUNCH(k_list<false>, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p, c.cl_lo.p,
-              c.cl_hi.p, c.lcount.p, (const int*)nullptr, (int2*)nullptr, (float4*)nullptr);
+    if (c.fp64)
+        PQ_LAUNCH(k_cluster<double>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
+                  c.cl_hi.p, as<double4>(c.xyzq));
+    else
+        PQ_LAUNCH(k_cluster<float>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
+                  c.cl_hi.p, as<float4>(c.xyzq));
+    PQ_LAUNCH((k_list<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
+              c.cl_lo.p, c.cl_hi.p, c.lcount.p, (const int*)nullptr, (int2*)nullptr, (float4*)nullptr);
     PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.lcount.p, c.lstart.p, ncl);
     int tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.lstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -345,9 +350,13 @@ void nbr_build(Ctx& c, const double* pos) {
     PQ_REQUIRE(tot >= 0, PQ_ERR_BOX, "cluster-pair list overflow");
     c.nlist = tot;
     c.lj.ensure(std::max(1, tot));
-    c.ls.ensure(std::max(1, tot));
-    PQ_LAUNCH(k_list<true>, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p, c.cl_lo.p,
-              c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, c.ls.p);
+    c.ls.ensure((size_t)std::max(1, tot) * 4 * rsz(c));
+    if (c.fp64)
+        PQ_LAUNCH((k_list<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
+                  c.cl_lo.p, c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, as<double4>(c.ls));
+    else
+        PQ_LAUNCH((k_list<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
+                  c.cl_lo.p, c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, as<float4>(c.ls));
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {

@@ -1,8 +1,9 @@
 // Smooth PME charge spreading and potential/force gathering
-// (Algorithm "Smooth PME", steps 1 and 5), FP32 bulk arithmetic.
+// (Algorithm "Smooth PME", steps 1 and 5). Bulk precision T: FP32 (the
+// production form) or FP64 (the same kernels instantiated in double).
 //
 // Atoms are sorted by the "brick" (B x B x B block of grid points) that holds
-// their base grid point floor(u). One workgroup owns one brick:
+// their base grid point floor(u), in atom-index order inside each brick.
 //  * spreading accumulates each brick's atoms into LDS copies of the brick
 //    plus its (p-1)-point halo (one atom per wavefront step, one stencil row
 //    per lane: conflict-free plain updates, no atomics), stores that region to
@@ -10,7 +11,6 @@
 //    regions that overlap it: deterministic, no clearing pass;
 //  * gathering stages the same region of the convolved grid in LDS and
 //    reads each atom's p^3 stencil from there.
-// Eight lanes serve one atom; lane y < p walks the (z, x) plane of stencil row y.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,32 +24,32 @@ constexpr int PME_B = 8;
 
 // Cardinal B-spline weights M_p(f + t), t = 0..P-1 (grid point base - t), and
 // their derivatives, by the Cox-de Boor recursion, f in [0, 1).
-template <int P>
-__device__ __forceinline__ void bspline(float f, float* w, float* dw) {
-    float m[P];
+template <int P, class T>
+__device__ __forceinline__ void bspline(T f, T* w, T* dw) {
+    T m[P];
 #pragma unroll
-    for (int t = 0; t < P; ++t) m[t] = 0.0f;
+    for (int t = 0; t < P; ++t) m[t] = T(0);
     m[0] = f;
-    m[1] = 1.0f - f;
+    m[1] = T(1) - f;
 #pragma unroll
     for (int k = 3; k <= P; ++k) {
         if (k == P) {
 #pragma unroll
-            for (int t = 0; t < P; ++t) dw[t] = m[t] - (t > 0 ? m[t - 1] : 0.0f);
+            for (int t = 0; t < P; ++t) dw[t] = m[t] - (t > 0 ? m[t - 1] : T(0));
         }
-        const float inv = 1.0f / (float)(k - 1);
-        m[k - 1] = (1.0f - f) * m[k - 2] * inv;
+        const T inv = T(1) / (T)(k - 1);
+        m[k - 1] = (T(1) - f) * m[k - 2] * inv;
 #pragma unroll
-        for (int t = k - 2; t >= 1; --t) m[t] = ((f + t) * m[t] + ((float)k - f - t) * m[t - 1]) * inv;
+        for (int t = k - 2; t >= 1; --t) m[t] = ((f + t) * m[t] + ((T)k - f - t) * m[t - 1]) * inv;
         m[0] = f * m[0] * inv;
     }
 #pragma unroll
     for (int t = 0; t < P; ++t) w[t] = m[t];
 }
 
-template <int P>
-__device__ __forceinline__ float pick(const float* v, int i) {
-    float r = 0.0f;
+template <int P, class T>
+__device__ __forceinline__ T pick(const T* v, int i) {
+    T r = T(0);
 #pragma unroll
     for (int t = 0; t < P; ++t) r = (t == i) ? v[t] : r;
     return r;
@@ -61,13 +61,14 @@ struct PmeGeo {
     double L[3], invL[3];
 };
 
+template <class T>
 __global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int* __restrict__ brick_of,
-                            float4* __restrict__ frac_tmp, int* __restrict__ brick_cnt) {
+                            V4<T>* __restrict__ frac_tmp, int* __restrict__ brick_cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int K[3] = {G.K0, G.K1, G.K2};
     int base[3];
-    float fr[3];
+    T fr[3];
     for (int d = 0; d < 3; ++d) {
         double u = (double)K[d] * (w64[3 * (size_t)i + d] * G.invL[d]);
         double fl = floor(u);
@@ -76,32 +77,29 @@ __global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int
         if (b >= K[d]) b -= K[d];
         if (b < 0) b += K[d];
         base[d] = b;
-        fr[d] = (float)f;
-        if (fr[d] >= 1.0f) fr[d] = 0.99999994f;
+        fr[d] = (T)f;
+        if (fr[d] >= T(1)) fr[d] = T(1) - T(1e-7);
     }
     int br = base[0] / PME_B + G.nb0 * (base[1] / PME_B + G.nb1 * (base[2] / PME_B));
     brick_of[i] = br;
-    frac_tmp[i] = make_float4(fr[0], fr[1], fr[2], __int_as_float(base[0] | (base[1] << 10) | (base[2] << 20)));
+    frac_tmp[i] = mk4<T>(fr[0], fr[1], fr[2], pack_base(base[0] | (base[1] << 10) | (base[2] << 20), T(0)));
     atomicAdd(&brick_cnt[br], 1);
 }
 
-__global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const float4* __restrict__ frac_tmp,
-                              const int* __restrict__ brick_start, int* __restrict__ brick_fill,
-                              int* __restrict__ pme_idx, float4* __restrict__ pme_frac) {
+__global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const int* __restrict__ brick_start,
+                              int* __restrict__ brick_fill, int* __restrict__ unordered) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int br = brick_of[i];
-    int pos = brick_start[br] + atomicAdd(&brick_fill[br], 1);
-    pme_idx[pos] = i;   // unordered within the brick; k_pme_order fixes the order
-    (void)frac_tmp;
-    (void)pme_frac;
+    unordered[brick_start[br] + atomicAdd(&brick_fill[br], 1)] = i;
 }
 
 // Deterministic order inside each brick (by atom index), so every
 // accumulation order, and hence every result, is reproducible bit for bit.
+template <class T>
 __global__ void k_pme_order(int n, const int* __restrict__ brick_of, const int* __restrict__ brick_start,
-                            const int* __restrict__ unordered, const float4* __restrict__ frac_tmp,
-                            int* __restrict__ pme_idx, float4* __restrict__ pme_frac) {
+                            const int* __restrict__ unordered, const V4<T>* __restrict__ frac_tmp,
+                            int* __restrict__ pme_idx, V4<T>* __restrict__ pme_frac) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int br = brick_of[i];
@@ -115,18 +113,18 @@ __global__ void k_pme_order(int n, const int* __restrict__ brick_of, const int* 
 // B-spline weights of every atom (brick order), computed once per set of
 // positions: pme_w[k] = {M_p(f_x + t)}_t, {M_p(f_y + t)}_t, {M_p(f_z + t)}_t,
 // each padded to 8 entries.
-template <int P>
-__global__ void k_pme_weights(int n, const float4* __restrict__ pme_frac, float* __restrict__ pme_w) {
+template <int P, class T>
+__global__ void k_pme_weights(int n, const V4<T>* __restrict__ pme_frac, T* __restrict__ pme_w) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const float4 f4 = pme_frac[k];
-    float w[P], dd[P];
-    float* out = pme_w + (size_t)k * 24;
-    const float fr[3] = {f4.x, f4.y, f4.z};
+    const V4<T> f4 = pme_frac[k];
+    T w[P], dd[P];
+    T* out = pme_w + (size_t)k * 24;
+    const T fr[3] = {f4.x, f4.y, f4.z};
     for (int d = 0; d < 3; ++d) {
-        bspline<P>(fr[d], w, dd);
+        bspline<P, T>(fr[d], w, dd);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) out[8 * d + t] = (t < P) ? w[t] : 0.0f;
+        for (int t = 0; t < 8; ++t) out[8 * d + t] = (t < P) ? w[t] : T(0);
     }
 }
 
@@ -138,49 +136,49 @@ __global__ void k_pme_weights(int n, const float4* __restrict__ pme_frac, float*
 // takes one atom per step, lane (y, z) updating stencil row (y, z): the
 // updates of one step hit distinct addresses, so plain read-modify-writes
 // replace atomics; the copies are summed at the end. No atomics at all.
-template <int P>
+template <int P, class T>
 __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __restrict__ brick_start,
                                                       const int* __restrict__ pme_idx,
-                                                      const float4* __restrict__ pme_frac,
-                                                      const float* __restrict__ pme_w,
-                                                      const double* __restrict__ q, float* __restrict__ stage) {
+                                                      const V4<T>* __restrict__ pme_frac,
+                                                      const T* __restrict__ pme_w, const double* __restrict__ q,
+                                                      T* __restrict__ stage) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
-    __shared__ float lds[4][R3];
+    __shared__ T lds[4][R3];
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
-    for (int t = threadIdx.x; t < 4 * R3; t += 256) (&lds[0][0])[t] = 0.0f;
+    for (int t = threadIdx.x; t < 4 * R3; t += 256) (&lds[0][0])[t] = T(0);
     __syncthreads();
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ty = lane & 7, tz = lane >> 3;
     const bool active = (ty < P) && (tz < P);
-    float* my = lds[wv];
+    T* my = lds[wv];
     for (int k = s0 + wv; k < s1; k += 4) {
-        const float4 f4 = pme_frac[k];
-        const float qq = (float)q[pme_idx[k]];
-        const float* wk = pme_w + (size_t)k * 24;
-        const int pk = __float_as_int(f4.w);
+        const V4<T> f4 = pme_frac[k];
+        const T qq = (T)q[pme_idx[k]];
+        const T* wk = pme_w + (size_t)k * 24;
+        const int pk = unpack_base(f4.w);
         const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
-        float wx[P];
+        T wx[P];
 #pragma unroll
         for (int t = 0; t < P; ++t) wx[t] = wk[t];
         if (active) {
-            const float c = qq * wk[8 + ty] * wk[16 + tz];
-            float* row = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
-            float v[P];
+            const T c = qq * wk[8 + ty] * wk[16 + tz];
+            T* row = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
+            T v[P];
 #pragma unroll
             for (int tx = 0; tx < P; ++tx) v[tx] = row[-tx];
 #pragma unroll
-            for (int tx = 0; tx < P; ++tx) row[-tx] = fmaf(c, wx[tx], v[tx]);
+            for (int tx = 0; tx < P; ++tx) row[-tx] = fma(c, wx[tx], v[tx]);
         }
         // the next atom may update the same rows
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
-    float* out = stage + (size_t)bid * R3;
+    T* out = stage + (size_t)bid * R3;
     for (int t = threadIdx.x; t < R3; t += 256) out[t] = (lds[0][t] + lds[1][t]) + (lds[2][t] + lds[3][t]);
 }
 
@@ -211,9 +209,8 @@ __device__ __forceinline__ int region_hits(int g, int K, int nb, int* bb, int* l
 
 // Spreading, pass 2: each grid point sums the staged regions that hold it
 // (fixed order: deterministic).
-template <int P>
-__global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const float* __restrict__ stage,
-                                                       float* __restrict__ grid) {
+template <int P, class T>
+__global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const T* __restrict__ stage, T* __restrict__ grid) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
     const size_t ng = (size_t)G.K0 * G.K1 * G.K2;
@@ -225,7 +222,7 @@ __global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const float* __
         const int nx = region_hits<P>(gx, G.K0, G.nb0, bx, lx);
         const int ny = region_hits<P>(gy, G.K1, G.nb1, by, ly);
         const int nz = region_hits<P>(gz, G.K2, G.nb2, bz, lz);
-        float v = 0.0f;
+        T v = T(0);
         for (int iz = 0; iz < nz; ++iz)
             for (int iy = 0; iy < ny; ++iy)
                 for (int ix = 0; ix < nx; ++ix) {
@@ -236,13 +233,17 @@ __global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const float* __
     }
 }
 
-template <int P, bool FORCE>
+// Gathering (step 5): phi_rec,i = sum_k W_i(k) psi(k) and
+// F_rec,i = -q_i sum_k grad W_i(k) psi(k), from an LDS copy of the brick's
+// region of the convolved grid; eight lanes per atom, lane y < p walks the
+// (z, x) plane of stencil row y.
+template <int P, bool FORCE, class T>
 __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
-                                                const int* __restrict__ pme_idx, const float4* __restrict__ pme_frac,
-                                                const double* __restrict__ q, const float* __restrict__ grid,
-                                                float* __restrict__ phi_out, float4* __restrict__ f_out) {
+                                                const int* __restrict__ pme_idx, const V4<T>* __restrict__ pme_frac,
+                                                const double* __restrict__ q, const T* __restrict__ grid,
+                                                T* __restrict__ phi_out, V4<T>* __restrict__ f_out) {
     constexpr int R = PME_B + P - 1;
-    __shared__ float lds[R * R * R];
+    __shared__ T lds[R * R * R];
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
@@ -261,41 +262,41 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
     }
     __syncthreads();
     const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
-    const float kx = (float)(G.K0 * G.invL[0]), ky = (float)(G.K1 * G.invL[1]), kz = (float)(G.K2 * G.invL[2]);
+    const T kx = (T)(G.K0 * G.invL[0]), ky = (T)(G.K1 * G.invL[1]), kz = (T)(G.K2 * G.invL[2]);
     // every group runs the same number of iterations so the shuffles see full groups
     const int iters = (s1 - s0 + 31) / 32;
     for (int it = 0; it < iters; ++it) {
         const int k = s0 + grp + 32 * it;
         const bool valid = k < s1;
-        float phi = 0.0f, gxs = 0.0f, gys = 0.0f, gzs = 0.0f;
+        T phi = 0, gxs = 0, gys = 0, gzs = 0;
         int i = -1;
         if (valid) {
-            const float4 f4 = pme_frac[k];
+            const V4<T> f4 = pme_frac[k];
             i = pme_idx[k];
-            const int pk = __float_as_int(f4.w);
+            const int pk = unpack_base(f4.w);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
-            float wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
-            bspline<P>(f4.x, wx, dx);
-            bspline<P>(f4.y, wy, dy);
-            bspline<P>(f4.z, wz, dz);
+            T wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
+            bspline<P, T>(f4.x, wx, dx);
+            bspline<P, T>(f4.y, wy, dy);
+            bspline<P, T>(f4.z, wz, dz);
             if (sub < P) {
                 const int ly = gy - sub - y0;
-                const float wys = pick<P>(wy, sub), dys = pick<P>(dy, sub);
+                const T wys = pick<P, T>(wy, sub), dys = pick<P, T>(dy, sub);
 #pragma unroll
                 for (int tz = 0; tz < P; ++tz) {
-                    const float* row = lds + ((gz - tz - z0) * R + ly) * R + (gx - x0);
-                    float s = 0.0f, sdx = 0.0f;
+                    const T* row = lds + ((gz - tz - z0) * R + ly) * R + (gx - x0);
+                    T s = 0, sdx = 0;
 #pragma unroll
                     for (int tx = 0; tx < P; ++tx) {
-                        const float v = row[-tx];
-                        s = fmaf(wx[tx], v, s);
-                        if (FORCE) sdx = fmaf(dx[tx], v, sdx);
+                        const T v = row[-tx];
+                        s = fma(wx[tx], v, s);
+                        if (FORCE) sdx = fma(dx[tx], v, sdx);
                     }
-                    phi = fmaf(wys * wz[tz], s, phi);
+                    phi = fma(wys * wz[tz], s, phi);
                     if (FORCE) {
-                        gxs = fmaf(wys * wz[tz], sdx, gxs);
-                        gys = fmaf(dys * wz[tz], s, gys);
-                        gzs = fmaf(wys * dz[tz], s, gzs);
+                        gxs = fma(wys * wz[tz], sdx, gxs);
+                        gys = fma(dys * wz[tz], s, gys);
+                        gzs = fma(wys * dz[tz], s, gzs);
                     }
                 }
             }
@@ -311,8 +312,8 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         if (valid && sub == 0) {
             phi_out[i] = phi;
             if (FORCE) {
-                const float qq = (float)q[i];
-                f_out[i] = make_float4(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, 0.0f);
+                const T qq = (T)q[i];
+                f_out[i] = mk4<T>(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, T(0));
             }
         }
     }
@@ -333,9 +334,37 @@ static PmeGeo geo(const Ctx& c) {
     return G;
 }
 
-void pme_setup(Ctx& c) {
+template <class T>
+static void pme_setup_t(Ctx& c) {
     const int n = (int)c.n;
     hipStream_t s = c.stream;
+    using v4 = V4<T>;
+    PmeGeo G = geo(c);
+    c.f_k.ensure((size_t)n * sizeof(v4));   // temporary for the unsorted fractional parts
+    c.pme_frac.ensure((size_t)n * sizeof(v4));
+    c.pme_w.ensure((size_t)n * 24 * sizeof(T));
+    c.tmp_atoms.ensure(n);
+    PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
+    PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
+    PQ_LAUNCH(k_pme_setup<T>, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, as<v4>(c.f_k), c.brick_cnt.p);
+    scan_ints(c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
+    PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.brick_fill.p,
+              c.tmp_atoms.p);
+    PQ_LAUNCH(k_pme_order<T>, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.tmp_atoms.p,
+              as<v4>(c.f_k), c.pme_idx.p, as<v4>(c.pme_frac));
+    switch (c.P) {
+        case 3: PQ_LAUNCH((k_pme_weights<3, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        case 4: PQ_LAUNCH((k_pme_weights<4, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        case 5: PQ_LAUNCH((k_pme_weights<5, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        case 6: PQ_LAUNCH((k_pme_weights<6, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        case 7: PQ_LAUNCH((k_pme_weights<7, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        case 8: PQ_LAUNCH((k_pme_weights<8, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
+        default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
+    }
+}
+
+void pme_setup(Ctx& c) {
+    const int n = (int)c.n;
     for (int d = 0; d < 3; ++d) {
         c.K[d] = c.prm.grid[d];
         c.nb[d] = (c.K[d] + PME_B - 1) / PME_B;
@@ -347,68 +376,60 @@ void pme_setup(Ctx& c) {
     c.brick_fill.ensure(c.nbrick);
     c.brick_start.ensure(c.nbrick + 1);
     c.pme_idx.ensure(n);
-    c.pme_frac.ensure(n);
-    c.f_k.ensure(n);   // temporary for the unsorted fractional parts
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
-    c.grid.ensure(ng);
+    c.grid.ensure(ng * rsz(c));
     const int R = PME_B + c.P - 1;
-    c.stage.ensure((size_t)c.nbrick * R * R * R);
-    c.spec.ensure((size_t)(c.K[0] / 2 + 1) * c.K[1] * c.K[2]);
-    PmeGeo G = geo(c);
-    PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
-    PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
-    PQ_LAUNCH(k_pme_setup, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, c.f_k.p, c.brick_cnt.p);
-    scan_ints(c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
-    c.tmp_atoms.ensure(n);
-    PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.f_k.p, c.brick_start.p, c.brick_fill.p,
-              c.tmp_atoms.p, c.pme_frac.p);
-    PQ_LAUNCH(k_pme_order, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.tmp_atoms.p, c.f_k.p,
-              c.pme_idx.p, c.pme_frac.p);
-    c.pme_w.ensure((size_t)n * 24);
-    switch (c.P) {
-        case 3: PQ_LAUNCH(k_pme_weights<3>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        case 4: PQ_LAUNCH(k_pme_weights<4>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        case 5: PQ_LAUNCH(k_pme_weights<5>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        case 6: PQ_LAUNCH(k_pme_weights<6>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        case 7: PQ_LAUNCH(k_pme_weights<7>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        case 8: PQ_LAUNCH(k_pme_weights<8>, cdiv(n, 256), 256, 0, s, n, c.pme_frac.p, c.pme_w.p); break;
-        default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
-    }
+    c.stage.ensure((size_t)c.nbrick * R * R * R * rsz(c));
+    c.spec.ensure((size_t)(c.K[0] / 2 + 1) * c.K[1] * c.K[2] * 2 * rsz(c));
+    if (c.fp64)
+        pme_setup_t<double>(c);
+    else
+        pme_setup_t<float>(c);
     fft_setup(c);
 }
 
-template <int P>
-static void pme_eval_p(Ctx& c, const double* q, bool force, float* phi, float4* f, hipEvent_t* ev, hipStream_t s) {
+template <int P, class T>
+static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
+    using v4 = V4<T>;
     PmeGeo G = geo(c);
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
-    PQ_LAUNCH(k_spread_stage<P>, c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, c.pme_frac.p, c.pme_w.p,
-              q, c.stage.p);
-    PQ_LAUNCH(k_spread_reduce<P>, std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, c.stage.p, c.grid.p);
+    PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
+              as<T>(c.pme_w), q, as<T>(c.stage));
+    PQ_LAUNCH((k_spread_reduce<P, T>), std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, as<T>(c.stage),
+              as<T>(c.grid));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT], s));
     fft_convolve(c, s);
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER], s));
     if (force)
-        PQ_LAUNCH((k_gather<P, true>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, c.pme_frac.p, q,
-                  c.grid.p, phi, f);
+        PQ_LAUNCH((k_gather<P, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
+                  q, as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     else
-        PQ_LAUNCH((k_gather<P, false>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, c.pme_frac.p, q,
-                  c.grid.p, phi, f);
+        PQ_LAUNCH((k_gather<P, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
+                  q, as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER + 1], s));
 }
 
-void pme_eval(Ctx& c, const double* q, bool force, float* phi, float4* f, hipEvent_t* ev, hipStream_t s) {
+template <class T>
+static void pme_eval_t(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
     switch (c.P) {
-        case 3: pme_eval_p<3>(c, q, force, phi, f, ev, s); break;
-        case 4: pme_eval_p<4>(c, q, force, phi, f, ev, s); break;
-        case 5: pme_eval_p<5>(c, q, force, phi, f, ev, s); break;
-        case 6: pme_eval_p<6>(c, q, force, phi, f, ev, s); break;
-        case 7: pme_eval_p<7>(c, q, force, phi, f, ev, s); break;
-        case 8: pme_eval_p<8>(c, q, force, phi, f, ev, s); break;
+        case 3: pme_eval_p<3, T>(c, q, force, ev, s); break;
+        case 4: pme_eval_p<4, T>(c, q, force, ev, s); break;
+        case 5: pme_eval_p<5, T>(c, q, force, ev, s); break;
+        case 6: pme_eval_p<6, T>(c, q, force, ev, s); break;
+        case 7: pme_eval_p<7, T>(c, q, force, ev, s); break;
+        case 8: pme_eval_p<8, T>(c, q, force, ev, s); break;
         default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
     }
+}
+
+void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
+    if (c.fp64)
+        pme_eval_t<double>(c, q, force, ev, s);
+    else
+        pme_eval_t<float>(c, q, force, ev, s);
 }
 
 }  // namespace pq

@@ -93,7 +93,7 @@ struct Fft1D {
     int radix[FFT_MAX_STAGES];
     int ns[FFT_MAX_STAGES];     // product of the radices of earlier stages
     int twoff[FFT_MAX_STAGES];  // offset of the stage's twiddles in the table
-    const float2* tw = nullptr; // exp(-2 pi i k r / (ns*R)) for k < ns, 1 <= r < R
+    const void* tw = nullptr;   // V2<T> exp(-2 pi i k r / (ns*R)) for k < ns, 1 <= r < R
 };
 
 // Per-axis influence-function tables (without KE and 1/(pi V)):
@@ -108,6 +108,7 @@ struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool have_system = false;
+    bool fp64 = false;       // bulk arithmetic in FP64 (PQ_FLAG_FP64) instead of FP32
     int64_t n = 0;
     pq_params prm{};
     Geom g{};
@@ -123,7 +124,7 @@ struct Ctx {
     DBuf<int> col_cl;        // ncol+1, cluster offsets per column
     DBuf<int> tmp_atoms;     // atoms grouped by column, unordered
     DBuf<int> orig;          // slot -> original atom (-1 padding), ncl*8
-    DBuf<float4> xyzq;       // slot-ordered FP32 offsets from the cluster reference + charge
+    DBuf<unsigned char> xyzq; // slot-ordered V4<T>: offset from the cluster reference + charge
     DBuf<double> cl_ref;     // ncl*3 reference points
     DBuf<double> cl_lo;      // ncl*3 bounding boxes
     DBuf<double> cl_hi;
@@ -131,7 +132,7 @@ struct Ctx {
     DBuf<int> lcount;        // ncl+1
     DBuf<int> lstart;        // ncl+1
     DBuf<int2> lj;           // list: (j cluster, packed image vector)
-    DBuf<float4> ls;         // list: FP32 shift ref_j + nL - ref_i
+    DBuf<unsigned char> ls;   // list: V4<T> shift ref_j + nL - ref_i
     DBuf<int> flag;          // device error flags
     DBuf<unsigned long long> counter;
 
@@ -140,12 +141,12 @@ struct Ctx {
     int nb[3] = {0, 0, 0}, nbrick = 0;
     DBuf<int> brick_of, brick_cnt, brick_start, brick_fill;
     DBuf<int> pme_idx;       // brick-ordered original indices
-    DBuf<float4> pme_frac;   // fractional parts + packed base index
-    DBuf<float> pme_w;       // B-spline weights per atom, 3 x 8 (brick order)
-    DBuf<float> grid;        // real grid K1*K2*K3 (x fastest)
-    DBuf<float> stage;       // per-brick spreading regions (B+p-1)^3
-    DBuf<float2> spec;       // half spectrum (K1/2+1)*K2*K3
-    DBuf<float2> twid;       // FFT twiddles of the three axes
+    DBuf<unsigned char> pme_frac; // V4<T>: fractional parts + packed base index
+    DBuf<unsigned char> pme_w;    // T: B-spline weights per atom, 3 x 8 (brick order)
+    DBuf<unsigned char> grid;     // T: real grid K1*K2*K3 (x fastest)
+    DBuf<unsigned char> stage;    // T: per-brick spreading regions (B+p-1)^3
+    DBuf<unsigned char> spec;     // V2<T>: half spectrum (K1/2+1)*K2*K3
+    DBuf<unsigned char> twid;     // V2<T>: FFT twiddles of the three axes
     DBuf<double> inftab;     // T and S tables (FP64)
     Fft1D fft[3];
     InfTab inf{};
@@ -157,8 +158,8 @@ struct Ctx {
     DBuf<double2> sfac;      // structure factors
 
     // --- per-evaluation scratch ---
-    DBuf<float> phi_r, phi_k;
-    DBuf<float4> f_r, f_k;
+    DBuf<unsigned char> phi_r, phi_k;   // T per atom (original order, without KE)
+    DBuf<unsigned char> f_r, f_k;       // V4<T> per atom
     DBuf<double> part;       // reduction partials
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
@@ -184,6 +185,14 @@ struct Ctx {
     ~Ctx();
 };
 
+// Typed view of a precision-dependent byte buffer.
+template <class X>
+inline X* as(DBuf<unsigned char>& b) {
+    return reinterpret_cast<X*>(b.p);
+}
+// Bytes of one bulk real number (4: FP32 form, 8: FP64 form).
+inline size_t rsz(const Ctx& c) { return c.fp64 ? 8 : 4; }
+
 // ---------------------------------------------------------------------------
 // launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
@@ -193,17 +202,17 @@ void nbr_build(Ctx& c, const double* pos);
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs);
 // pair.hip: outputs in original atom order, without KE; force includes q_i
 void stage_charges(Ctx& c, const double* q, hipStream_t s);
-void pair_sum(Ctx& c, bool force, float* phi, float4* f, hipStream_t s);
+void pair_sum(Ctx& c, bool force, hipStream_t s);   // into c.phi_r, c.f_r
 // pme.hip
 void pme_setup(Ctx& c);
 // ev: 2*PQ_NPHASE timing events or NULL (spread, FFT and gather phases are recorded)
-void pme_eval(Ctx& c, const double* q, bool force, float* phi, float4* f, hipEvent_t* ev, hipStream_t s);
+void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s);   // into c.phi_k, c.f_k
 // fft.hip
 void fft_setup(Ctx& c);
 void fft_convolve(Ctx& c, hipStream_t s);   // grid -> psi in place; energy partials into c.part
 // ewald.hip
 void ewald_setup(Ctx& c);
-void ewald_eval(Ctx& c, const double* q, bool force, float* phi, float4* f, hipStream_t s);
+void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s);   // into c.phi_k, c.f_k
 // vec.hip
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s);
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s);

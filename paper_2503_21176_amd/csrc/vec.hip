@@ -59,9 +59,10 @@ void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out
 // ---- energy assembly --------------------------------------------------------
 // phi_i = KE (phi_real + phi_rec + self_i + background), F_i = KE (F_real + F_rec)
 // part: 3 partial sums per block of q_i * (real, rec, self+bg) potentials.
+template <class T>
 __global__ __launch_bounds__(VB) void k_combine(int64_t n, const double* __restrict__ q, const double* __restrict__ Q,
-                                                const float* __restrict__ pr, const float4* __restrict__ fr,
-                                                const float* __restrict__ pk, const float4* __restrict__ fk,
+                                                const T* __restrict__ pr, const V4<T>* __restrict__ fr,
+                                                const T* __restrict__ pk, const V4<T>* __restrict__ fk,
                                                 double cself, double cbg, double* __restrict__ phi,
                                                 double* __restrict__ force, double* __restrict__ part) {
     __shared__ double red[VB / 64];
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(VB) void k_combine(int64_t n, const double* __restr
         const double sb = KE * (cself * qi + cbg * Qs);
         if (phi) phi[i] = (a + b) + sb;
         if (force) {
-            const float4 x = fr[i], y = fk[i];
+            const V4<T> x = fr[i], y = fk[i];
             force[3 * i + 0] = KE * ((double)x.x + (double)y.x);
             force[3 * i + 1] = KE * ((double)x.y + (double)y.y);
             force[3 * i + 2] = KE * ((double)x.z + (double)y.z);
@@ -120,8 +121,12 @@ void combine(Ctx& c, const double* q, const double* Q, double* phi, double* forc
     const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
     const double cself = -2.0 * a / std::sqrt(PI);
     const double cbg = -PI / (V * a * a);
-    PQ_LAUNCH(k_combine, nb, VB, 0, s, n, q, Q, c.phi_r.p, c.f_r.p, c.phi_k.p, c.f_k.p, cself, cbg, phi, force,
-              c.part.p);
+    if (c.fp64)
+        PQ_LAUNCH(k_combine<double>, nb, VB, 0, s, n, q, Q, as<double>(c.phi_r), as<double4>(c.f_r),
+                  as<double>(c.phi_k), as<double4>(c.f_k), cself, cbg, phi, force, c.part.p);
+    else
+        PQ_LAUNCH(k_combine<float>, nb, VB, 0, s, n, q, Q, as<float>(c.phi_r), as<float4>(c.f_r), as<float>(c.phi_k),
+                  as<float4>(c.f_k), cself, cbg, phi, force, c.part.p);
     if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.part.p, nb, c.scal.p + 1, energy);
 }
 
