@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define PQ_ABI_VERSION 1
+#define PQ_ABI_VERSION 2
 
 typedef enum pq_status {
     PQ_OK = 0,
@@ -176,7 +176,12 @@ pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count);
  *   chi, eta (= u): device n FP64; q0: device n FP64 start vector or NULL (0);
  *   q: device n FP64 output; force: device n*3 FP64 output F = -dE/dR at the
  *   solution, or NULL; energy: device FP64[1] output E(q), or NULL;
- *   info: host, may be NULL. Host-synchronising (convergence checks). */
+ *   info: host, may be NULL. Host-synchronising (convergence checks).
+ * Each Arnoldi step (operator product, orthogonalisation, Givens update) is
+ * one launch of a HIP graph that the context builds at its first solve of a
+ * system and reuses across restarts and calls; the host reads the residual
+ * estimate of step j - 1 while step j runs, so a solve may execute one
+ * product beyond the step it converges at (counted in info->iterations). */
 pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot,
                        double tol, int max_it, int restart, const double* q0,
                        double* q, double* force, double* energy, pq_solve_info* info);
@@ -188,7 +193,8 @@ pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double
  *   computed as F[q] - F[q - n]; and the n_krylov-step GMRES iterate x from
  *   x0 = 0 for J x = -(q[n] - n) (eq. Jnddot with omega^2 = 1),
  *   J = -I - P D^-1 A, P = I - D^-1 1 1^T / (1^T D^-1 1), D = diag(u).
- * Fixed work: 1 potential + 2 force evaluations + n_krylov products; no host
+ * Fixed work: 1 potential + 2 force evaluations + n_krylov products (each
+ * Krylov step one graph launch, as in pq_qeq_solve); no host
  * synchronisation. Outputs (device FP64): q_n[n], force[n*3] (may be NULL),
  * nddot[n] (may be NULL), energy[2] = {shadow energy, lambda} (may be NULL). */
 pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, double q_tot,
@@ -207,13 +213,37 @@ pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const do
                      const double* gbar, double tol, int max_it,
                      double* d_pos, double* d_chi, double* d_eta);
 
+/* ---- autotuning ------------------------------------------------------------ */
+/* Launch shape of the real-space pair kernel: 0 runs one wavefront per
+ * i-cluster (every cluster in flight at once); k > 0 runs k workgroups per CU
+ * that stride over the clusters, leaving LDS and wave slots of every CU to the
+ * reciprocal-space kernels that run concurrently on the context's other
+ * stream. Every shape gives bitwise-identical results. */
+typedef struct pq_tune_result {
+    int32_t pair_wg_per_cu;   /* chosen shape (0 or workgroups per CU)                 */
+    int32_t candidates;       /* shapes timed                                          */
+    double ms;                /* mean phi+F evaluation time of the chosen shape, ms    */
+    double ms_default;        /* the same for shape 0                                  */
+} pq_tune_result;
+
+/* Times the pair-kernel shapes 0, 1, 2, 3, 4, 6, 8 on `reps` (1..1000)
+ * potential + force evaluations each, after one warm-up, of the current system
+ * with charges q (device, n), and keeps the fastest for this context (also
+ * across later pq_set_system calls). Phase timing must be off. Host-
+ * synchronising; out may be NULL. */
+pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out);
+/* Applies a stored choice (only pair_wg_per_cu is read; 0..64). */
+pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
+
 /* ---- continuous-batching QEQ server -------------------------------------- */
-/* A server owns `slots` contexts, each with its own HIP stream, on one
- * device, and a scheduler thread. Submitted requests wait in FIFO order and
- * are admitted when a slot is free and their estimated device-memory
- * footprint fits the remaining budget; admitted requests advance one GMRES
- * iteration per scheduler turn, so their kernels overlap on the device and new
- * requests join while others are still running. */
+/* A server owns `slots` contexts on one device, each with its own HIP stream
+ * and worker thread, and a scheduler thread. Submitted requests wait in FIFO
+ * order and are admitted when a slot is free and their estimated
+ * device-memory footprint fits the remaining budget; each admitted request
+ * runs its neighbour build and GMRES solve on its slot's stream, so the
+ * kernels of all admitted requests overlap on the device and new requests
+ * start as soon as earlier ones release a slot and memory. Slots launch their
+ * kernels directly (no Arnoldi-step graphs). */
 typedef struct pq_server pq_server;
 
 typedef struct pq_server_cfg {
@@ -243,6 +273,7 @@ typedef struct pq_result {
     pq_solve_info info;
     int32_t status;           /* pq_status of the solve */
     double t_submit_s, t_start_s, t_done_s;   /* server clock, seconds */
+    char message[256];        /* for an error status: what failed (NUL-terminated) */
 } pq_result;
 
 pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg);
@@ -255,6 +286,11 @@ pq_status pq_server_submit(pq_server* s, const pq_request* req, uint64_t* ticket
 pq_status pq_server_poll(pq_server* s, uint64_t ticket, pq_result* res, int64_t timeout_us);
 /* Stops the scheduler after the requests already submitted complete. */
 pq_status pq_server_destroy(pq_server* s);
+/* The footprint in bytes that admission charges for a request of n atoms with
+ * these parameters and GMRES restart length (an estimate of the device memory
+ * it holds while running: neighbour lists, per-atom arrays, PME grids, Krylov
+ * basis). -1 for invalid arguments. Host only, no device call. */
+double pq_request_footprint(int64_t n, const pq_params* params, int32_t restart);
 
 #ifdef __cplusplus
 }

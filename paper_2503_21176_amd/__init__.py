@@ -17,6 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 
+ABI_VERSION = 2
 PQ_OK = 0
 FLAG_FP64 = 1
 PQ_WARN_NOT_CONVERGED = 1
@@ -28,7 +29,7 @@ METHOD_PME, METHOD_EWALD = 0, 1
 EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create", "pq_set_stream",
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
-           "pq_server_poll", "pq_server_destroy"]
+           "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -49,6 +50,11 @@ class SolveInfo(ctypes.Structure):
                 ("rel_residual", ctypes.c_double), ("lambda_", ctypes.c_double)]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("pair_wg_per_cu", ctypes.c_int32), ("candidates", ctypes.c_int32), ("ms", ctypes.c_double),
+                ("ms_default", ctypes.c_double)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_double)]
 
@@ -63,7 +69,7 @@ class Request(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("q", ctypes.c_void_p), ("energy", ctypes.c_double), ("info", SolveInfo),
                 ("status", ctypes.c_int32), ("t_submit_s", ctypes.c_double), ("t_start_s", ctypes.c_double),
-                ("t_done_s", ctypes.c_double)]
+                ("t_done_s", ctypes.c_double), ("message", ctypes.c_char * 256)]
 
 
 _lib = None
@@ -97,10 +103,15 @@ def load() -> ctypes.CDLL:
         "pq_server_submit": (i32, [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
         "pq_server_poll": (i32, [vp, ctypes.c_uint64, ctypes.POINTER(Result), i64]),
         "pq_server_destroy": (i32, [vp]),
+        "pq_request_footprint": (dbl, [i64, ctypes.POINTER(Params), i32]),
+        "pq_autotune": (i32, [vp, vp, i32, ctypes.POINTER(TuneResult)]),
+        "pq_set_tuning": (i32, [vp, ctypes.POINTER(TuneResult)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype, f.argtypes = res, args
+    if L.pq_abi_version() != ABI_VERSION:
+        raise RuntimeError(f"{LIB_PATH} has ABI version {L.pq_abi_version()}, the binding expects {ABI_VERSION}")
     _lib = L
     return L
 
@@ -213,6 +224,19 @@ class Context:
         _check(self.lib.pq_neighbor_pairs(self.h, cnt.value, _ptr(out), ctypes.byref(cnt)))
         return out[:cnt.value]
 
+    def autotune(self, q, reps: int = 5) -> dict:
+        """Times the pair kernel's launch shapes on phi+F evaluations with
+        charges q and keeps the fastest for this context."""
+        self._sync_stream()
+        q = self._vec(q, self.n, "q")
+        t = TuneResult()
+        _check(self.lib.pq_autotune(self.h, _ptr(q), int(reps), ctypes.byref(t)))
+        return dict(pair_wg_per_cu=t.pair_wg_per_cu, candidates=t.candidates, ms=t.ms, ms_default=t.ms_default)
+
+    def set_tuning(self, pair_wg_per_cu: int):
+        t = TuneResult(int(pair_wg_per_cu), 0, 0.0, 0.0)
+        _check(self.lib.pq_set_tuning(self.h, ctypes.byref(t)))
+
     def set_timing(self, mode=1):
         """0 off, 1 phase events (phases overlap as in production), 2 phases serialised."""
         _check(self.lib.pq_set_timing(self.h, int(mode)))
@@ -310,6 +334,14 @@ class QEQCharges(torch.autograd.Function):
         return dpos, dchi, deta, None, None, None
 
 
+def request_footprint(n: int, params: Params, restart: int = 50) -> float:
+    """Device bytes that server admission charges for such a request."""
+    v = load().pq_request_footprint(int(n), ctypes.byref(params), int(restart))
+    if v < 0:
+        raise ValueError("invalid request")
+    return float(v)
+
+
 class Server:
     """Continuous-batching QEQ server (host arrays in, host charges out)."""
 
@@ -346,7 +378,8 @@ class Server:
         _check(code)
         del self._keep[ticket]
         return dict(q=q, energy=res.energy, iterations=res.info.iterations, rel_residual=res.info.rel_residual,
-                    status=res.status, t_submit=res.t_submit_s, t_start=res.t_start_s, t_done=res.t_done_s)
+                    status=res.status, t_submit=res.t_submit_s, t_start=res.t_start_s, t_done=res.t_done_s,
+                    message=res.message.decode(errors="replace"))
 
     def close(self):
         if getattr(self, "h", None):

@@ -13,10 +13,20 @@ namespace pq {
 
 thread_local std::string g_err;
 
+std::recursive_mutex& device_mem_lock() {
+    static std::recursive_mutex m;
+    return m;
+}
+
 void set_error(const std::string& m) { g_err = m; }
 
 Ctx::~Ctx() {
+    std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
     if (side) (void)hipStreamSynchronize(side);
+    if (kgraph) (void)hipGraphExecDestroy(kgraph);
+    for (auto e : kev)
+        if (e) (void)hipEventDestroy(e);
+    if (pinned_hist) (void)hipHostFree(pinned_hist);
     if (pinned) (void)hipHostFree(pinned);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (ev_join) (void)hipEventDestroy(ev_join);
@@ -95,6 +105,13 @@ struct PhaseEvents {
     }
 };
 
+void ensure_side(Ctx& c) {
+    if (c.side) return;
+    PQ_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+    PQ_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+    PQ_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+}
+
 void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s) {
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     ensure_eval(c);
@@ -107,18 +124,14 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     E.end(PQ_PHASE_STAGE);
     // the real-space pair kernel (ALU bound) runs on the context's second
     // stream, concurrently with the memory-bound reciprocal-space chain
-    if (!c.side) {
-        PQ_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
-        PQ_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
-        PQ_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
-    }
+    ensure_side(c);
     hipStream_t ps = c.serial ? s : c.side;
-    PQ_HIP(hipEventRecord(c.ev_fork, s));
-    PQ_HIP(hipStreamWaitEvent(ps, c.ev_fork, 0));
+    ev_record(c.ev_fork, s);
+    stream_wait(ps, c.ev_fork);
     E.begin(PQ_PHASE_PAIR, ps);
     pair_sum(c, fo, ps);
     E.end(PQ_PHASE_PAIR, ps);
-    PQ_HIP(hipEventRecord(c.ev_join, ps));
+    ev_record(c.ev_join, ps);
     if (c.prm.method == PQ_METHOD_PME) {
         pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s);
     } else {
@@ -130,7 +143,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
         ewald_eval(c, q, fo, s);
         E.end(PQ_PHASE_GATHER);
     }
-    PQ_HIP(hipStreamWaitEvent(s, c.ev_join, 0));
+    stream_wait(s, c.ev_join);
     E.begin(PQ_PHASE_COMBINE);
     combine(c, q, c.scal.p + 0, phi, force, energy, s);
     E.end(PQ_PHASE_COMBINE);
@@ -177,6 +190,7 @@ pq_status pq_create(pq_ctx** out, int device, void* stream) {
     Ctx* c = new Ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
     if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete c;
         throw Error(PQ_ERR_NOMEM, "pinned host allocation failed");
@@ -212,6 +226,7 @@ pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_para
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
     PQ_HIP(hipSetDevice(c.device));
     c.have_system = false;
+    ++c.gen;
     c.n = n;
     c.prm = *prm;
     c.fp64 = (prm->flags & PQ_FLAG_FP64) != 0;
@@ -239,6 +254,77 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
         set_error("pair buffer too small: " + std::to_string(tot) + " pairs");
         return PQ_ERR_CAPACITY;
     }
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx and q must not be NULL");
+    PQ_REQUIRE(reps >= 1 && reps <= 1000, PQ_ERR_INVALID, "reps must be in 1..1000");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_REQUIRE(!c.timing, PQ_ERR_STATE, "phase timing must be off while tuning");
+    PQ_HIP(hipSetDevice(c.device));
+    int ncu = 0;
+    PQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+    hipStream_t s = c.stream;
+    const size_t n = (size_t)c.n;
+    DBuf<double> phi, f, e;
+    phi.ensure(n);
+    f.ensure(3 * n);
+    e.ensure(4);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PQ_HIP(hipEventCreate(&e0));
+    PQ_HIP(hipEventCreate(&e1));
+    const int cand[] = {0, 1, 2, 3, 4, 6, 8};
+    int best = 0;
+    double best_ms = 1e300, ms0 = 0.0;
+    try {
+        for (int k : cand) {
+            c.pair_grid = k * ncu;
+            coulomb_eval(c, q, phi.p, f.p, e.p, s);
+            PQ_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) coulomb_eval(c, q, phi.p, f.p, e.p, s);
+            PQ_HIP(hipEventRecord(e1, s));
+            PQ_HIP(hipEventSynchronize(e1));
+            float el = 0.f;
+            PQ_HIP(hipEventElapsedTime(&el, e0, e1));
+            const double ms = (double)el / reps;
+            if (k == 0) ms0 = ms;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = k;
+            }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c.pair_grid = best * ncu;
+    c.tune_ms = best_ms;
+    if (out) {
+        out->pair_wg_per_cu = best;
+        out->candidates = (int32_t)(sizeof(cand) / sizeof(cand[0]));
+        out->ms = best_ms;
+        out->ms_default = ms0;
+    }
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && t != nullptr, PQ_ERR_INVALID, "ctx and t must not be NULL");
+    PQ_REQUIRE(t->pair_wg_per_cu >= 0 && t->pair_wg_per_cu <= 64, PQ_ERR_INVALID, "pair_wg_per_cu must be in 0..64");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_HIP(hipSetDevice(c.device));
+    int ncu = 0;
+    PQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));
+    c.pair_grid = t->pair_wg_per_cu * ncu;
     return PQ_OK;
     PQ_API_END
 }

@@ -81,11 +81,12 @@ __host__ __device__ __forceinline__ V2<T> mk2(T x, T y) {
     return r;
 }
 
-// A packed grid base index stored in the 4th component of a V4<T>.
-__device__ __forceinline__ float pack_base(int b, float) { return __int_as_float(b); }
-__device__ __forceinline__ double pack_base(int b, double) { return (double)b; }
-__device__ __forceinline__ int unpack_base(float w) { return __float_as_int(w); }
-__device__ __forceinline__ int unpack_base(double w) { return (int)w; }
+// An integer (packed grid base index, atom slot) stored in the 4th component
+// of a V4<T>: the bit pattern in FP32, the value in FP64 (exact below 2^53).
+__device__ __forceinline__ float pack_int(int b, float) { return __int_as_float(b); }
+__device__ __forceinline__ double pack_int(int b, double) { return (double)b; }
+__device__ __forceinline__ int unpack_int(float w) { return __float_as_int(w); }
+__device__ __forceinline__ int unpack_int(double w) { return (int)w; }
 
 // Number of set bits of `mask` below this lane.
 __device__ __forceinline__ int lanes_below(unsigned long long mask) {

@@ -23,7 +23,7 @@ namespace {
 size_t round_ld(int64_t n) { return (size_t)((n + 63) / 64 * 64); }
 
 // Work vectors of the solvers (each ld doubles).
-enum { W_B = 0, W_X, W_R, W_W, W_T, W_PHI, W_PHI2, W_D, W_N };
+enum { W_B = 0, W_X, W_R, W_W, W_T, W_PHI, W_PHI2, W_D, W_VJ, W_N };
 
 struct Work {
     Ctx& c;
@@ -58,18 +58,86 @@ double read_scalar(Ctx& c, const double* dev, hipStream_t s) {
     return c.pinned[0];
 }
 
-// GMRES(m) for A x = b with vectors of length nv, x in/out (x_zero: x = 0 on
-// entry). fixed: exactly m products from x = 0, no host synchronisation.
-GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, bool x_zero, double tol, int max_it,
-               bool fixed) {
+// One Arnoldi step at the device step index j = *kj: w = A V_j, CGS2 against
+// V_0..V_j, V_{j+1} = w / |w|, Givens update of Hessenberg column j (|g[j+1]|
+// into hist[j]), then j + 1. The kernels take j from device memory, so one
+// captured step serves every iteration of a cycle.
+void arnoldi_step(Work& W, const OpFn& op, int64_t nv) {
     Ctx& c = W.c;
     hipStream_t s = c.stream;
     const int m = W.m;
-    const size_t ld = W.ld;
+    double* xj = W.w(W_VJ);
+    double* w = W.w(W_W);
+    copy_j(nv, W.V, W.ld, c.kj.p, xj, s);
+    op(xj, w);
+    orthogonalize_j(c, nv, W.V, W.ld, m, c.kj.p, w, W.st, W.st + gs_t(m), s);
+    dot_vector(c, w, w, nv, W.sc(2), s);
+    normalize_j(nv, w, W.sc(2), W.st, m, W.V, W.ld, c.kj.p, s);
+    givens_j(W.st, m, c.kj.p, W.st + gs_hist(m), s);
+}
+
+// The Arnoldi step as an instantiated HIP graph, built once per operator,
+// system and workspace by recording the step's launches (cached in the
+// context; pq_set_system invalidates it). Returns nullptr when graphs are off
+// or the build fails (the caller then launches the step's kernels directly).
+hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, const void* opkey) {
+    Ctx& c = W.c;
+    if (!c.graphs || c.timing) return nullptr;
+    std::vector<uintptr_t> key = {kind, (uintptr_t)opkey, (uintptr_t)nv, (uintptr_t)W.m, (uintptr_t)W.ld,
+                                  (uintptr_t)c.kv.p, (uintptr_t)c.kw.p, (uintptr_t)c.kh.p, (uintptr_t)c.scal.p,
+                                  (uintptr_t)c.part.p, (uintptr_t)c.kj.p, (uintptr_t)c.gen, (uintptr_t)c.pair_grid};
+    if (c.kgraph && key == c.kgraph_key) return c.kgraph;
+    if (c.kgraph) {
+        (void)hipGraphExecDestroy(c.kgraph);
+        c.kgraph = nullptr;
+        c.kgraph_key.clear();
+    }
+    ensure_side(c);
+    GraphRec rec;
+    hipGraphExec_t ex = nullptr;
+    bool ok = hipGraphCreate(&rec.g, 0) == hipSuccess;
+    if (ok) {
+        graph_rec() = &rec;
+        try {
+            arnoldi_step(W, op, nv);
+        } catch (...) {
+            ok = false;
+        }
+        graph_rec() = nullptr;
+    }
+    if (ok) ok = hipGraphInstantiate(&ex, rec.g, nullptr, nullptr, 0) == hipSuccess && ex;
+    if (rec.g) (void)hipGraphDestroy(rec.g);
+    if (!ok) {
+        (void)hipGetLastError();
+        c.graphs = false;   // launch the kernels directly from now on
+        return nullptr;
+    }
+    c.kgraph = ex;
+    c.kgraph_key = key;
+    return ex;
+}
+
+// GMRES(m) for A x = b with vectors of length nv, x in/out (x_zero: x = 0 on
+// entry). fixed: exactly m products from x = 0, no host synchronisation.
+// Each Arnoldi step is one graph launch; the host reads the residual estimate
+// of step j - 1 while step j runs, so a converged cycle has run at most one
+// step more than it uses (its product is counted).
+GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, bool x_zero, double tol, int max_it,
+               bool fixed, uintptr_t kind, const void* opkey) {
+    Ctx& c = W.c;
+    hipStream_t s = c.stream;
+    const int m = W.m;
     double* r = W.w(W_R);
     double* w = W.w(W_W);
     GmresOut out;
     double bnorm = 1.0;
+    c.kj.ensure(4);
+    if (!c.pinned_hist) {
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
+        PQ_HIP(hipHostMalloc((void**)&c.pinned_hist, 520 * sizeof(double), hipHostMallocDefault));
+    }
+    for (auto& ev : c.kev)
+        if (!ev) PQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     if (!fixed) {
         dot_vector(c, b, b, nv, W.sc(0), s);
         bnorm = std::sqrt(read_scalar(c, W.sc(0), s));
@@ -95,25 +163,38 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
             return out;
         }
     }
+    hipGraphExec_t step = step_graph(W, op, nv, kind, opkey);
+    const double* hist = W.st + gs_hist(m);
     for (;;) {
         gmres_start(W.st, m, W.sc(1), s);
         normalize(nv, r, W.sc(1), nullptr, W.V, s);
-        int jdone = 0;
+        set_int(c.kj.p, 0, s);
+        int launched = 0, jdone = -1;
         for (int j = 0; j < m; ++j) {
-            op(W.V + (size_t)j * ld, w);
+            if (!fixed && out.products >= max_it) break;
+            if (step)
+                PQ_HIP(hipGraphLaunch(step, s));
+            else
+                arnoldi_step(W, op, nv);
             out.products++;
-            orthogonalize(c, nv, W.V, ld, j + 1, w, W.st + (size_t)j * (m + 1), W.st + gs_t(m), s);
-            dot_vector(c, w, w, nv, W.sc(2), s);
-            normalize(nv, w, W.sc(2), W.st + (size_t)j * (m + 1) + j + 1, W.V + (size_t)(j + 1) * ld, s);
-            givens(W.st, m, j, W.sc(3), s);
-            jdone = j + 1;
-            if (!fixed) {
-                const double est = read_scalar(c, W.sc(3), s) / bnorm;
-                if (est <= tol || out.products >= max_it) break;
+            ++launched;
+            if (fixed) continue;
+            PQ_HIP(hipMemcpyAsync(c.pinned_hist, hist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+            PQ_HIP(hipEventRecord(c.kev[j & 1], s));
+            if (j >= 1) {
+                PQ_HIP(hipEventSynchronize(c.kev[(j - 1) & 1]));
+                if (c.pinned_hist[j - 1] / bnorm <= tol) {
+                    jdone = j;
+                    break;
+                }
             }
         }
+        if (jdone < 0) {
+            jdone = launched;
+            if (!fixed && launched > 0) PQ_HIP(hipEventSynchronize(c.kev[(launched - 1) & 1]));
+        }
         backsolve(W.st, m, jdone, s);
-        xupdate(nv, W.V, ld, jdone, W.st + gs_y(m), x, s);
+        xupdate(nv, W.V, W.ld, jdone, W.st + gs_y(m), x, s);
         if (fixed) return out;
         // true residual
         op(x, w);
@@ -168,7 +249,7 @@ GmresOut bordered_solve(Work& W, const double* eta, const double* rhs_q, double 
         xz = false;
     }
     OpFn op = bordered_op(W, eta);
-    GmresOut o = gmres(W, op, n + 1, b, x, xz, tol, max_it, false);
+    GmresOut o = gmres(W, op, n + 1, b, x, xz, tol, max_it, false, 1, eta);
     vdiv(n, x, eta, qout, s);
     return o;
 }
@@ -273,7 +354,7 @@ pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, doub
         };
         double* b = W.w(W_B);
         axpby(n, 1.0, n_vec, -1.0, q_n, b, s);   // -(q[n] - n)
-        gmres(W, op, n, b, nddot, true, 0.0, n_krylov, true);
+        gmres(W, op, n, b, nddot, true, 0.0, n_krylov, true, 2, eta);
     }
     return PQ_OK;
     PQ_API_END

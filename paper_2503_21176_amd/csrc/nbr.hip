@@ -157,12 +157,11 @@ __device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, do
 // Cluster-pair list: one wavefront per i-cluster; lanes scan the clusters of
 // each candidate column and every z image. FILL = false counts, FILL = true
 // writes at lstart[ic] in the same deterministic order.
-template <bool FILL, class T>
+template <bool FILL>
 __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
-                                              const int* __restrict__ col_cl, const double* __restrict__ ref,
-                                              const double* __restrict__ lo, const double* __restrict__ hi,
-                                              int* __restrict__ lcount, const int* __restrict__ lstart,
-                                              int2* __restrict__ lj, V4<T>* __restrict__ ls) {
+                                              const int* __restrict__ col_cl, const double* __restrict__ lo,
+                                              const double* __restrict__ hi, int* __restrict__ lcount,
+                                              const int* __restrict__ lstart, int2* __restrict__ lj) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
@@ -172,7 +171,6 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
     const int cxi = coli % g.ncx, cyi = coli / g.ncx;
     const double loi0 = lo[3 * ic], loi1 = lo[3 * ic + 1], loi2 = lo[3 * ic + 2];
     const double hii0 = hi[3 * ic], hii1 = hi[3 * ic + 1], hii2 = hi[3 * ic + 2];
-    const double ri0 = ref[3 * ic], ri1 = ref[3 * ic + 1], ri2 = ref[3 * ic + 2];
     int cnt = 0;
     const int base = FILL ? lstart[ic] : 0;
     for (int dy = -g.Ry; dy <= g.Ry; ++dy) {
@@ -194,34 +192,88 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
             for (int jb = j0; jb < j1; jb += 64) {
                 const int jc = jb + lane;
                 const bool valid = jc < j1;
-                double dxy2 = 0.0, loj2 = 0.0, hij2 = 0.0, rj0 = 0.0, rj1 = 0.0, rj2 = 0.0;
+                double dxy2 = 0.0, loj2 = 0.0, hij2 = 0.0;
                 if (valid) {
                     double gxx = gap1(lo[3 * jc] + sx, hi[3 * jc] + sx, loi0, hii0);
                     double gyy = gap1(lo[3 * jc + 1] + sy, hi[3 * jc + 1] + sy, loi1, hii1);
                     dxy2 = gxx * gxx + gyy * gyy;
                     loj2 = lo[3 * jc + 2];
                     hij2 = hi[3 * jc + 2];
-                    rj0 = ref[3 * jc];
-                    rj1 = ref[3 * jc + 1];
-                    rj2 = ref[3 * jc + 2];
                 }
                 for (int nz = -g.Rz; nz <= g.Rz; ++nz) {
                     double sz = (double)nz * g.L[2];
                     double gz = gap1(loj2 + sz, hij2 + sz, loi2, hii2);
                     bool pass = valid && (dxy2 + gz * gz < rl2);
                     unsigned long long m = __ballot(pass);
-                    if (FILL && pass) {
-                        int pos = base + cnt + lanes_below(m);
-                        lj[pos] = make_int2(jc, pack_img(nx, ny, nz));
-                        ls[pos] = mk4<T>((T)((rj0 + sx) - ri0), (T)((rj1 + sy) - ri1), (T)((rj2 + sz) - ri2),
-                                         (T)0);
-                    }
+                    if (FILL && pass) lj[base + cnt + lanes_below(m)] = make_int2(jc, pack_img(nx, ny, nz));
                     cnt += __popcll(m);
                 }
             }
         }
     }
     if (!FILL && lane == 0) lcount[ic] = cnt;
+}
+
+// Atom-level j list of each i-cluster, derived from its cluster-pair list: the
+// atoms of the listed j-clusters, at the entry's periodic image, that lie
+// within the list radius of the i-cluster's bounding box (a superset of every
+// pair of the cluster closer than the list radius). Entries are V4<T>
+// (x, y, z of the image relative to the i-cluster's reference point, rounded
+// once from FP64; the j slot), in list order, grouped in rows of 8; the last
+// row is padded with atoms far outside any cutoff. About 44 % of the 8 x 8
+// candidates of a row are within the cutoff at liquid-like densities, against
+// ~29 % for whole cluster pairs. FILL = false counts rows, FILL = true writes.
+template <bool FILL, class T>
+__global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lstart,
+                                               const int2* __restrict__ lj, const int* __restrict__ orig,
+                                               const double* __restrict__ w64, const double* __restrict__ ref,
+                                               const double* __restrict__ lo, const double* __restrict__ hi,
+                                               int* __restrict__ jcount, const int* __restrict__ jstart,
+                                               V4<T>* __restrict__ jl) {
+    const int lane = lane_id();
+    const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ic >= ncl) return;
+    const double rl2 = g.rlist * g.rlist * (1.0 + 1e-9) + 1e-12;
+    const double lo0 = lo[3 * ic], lo1 = lo[3 * ic + 1], lo2 = lo[3 * ic + 2];
+    const double hi0 = hi[3 * ic], hi1 = hi[3 * ic + 1], hi2 = hi[3 * ic + 2];
+    const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
+    const int e0 = lstart[ic], e1 = lstart[ic + 1];
+    const int eo = lane >> 3, b = lane & 7;
+    const size_t base = FILL ? (size_t)jstart[ic] * CL : 0;
+    int cnt = 0;
+    for (int eb = e0; eb < e1; eb += 8) {
+        const int e = eb + eo;
+        bool pass = false;
+        int slot = 0;
+        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+        if (e < e1) {
+            const int2 je = lj[e];
+            slot = je.x * CL + b;
+            const int j = orig[slot];
+            if (j >= 0) {
+                int n0, n1, n2;
+                unpack_img(je.y, n0, n1, n2);
+                p0 = w64[3 * (size_t)j + 0] + (double)n0 * g.L[0];
+                p1 = w64[3 * (size_t)j + 1] + (double)n1 * g.L[1];
+                p2 = w64[3 * (size_t)j + 2] + (double)n2 * g.L[2];
+                const double gx = fmax(0.0, fmax(lo0 - p0, p0 - hi0));
+                const double gy = fmax(0.0, fmax(lo1 - p1, p1 - hi1));
+                const double gz = fmax(0.0, fmax(lo2 - p2, p2 - hi2));
+                pass = gx * gx + gy * gy + gz * gz < rl2;
+            }
+        }
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(pass);
+        if (FILL && pass)
+            jl[base + cnt + lanes_below(m)] = mk4<T>((T)(p0 - r0), (T)(p1 - r1), (T)(p2 - r2), pack_int(slot, T(0)));
+        cnt += __popcll(m);
+    }
+    const int rows = (cnt + CL - 1) / CL;
+    if (!FILL) {
+        if (lane == 0) jcount[ic] = rows;
+    } else {
+        for (int k = cnt + lane; k < rows * CL; k += 64)
+            jl[base + k] = mk4<T>((T)-1.0e4, (T)-1.0e4, (T)-1.0e4, pack_int(0, T(0)));
+    }
 }
 
 // Export of the atom pairs closer than the list radius, by the canonical FP64
@@ -341,8 +393,8 @@ void nbr_build(Ctx& c, const double* pos) {
     else
         PQ_LAUNCH(k_cluster<float>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
                   c.cl_hi.p, as<float4>(c.xyzq));
-    PQ_LAUNCH((k_list<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
-              c.cl_lo.p, c.cl_hi.p, c.lcount.p, (const int*)nullptr, (int2*)nullptr, (float4*)nullptr);
+    PQ_LAUNCH((k_list<false>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p,
+              c.lcount.p, (const int*)nullptr, (int2*)nullptr);
     PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.lcount.p, c.lstart.p, ncl);
     int tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.lstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -350,13 +402,30 @@ void nbr_build(Ctx& c, const double* pos) {
     PQ_REQUIRE(tot >= 0, PQ_ERR_BOX, "cluster-pair list overflow");
     c.nlist = tot;
     c.lj.ensure(std::max(1, tot));
-    c.ls.ensure((size_t)std::max(1, tot) * 4 * rsz(c));
+    PQ_LAUNCH((k_list<true>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p,
+              c.lcount.p, c.lstart.p, c.lj.p);
+    // atom-level j lists for the pair kernel
+    c.jcount.ensure(ncl + 1);
+    c.jstart.ensure(ncl + 1);
     if (c.fp64)
-        PQ_LAUNCH((k_list<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
-                  c.cl_lo.p, c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, as<double4>(c.ls));
+        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
     else
-        PQ_LAUNCH((k_list<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_ref.p,
-                  c.cl_lo.p, c.cl_hi.p, c.lcount.p, c.lstart.p, c.lj.p, as<float4>(c.ls));
+        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
+    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.jcount.p, c.jstart.p, ncl);
+    int rows = 0;
+    PQ_HIP(hipMemcpyAsync(&rows, c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    PQ_REQUIRE(rows >= 0, PQ_ERR_BOX, "atom list overflow");
+    c.njrows = rows;
+    c.jl.ensure((size_t)std::max(1, rows) * CL * 4 * rsz(c));
+    if (c.fp64)
+        PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
+    else
+        PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {

@@ -82,7 +82,7 @@ __global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int
     }
     int br = base[0] / PME_B + G.nb0 * (base[1] / PME_B + G.nb1 * (base[2] / PME_B));
     brick_of[i] = br;
-    frac_tmp[i] = mk4<T>(fr[0], fr[1], fr[2], pack_base(base[0] | (base[1] << 10) | (base[2] << 20), T(0)));
+    frac_tmp[i] = mk4<T>(fr[0], fr[1], fr[2], pack_int(base[0] | (base[1] << 10) | (base[2] << 20), T(0)));
     atomicAdd(&brick_cnt[br], 1);
 }
 
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __res
         const V4<T> f4 = pme_frac[k];
         const T qq = (T)q[pme_idx[k]];
         const T* wk = pme_w + (size_t)k * 24;
-        const int pk = unpack_base(f4.w);
+        const int pk = unpack_int(f4.w);
         const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
         T wx[P];
 #pragma unroll
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         if (valid) {
             const V4<T> f4 = pme_frac[k];
             i = pme_idx[k];
-            const int pk = unpack_base(f4.w);
+            const int pk = unpack_int(f4.w);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
             T wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
             bspline<P, T>(f4.x, wx, dx);

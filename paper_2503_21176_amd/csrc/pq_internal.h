@@ -4,7 +4,11 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
+#include <mutex>
+#include <tuple>
+#include <utility>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -33,13 +37,104 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::pq::Error((code), (msg)); \
     } while (0)
 
-#define PQ_LAUNCH(kern, grid, block, shmem, stream, ...)                               \
-    do {                                                                               \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__); \
-        PQ_HIP(hipGetLastError());                                                     \
-    } while (0)
+// ---------------------------------------------------------------------------
+// Graph recorder: while one is active on the calling thread, kernel launches
+// and the fork/join event operations of an evaluation become nodes and edges
+// of a HIP graph instead of running. The graph is built node by node (no
+// stream capture), so no stream of the process is ever in capture mode and
+// other threads can allocate, free and synchronise freely meanwhile.
+// ---------------------------------------------------------------------------
+struct GraphRec {
+    hipGraph_t g = nullptr;
+    // per stream: the nodes its next node depends on
+    std::vector<std::pair<hipStream_t, std::vector<hipGraphNode_t>>> deps;
+    // per recorded event: the nodes it stands for
+    std::vector<std::pair<hipEvent_t, std::vector<hipGraphNode_t>>> evs;
+    std::vector<hipGraphNode_t>& deps_of(hipStream_t s) {
+        for (auto& d : deps)
+            if (d.first == s) return d.second;
+        deps.emplace_back(s, std::vector<hipGraphNode_t>{});
+        return deps.back().second;
+    }
+    void add_kernel(const void* f, dim3 grid, dim3 block, size_t shmem, hipStream_t s, void** args) {
+        hipKernelNodeParams p{};
+        p.func = const_cast<void*>(f);
+        p.gridDim = grid;
+        p.blockDim = block;
+        p.sharedMemBytes = (unsigned)shmem;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        std::vector<hipGraphNode_t>& d = deps_of(s);
+        hipGraphNode_t node = nullptr;
+        PQ_HIP(hipGraphAddKernelNode(&node, g, d.empty() ? nullptr : d.data(), d.size(), &p));
+        d.assign(1, node);
+    }
+    void record(hipEvent_t e, hipStream_t s) {
+        const std::vector<hipGraphNode_t> d = deps_of(s);
+        for (auto& x : evs)
+            if (x.first == e) {
+                x.second = d;
+                return;
+            }
+        evs.emplace_back(e, d);
+    }
+    void wait(hipStream_t s, hipEvent_t e) {
+        std::vector<hipGraphNode_t>& d = deps_of(s);
+        for (auto& x : evs)
+            if (x.first == e)
+                for (hipGraphNode_t n : x.second)
+                    if (std::find(d.begin(), d.end(), n) == d.end()) d.push_back(n);
+    }
+};
+inline GraphRec*& graph_rec() {
+    thread_local GraphRec* r = nullptr;
+    return r;
+}
+
+template <class Tup, size_t... I>
+inline void arg_ptrs(Tup& t, void** out, std::index_sequence<I...>) {
+    ((out[I] = (void*)&std::get<I>(t)), ...);
+}
+
+// Launches kernel k, or adds it to the active graph recorder. The arguments
+// are converted to the kernel's parameter types first.
+template <class... P, class... A>
+inline void launch_kernel(void (*k)(P...), dim3 grid, dim3 block, size_t shmem, hipStream_t s, A&&... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "kernel argument count");
+    std::tuple<std::decay_t<P>...> t(std::forward<A>(a)...);
+    void* args[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    arg_ptrs(t, args, std::index_sequence_for<P...>{});
+    if (GraphRec* r = graph_rec()) {
+        r->add_kernel(reinterpret_cast<const void*>(k), grid, block, shmem, s, args);
+        return;
+    }
+    PQ_HIP(hipLaunchKernel(reinterpret_cast<const void*>(k), grid, block, args, shmem, s));
+}
+
+#define PQ_LAUNCH(kern, grid, block, shmem, stream, ...) \
+    ::pq::launch_kernel(kern, dim3(grid), dim3(block), (size_t)(shmem), stream, __VA_ARGS__)
+
+// Event record / stream wait that a graph recorder turns into edges.
+inline void ev_record(hipEvent_t e, hipStream_t s) {
+    if (GraphRec* r = graph_rec())
+        r->record(e, s);
+    else
+        PQ_HIP(hipEventRecord(e, s));
+}
+inline void stream_wait(hipStream_t s, hipEvent_t e) {
+    if (GraphRec* r = graph_rec())
+        r->wait(s, e);
+    else
+        PQ_HIP(hipStreamWaitEvent(s, e, 0));
+}
 
 inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Process-wide lock ordering device allocation, free and device-wide
+// synchronisation against stream captures in other threads (several contexts
+// may be used from several threads, as in the server): a free or a device
+// synchronise must never meet a stream that is being captured.
+std::recursive_mutex& device_mem_lock();
 
 // Device buffer owned by a context; grows on demand, never shrinks.
 template <class T>
@@ -52,6 +147,7 @@ struct DBuf {
     ~DBuf() { release(); }
     void ensure(size_t m) {
         if (m <= n) return;
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
         release();
         if (m == 0) return;
         void* q = nullptr;
@@ -64,9 +160,11 @@ struct DBuf {
         n = m;
     }
     void release() {
+        if (!p) return;
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
         // kernels queued on any stream may still use the old buffer
-        if (p) (void)hipDeviceSynchronize();
-        if (p) (void)hipFree(p);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(p);
         p = nullptr;
         n = 0;
     }
@@ -131,8 +229,11 @@ struct Ctx {
     DBuf<int> cl_col;        // column of each cluster
     DBuf<int> lcount;        // ncl+1
     DBuf<int> lstart;        // ncl+1
-    DBuf<int2> lj;           // list: (j cluster, packed image vector)
-    DBuf<unsigned char> ls;   // list: V4<T> shift ref_j + nL - ref_i
+    DBuf<int2> lj;           // cluster-pair list: (j cluster, packed image vector)
+    DBuf<int> jcount;        // ncl+1: rows of 8 j atoms per i-cluster
+    DBuf<int> jstart;        // ncl+1: row offsets
+    DBuf<unsigned char> jl;  // atom-level j lists: V4<T> (image position - ref_i, slot)
+    int64_t njrows = 0;
     DBuf<int> flag;          // device error flags
     DBuf<unsigned long long> counter;
 
@@ -164,6 +265,10 @@ struct Ctx {
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
 
+    // --- tuned launch shapes (pq_autotune) ---
+    int pair_grid = 0;       // pair kernel workgroups (0: one wavefront per i-cluster)
+    double tune_ms = 0.0;    // evaluation time of the chosen shape
+
     // --- second stream: the pair kernel overlaps the PME chain ---
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -181,6 +286,15 @@ struct Ctx {
     DBuf<double> kf;         // force scratch n*3 (x2)
     size_t kld = 0;
     int km = 0;
+
+    // --- Arnoldi step as a HIP graph (one step replayed every iteration) ---
+    uint64_t gen = 0;                 // incremented by every pq_set_system
+    bool graphs = true;               // off after a failed capture
+    hipGraphExec_t kgraph = nullptr;
+    std::vector<uintptr_t> kgraph_key;
+    DBuf<int> kj;                     // device step index j
+    double* pinned_hist = nullptr;    // host copy of the residual estimates
+    hipEvent_t kev[2] = {nullptr, nullptr};
 
     ~Ctx();
 };
@@ -220,6 +334,7 @@ void combine(Ctx& c, const double* q, const double* Q, double* phi, double* forc
              double* energy, hipStream_t s);
 
 // high-level evaluation used by the ABI and the Krylov solvers (abi.cpp)
+void ensure_side(Ctx& c);   // creates the pair kernel's stream and fork/join events
 void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy,
                   hipStream_t s);
 

@@ -10,6 +10,8 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -43,6 +45,7 @@ struct Req {
     double energy = 0;
     pq_solve_info info{};
     int status = 0;
+    std::string message;
     bool done = false;
 };
 
@@ -52,23 +55,33 @@ double now_s(std::chrono::steady_clock::time_point t0) {
 
 }  // namespace
 
-// Estimated device bytes of one request (neighbour list, PME grids, Krylov basis).
+// Estimated device bytes of one request: neighbour lists, per-atom arrays,
+// PME grids and staging, Krylov basis. Bulk arrays take 4 or 8 bytes per real
+// (FP32 or FP64 form). The list sizes follow from the volume within the list
+// radius of a cluster's bounding box (edge a for 8 atoms at the system's
+// density): a box of edge e grown by a ball of radius r has volume
+// e^3 + 6 e^2 r + 3 pi e r^2 + 4/3 pi r^3.
 double request_footprint(int64_t n, const pq_params& p, int restart) {
+    const double rs = (p.flags & PQ_FLAG_FP64) ? 8.0 : 4.0;
     const double V = p.box[0] * p.box[1] * p.box[2];
     const double rho = (double)n / V;
     const double a = std::cbrt(8.0 / rho);
-    const double rl = p.cutoff + p.skin + 2.0 * a;
+    const double rl = p.cutoff + p.skin;
+    auto grown = [&](double e) { return e * e * e + 6 * e * e * rl + 3 * PI * e * rl * rl + 4.0 / 3.0 * PI * rl * rl * rl; };
     const double ncl = std::ceil((double)n / 8.0) + 1.0;
-    double per_cl = (4.0 / 3.0) * PI * rl * rl * rl * rho / 8.0;
-    double list = ncl * per_cl * 24.0;
-    double atoms = (double)n * (24 + 16 + 16 + 16 + 20 + 8 + 32 + 24);
+    const double pairs = ncl * grown(2.0 * a) * rho / 8.0 * 8.0;        // cluster pairs, int2 each
+    const double jatoms = ncl * (grown(a) * rho + 8.0) * 4.0 * rs;       // atom list, V4 each
+    const double atoms = (double)n * (24 + 16 + 16 + 16 + 20 + 8 + 32 + 24) + (double)n * (4 + 4 + 16 + 24) * rs;
     double grid = 0;
     if (p.method == PQ_METHOD_PME) {
-        double K3 = (double)p.grid[0] * p.grid[1] * p.grid[2];
-        grid = K3 * 4.0 + (p.grid[0] / 2 + 1) * (double)p.grid[1] * p.grid[2] * 8.0;
+        const double K3 = (double)p.grid[0] * p.grid[1] * p.grid[2];
+        const double R = 8 + p.order - 1;
+        const double nbrick = std::ceil(p.grid[0] / 8.0) * std::ceil(p.grid[1] / 8.0) * std::ceil(p.grid[2] / 8.0);
+        grid = K3 * rs + (p.grid[0] / 2 + 1) * (double)p.grid[1] * p.grid[2] * 2.0 * rs + nbrick * R * R * R * rs +
+               (double)n * 24.0 * rs;
     }
-    double kry = ((double)n + 64) * 8.0 * (9 + restart + 1);
-    return list + atoms + grid + kry + (1 << 20);
+    const double kry = ((double)n + 64) * 8.0 * (9 + restart + 1);
+    return 1.25 * (pairs + jatoms + atoms + grid + kry) + (1 << 20);
 }
 
 }  // namespace pq
@@ -87,6 +100,8 @@ struct pq_server {
     struct Slot {
         pq_ctx* ctx = nullptr;
         hipStream_t stream = nullptr;
+        double* io = nullptr;      // device copies of a request's inputs and outputs; grows, never shrinks
+        size_t io_bytes = 0;
         std::shared_ptr<pq::Req> req;
         std::thread th;
         std::condition_variable cv;
@@ -101,25 +116,36 @@ namespace pq {
 namespace {
 
 void run_request(pq_server* S, pq_server::Slot* sl, Req& r) {
+    (void)S;
     pq_ctx* ctx = sl->ctx;
-    double* d = nullptr;
     const int64_t n = r.n;
     r.q.assign(n, 0.0);
     pq_status st = PQ_OK;
-    // one device allocation: pos, chi, eta, q0, q, energy
+    hipStream_t s = sl->stream;
+    // pos, chi, eta, q0, q, energy in the slot's buffer; it is reallocated only
+    // when a larger request arrives (a free synchronises the whole device)
     const size_t bytes = sizeof(double) * (size_t)(n * 3 + n * 4 + 1);
-    if (hipMalloc(&d, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        r.status = PQ_ERR_NOMEM;
-        return;
+    if (bytes > sl->io_bytes) {
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
+        (void)hipStreamSynchronize(s);
+        if (sl->io) (void)hipFree(sl->io);
+        sl->io = nullptr;
+        sl->io_bytes = 0;
+        const size_t want = bytes + bytes / 2;
+        if (hipMalloc(&sl->io, want) != hipSuccess) {
+            (void)hipGetLastError();
+            sl->io = nullptr;
+            r.status = PQ_ERR_NOMEM;
+            return;
+        }
+        sl->io_bytes = want;
     }
-    double* dpos = d;
+    double* dpos = sl->io;
     double* dchi = dpos + 3 * n;
     double* deta = dchi + n;
     double* dq0 = deta + n;
     double* dq = dq0 + n;
     double* den = dq + n;
-    hipStream_t s = sl->stream;
     bool ok = hipMemcpyAsync(dpos, r.pos.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(dchi, r.chi.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) == hipSuccess &&
               hipMemcpyAsync(deta, r.eta.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -137,8 +163,8 @@ void run_request(pq_server* S, pq_server::Slot* sl, Req& r) {
             st = PQ_ERR_HIP;
     }
     (void)hipStreamSynchronize(s);
-    (void)hipFree(d);
     r.status = st;
+    if (st < 0) r.message = pq_last_error();
 }
 
 void slot_main(pq_server* S, pq_server::Slot* sl) {
@@ -236,6 +262,10 @@ pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg) {
         PQ_HIP(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
         pq_status st = pq_create(&sl->ctx, cfg->device, sl->stream);
         if (st != PQ_OK) throw Error(st, pq_last_error());
+        // slots launch their kernels directly; Arnoldi-step graphs are kept
+        // for contexts driven from one thread (several slots replaying their
+        // graphs concurrently crashed the process; the cause is not known)
+        reinterpret_cast<Ctx*>(sl->ctx)->graphs = false;
         S->slots.push_back(std::move(sl));
     }
     for (auto& sl : S->slots) sl->th = std::thread(slot_main, S.get(), sl.get());
@@ -299,9 +329,15 @@ pq_status pq_server_poll(pq_server* S, uint64_t ticket, pq_result* res, int64_t 
     res->t_submit_s = r->t_submit;
     res->t_start_s = r->t_start;
     res->t_done_s = r->t_done;
+    std::snprintf(res->message, sizeof(res->message), "%s", r->message.c_str());
     S->all.erase(it);
     return PQ_OK;
     PQ_API_END
+}
+
+double pq_request_footprint(int64_t n, const pq_params* params, int32_t restart) {
+    if (n < 1 || !params || restart < 1) return -1.0;
+    return request_footprint(n, *params, restart);
 }
 
 pq_status pq_server_destroy(pq_server* S) {
@@ -316,6 +352,8 @@ pq_status pq_server_destroy(pq_server* S) {
     for (auto& sl : S->slots) {
         if (sl->th.joinable()) sl->th.join();
         pq_destroy(sl->ctx);
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
+        if (sl->io) (void)hipFree(sl->io);
         if (sl->stream) (void)hipStreamDestroy(sl->stream);
     }
     delete S;

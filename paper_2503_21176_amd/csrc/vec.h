@@ -10,13 +10,15 @@
 namespace pq {
 
 // Layout of the small GMRES state for restart length m (all FP64):
-// H (m+1) x m column-major, then g[m+1], cs[m], sn[m], y[m], h2[m+1].
+// H (m+1) x m column-major, then g[m+1], cs[m], sn[m], y[m], h2[m+1],
+// hist[m] (|g[j+1]| after step j).
 __host__ __device__ inline size_t gs_g(int m) { return (size_t)(m + 1) * m; }
 __host__ __device__ inline size_t gs_c(int m) { return gs_g(m) + m + 1; }
 __host__ __device__ inline size_t gs_s(int m) { return gs_c(m) + m; }
 __host__ __device__ inline size_t gs_y(int m) { return gs_s(m) + m; }
 __host__ __device__ inline size_t gs_t(int m) { return gs_y(m) + m; }
-__host__ __device__ inline size_t gs_size(int m) { return gs_t(m) + m + 2; }
+__host__ __device__ inline size_t gs_hist(int m) { return gs_t(m) + m + 2; }   // residual estimates, m
+__host__ __device__ inline size_t gs_size(int m) { return gs_hist(m) + m + 1; }
 
 // mode 0: sum x; 1: sum x*y; 2: sum x/y. out = alpha * result (device scalar)
 void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, double alpha, double* out, hipStream_t s);
@@ -39,6 +41,14 @@ void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, dou
 void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const double* u, const double* a,
                 const double* phi, double* out, hipStream_t s);
 void copy_scalar(const double* a, double* b, hipStream_t s);
+// device-indexed forms: the step index j is *jdev (graph-captured steps)
+void copy_j(int64_t n, const double* V, size_t ld, const int* jdev, double* out, hipStream_t s);
+void orthogonalize_j(Ctx& c, int64_t n, const double* V, size_t ld, int m, const int* jdev, double* w, double* st,
+                     double* tmp2, hipStream_t s);
+void normalize_j(int64_t n, const double* w, const double* nrm2, double* st, int m, double* V, size_t ld,
+                 const int* jdev, hipStream_t s);
+void givens_j(double* st, int m, int* jdev, double* hist, hipStream_t s);
+void set_int(int* p, int v, hipStream_t s);
 void set_scalar(double* b, double v, hipStream_t s);
 
 }  // namespace pq

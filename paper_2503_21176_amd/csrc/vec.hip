@@ -29,10 +29,19 @@ __global__ __launch_bounds__(VB) void k_part_sum(const double* __restrict__ x, c
     if (threadIdx.x == 0) part[blockIdx.x] = v;
 }
 
-// out[k] = alpha * sum of part[k*nb .. k*nb+nb-1] (+ beta * out2 optional)
+// Step index of a graph-captured Arnoldi step: *jdev when given, else j.
+__device__ __forceinline__ int step_of(const int* jdev, int j) { return jdev ? *jdev : j; }
+
+// out[k] = alpha * sum of part[k*nb .. k*nb+nb-1], k < nk; with jdev:
+// nk = *jdev + 1 and out advanced by *jdev * ostride
 __global__ __launch_bounds__(VB) void k_part_final(const double* __restrict__ part, int nb, int nk, double alpha,
-                                                   double* __restrict__ out) {
+                                                   double* __restrict__ out, const int* __restrict__ jdev,
+                                                   size_t ostride) {
     __shared__ double red[VB / 64];
+    if (jdev) {
+        nk = *jdev + 1;
+        out += (size_t)(*jdev) * ostride;
+    }
     for (int k = 0; k < nk; ++k) {
         double v = 0.0;
         for (int i = threadIdx.x; i < nb; i += VB) v += part[(size_t)k * nb + i];
@@ -48,7 +57,7 @@ void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, doubl
     const int nb = red_blocks(n);
     c.part.ensure(nb + 16);
     PQ_LAUNCH(k_part_sum, nb, VB, 0, s, x, y, n, mode, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, alpha, out);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, alpha, out, (const int*)nullptr, (size_t)0);
 }
 
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s) { reduce(c, x, nullptr, n, 0, 1.0, out, s); }
@@ -216,14 +225,16 @@ void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const do
     const int nb = red_blocks(n);
     c.part.ensure(2 * nb + 16);
     PQ_LAUNCH(k_part_shadow, nb, VB, 0, s, n, chi, v, u, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 2, 1.0, out2);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 2, 1.0, out2, (const int*)nullptr, (size_t)0);
 }
 
 // ---- Gram-Schmidt -----------------------------------------------------------
-// part[k*nb + b] = partial of V_k . w for k <= j
+// part[k*nb + b] = partial of V_k . w for k < nk (nk = *jdev + 1 with jdev)
 __global__ __launch_bounds__(VB) void k_mdot(int64_t n, const double* __restrict__ V, size_t ld, int nk,
-                                             const double* __restrict__ w, double* __restrict__ part) {
+                                             const int* __restrict__ jdev, const double* __restrict__ w,
+                                             double* __restrict__ part) {
     __shared__ double red[VB / 64];
+    if (jdev) nk = *jdev + 1;
     for (int k = 0; k < nk; ++k) {
         double v = 0.0;
         const double* Vk = V + (size_t)k * ld;
@@ -233,33 +244,54 @@ __global__ __launch_bounds__(VB) void k_mdot(int64_t n, const double* __restrict
         __syncthreads();
     }
 }
-// w -= sum_k h[k] V_k ; hacc[k] += h[k] (optional)
-__global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const double* __restrict__ h,
-                          double* __restrict__ w) {
+// w -= sum_k h[k] V_k, k < nk (with jdev: nk = *jdev + 1, h advanced by *jdev * hstride)
+__global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const int* __restrict__ jdev,
+                          size_t hstride, const double* __restrict__ h, double* __restrict__ w) {
+    if (jdev) {
+        nk = *jdev + 1;
+        h += (size_t)(*jdev) * hstride;
+    }
     for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
         double acc = w[i];
         for (int k = 0; k < nk; ++k) acc -= h[k] * V[(size_t)k * ld + i];
         w[i] = acc;
     }
 }
-__global__ void k_hadd(int nk, const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+// out[k] = a[k] + b[k], k < nk (with jdev: nk = *jdev + 1, a and out advanced by *jdev * stride)
+__global__ void k_hadd(int nk, const int* __restrict__ jdev, size_t stride, const double* __restrict__ a,
+                       const double* __restrict__ b, double* __restrict__ out) {
+    if (jdev) {
+        nk = *jdev + 1;
+        a += (size_t)(*jdev) * stride;
+        out += (size_t)(*jdev) * stride;
+    }
     for (int k = threadIdx.x; k < nk; k += blockDim.x) out[k] = a[k] + b[k];
 }
 
-void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
-                   hipStream_t s) {
+// CGS2 of w against V_0..V_{nk-1}; coefficients into hcol. With jdev the
+// column is that of step *jdev: nk = *jdev + 1, hcol = h0 + *jdev * hstride.
+static void orthogonalize_impl(Ctx& c, int64_t n, const double* V, size_t ld, int nk, const int* jdev,
+                               size_t hstride, double* w, double* hcol, double* tmp2, hipStream_t s) {
     const int nb = red_blocks(n);
-    c.part.ensure((size_t)nk * nb + 16);
+    c.part.ensure((size_t)(nk + 1) * nb + 16);
     const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
     // pass 1
-    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, w, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, hcol);
-    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, hcol, w);
+    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, hcol, jdev, hstride);
+    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, hstride, hcol, w);
     // pass 2 (re-orthogonalisation)
-    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, w, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, tmp2);
-    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, tmp2, w);
-    PQ_LAUNCH(k_hadd, 1, 64, 0, s, nk, hcol, tmp2, hcol);
+    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, tmp2, jdev, (size_t)0);
+    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, (size_t)0, tmp2, w);
+    PQ_LAUNCH(k_hadd, 1, 64, 0, s, nk, jdev, hstride, hcol, tmp2, hcol);
+}
+void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
+                   hipStream_t s) {
+    orthogonalize_impl(c, n, V, ld, nk, nullptr, 0, w, hcol, tmp2, s);
+}
+void orthogonalize_j(Ctx& c, int64_t n, const double* V, size_t ld, int m, const int* jdev, double* w, double* st,
+                     double* tmp2, hipStream_t s) {
+    orthogonalize_impl(c, n, V, ld, m + 1, jdev, (size_t)(m + 1), w, st, tmp2, s);
 }
 
 // V_{j+1} = w / h, h = sqrt(nrm2) stored into H(j+1, j); zero vector if h == 0
@@ -358,8 +390,67 @@ void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const dou
     const int nb = red_blocks(n);
     c.part.ensure(nb + 16);
     PQ_LAUNCH(k_part_energy, nb, VB, 0, s, n, q, chi, u, a, phi, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, out);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0);
 }
+
+// ---- device-indexed steps (graph-captured Arnoldi iterations) --------------
+// out = V_{*jdev}
+__global__ void k_copy_j(int64_t n, const double* __restrict__ V, size_t ld, const int* __restrict__ jdev,
+                         double* __restrict__ out) {
+    const double* v = V + (size_t)(*jdev) * ld;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) out[i] = v[i];
+}
+void copy_j(int64_t n, const double* V, size_t ld, const int* jdev, double* out, hipStream_t s) {
+    PQ_LAUNCH(k_copy_j, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, V, ld, jdev, out);
+}
+// V_{j+1} = w / h and H(j+1, j) = h = sqrt(nrm2), j = *jdev
+__global__ void k_normalize_j(int64_t n, const double* __restrict__ w, const double* __restrict__ nrm2,
+                              double* __restrict__ st, int m, double* __restrict__ V, size_t ld,
+                              const int* __restrict__ jdev) {
+    const int j = *jdev;
+    const double h = sqrt(fmax(*nrm2, 0.0));
+    const double inv = h > 0.0 ? 1.0 / h : 0.0;
+    double* out = V + (size_t)(j + 1) * ld;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) out[i] = w[i] * inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st[(size_t)j * (m + 1) + j + 1] = h;
+}
+void normalize_j(int64_t n, const double* w, const double* nrm2, double* st, int m, double* V, size_t ld,
+                 const int* jdev, hipStream_t s) {
+    PQ_LAUNCH(k_normalize_j, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, w, nrm2, st, m, V, ld, jdev);
+}
+// Givens update of column j = *jdev; |g[j+1]| into hist[j]; then *jdev = j + 1
+__global__ void k_givens_j(double* __restrict__ st, int m, int* __restrict__ jdev, double* __restrict__ hist) {
+    if (threadIdx.x != 0) return;
+    const int j = *jdev;
+    double* H = st;
+    double* g = st + gs_g(m);
+    double* cs = st + gs_c(m);
+    double* sn = st + gs_s(m);
+    double* col = H + (size_t)j * (m + 1);
+    for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    g[j + 1] = -s * g[j];
+    g[j] = c * g[j];
+    hist[j] = fabs(g[j + 1]);
+    *jdev = j + 1;
+}
+void givens_j(double* st, int m, int* jdev, double* hist, hipStream_t s) {
+    PQ_LAUNCH(k_givens_j, 1, 64, 0, s, st, m, jdev, hist);
+}
+__global__ void k_set_int(int* __restrict__ p, int v) {
+    if (threadIdx.x == 0) *p = v;
+}
+void set_int(int* p, int v, hipStream_t s) { PQ_LAUNCH(k_set_int, 1, 64, 0, s, p, v); }
 
 __global__ void k_copy_scalar(const double* __restrict__ a, double* __restrict__ b) {
     if (threadIdx.x == 0) *b = *a;

@@ -31,7 +31,7 @@ def test_library_loads_and_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == _declared()
     L = P.load()
-    assert L.pq_abi_version() == 1
+    assert L.pq_abi_version() == P.ABI_VERSION == 2
     assert L.pq_coulomb_constant() == 14.3996454784
 
 
@@ -51,3 +51,27 @@ def test_make_params_validation_on_host():
     assert p.method == P.METHOD_EWALD and list(p.kmax) == [8, 8, 8]
     with pytest.raises(ValueError):
         P.make_params(20.0, 8.0, 0.35, method="p3m")
+
+
+def test_result_and_tune_struct_layouts():
+    import paper_2503_21176_amd as P
+    # q pointer, energy, solve info (24), status + pad, three doubles, message[256]
+    assert P.Result.message.offset == 8 + 8 + 24 + 8 + 24
+    assert ctypes.sizeof(P.Result) == 8 + 8 + 24 + 8 + 24 + 256
+    assert ctypes.sizeof(P.TuneResult) == 24
+
+
+def test_request_footprint_is_host_only_and_sane():
+    # the admission estimate needs no device: positive, growing with the atom
+    # count, larger for the FP64 form and for longer GMRES restarts
+    import paper_2503_21176_amd as P
+    def fp(n, fp64=False, restart=50):
+        L = (n / 0.1) ** (1 / 3)
+        K = 2 * ((int(L) + 2) // 2)
+        return P.request_footprint(n, P.make_params(L, 9.0, 0.29, grid=max(K, 10), order=5, fp64=fp64), restart)
+    a, b = fp(1000), fp(20000)
+    assert 0 < a < b
+    assert fp(20000, fp64=True) > b
+    assert fp(20000, restart=200) > b
+    with pytest.raises(ValueError):
+        P.request_footprint(0, P.make_params(10.0, 4.0, 0.5, grid=10, order=4))

@@ -231,3 +231,33 @@ def test_autograd_function(P, system):
     _, dcw, _ = G.qeq_vjp(s.pos, s.box, coul, s.chi, s.eta, w)
     assert np.linalg.norm(host(chi2.grad) - dcw) / np.linalg.norm(dcw) < 90 * kappa * EPS_OP
     ctx.close()
+
+
+def test_graph_replays_match_direct_launches(P, system):
+    """Each Arnoldi step is one replay of a captured HIP graph, with the
+    solver's own eager kernels, copies and host synchronisations between the
+    replays; phase-timing mode launches the same kernels directly. Solves with
+    several restart cycles (graph reused across cycles and calls) and the
+    fixed-length shadow Krylov solve must agree bit for bit with the direct
+    launches, on every call."""
+    s, coul, A = system
+    ctx = make_ctx(P, s, coul)
+    n_vec = gpu(Q.qeq_dense(A, s.chi, s.eta, 0.0)[0] + np.random.default_rng(5).normal(0, 0.05, s.n))
+    runs = {}
+    for mode in (0, 1, 0, 1, 0):
+        ctx.set_timing(mode)
+        r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=1e-7, max_it=400, restart=6)
+        q, F, x, e = ctx.shadow_step(gpu(s.chi), gpu(s.eta), n_vec, n_krylov=8)
+        torch.cuda.synchronize()
+        runs.setdefault(mode, []).append((host(r.q), r.iterations, r.restarts, host(x), host(q)))
+        if mode:
+            ctx.timings()
+    ctx.close()
+    ref = runs[1][0]
+    say(f"[graph] its {ref[1]} restarts {ref[2]}, {len(runs[0])} graph runs, {len(runs[1])} direct runs")
+    assert ref[2] >= 2
+    for run in runs[0] + runs[1]:
+        assert np.array_equal(run[0], ref[0])
+        assert run[1:3] == ref[1:3]
+        assert np.array_equal(run[3], ref[3])
+        assert np.array_equal(run[4], ref[4])

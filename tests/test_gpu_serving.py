@@ -86,9 +86,12 @@ def test_admission_by_memory_budget(P):
         srv.submit(s.pos, s.chi, s.eta, params(P, s, K))
     assert e.value.code == -6
     srv.close()
-    # a budget that fits one request at a time (each of these estimates
-    # 1.1-1.4 MB): requests run one after another
-    srv = P.Server(0, slots=4, hbm_budget_bytes=1.9e6)
+    # a budget that fits one request at a time: requests run one after another
+    fp = [P.request_footprint(s.n, params(P, s, K), 50) for s, K in reqs]
+    say(f"[admission] footprints {[round(f / 1e6, 3) for f in fp]} MB")
+    budget = max(fp) + 0.5 * min(fp)
+    assert budget < sum(sorted(fp)[:2])
+    srv = P.Server(0, slots=4, hbm_budget_bytes=budget)
     tickets = [srv.submit(s.pos, s.chi, s.eta, params(P, s, K), tol=1e-6, max_it=300) for s, K in reqs]
     res = [srv.poll(tk) for tk in tickets]
     srv.close()
@@ -111,3 +114,33 @@ def test_evaluations_are_bitwise_reproducible(P):
         ctx.close()
     for o in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
+
+
+def test_mixed_stream_eight_slots_no_errors(P):
+    """The served stream's own shape (log-uniform 64..20000 atoms, PME 1 A
+    spacing, order 5) on 8 slots with short solves: every request must end
+    converged or at its product limit, never with an error, and a request's
+    charges must not depend on what ran beside it."""
+    stream = W.serving_stream(n_req=24)
+    reqs = [x[1] for x in stream]
+
+    def prm(r):
+        return P.make_params(r.box, r.params["cutoff"], r.params["alpha"], grid=r.params["grid"],
+                             order=r.params["order"])
+
+    srv = P.Server(0, slots=8, hbm_budget_bytes=50e9)
+    tickets = [srv.submit(r.pos, r.chi, r.eta, prm(r), q0=r.q, tol=1e-5, max_it=20, restart=10) for r in reqs]
+    res = [srv.poll(tk) for tk in tickets]
+    # the same requests again, one slot: results must be identical
+    srv1 = P.Server(0, slots=1, hbm_budget_bytes=50e9)
+    res1 = [srv1.poll(srv1.submit(r.pos, r.chi, r.eta, prm(r), q0=r.q, tol=1e-5, max_it=20, restart=10))
+            for r in reqs[:6]]
+    srv.close()
+    srv1.close()
+    for r, x in zip(reqs, res):
+        say(f"[stream] n={r.n} K={r.params['grid']} status={x['status']} its={x['iterations']} "
+            f"relres={x['rel_residual']:.2e} {x['message']}")
+    assert all(x["status"] in (0, 1) for x in res), [x["message"] for x in res if x["status"] < 0]
+    assert all(x["iterations"] >= 1 for x in res)
+    for a, b in zip(res[:6], res1):
+        assert np.array_equal(a["q"], b["q"])
