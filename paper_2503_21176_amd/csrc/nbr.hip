@@ -276,6 +276,11 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
     }
 }
 
+template <class T>
+__global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) out[k] = mk4<T>((T)-1.0e4, (T)-1.0e4, (T)-1.0e4, pack_int(0, T(0)));
+}
+
 // Export of the atom pairs closer than the list radius, by the canonical FP64
 // predicate; each unordered pair once. Rows are reserved with a global
 // counter; rows beyond `cap` are not written but still counted.
@@ -419,7 +424,13 @@ void nbr_build(Ctx& c, const double* pos) {
     PQ_HIP(hipStreamSynchronize(s));
     PQ_REQUIRE(rows >= 0, PQ_ERR_BOX, "atom list overflow");
     c.njrows = rows;
-    c.jl.ensure((size_t)std::max(1, rows) * CL * 4 * rsz(c));
+    // JL_TAIL far-away entries after the last row keep the pair kernel's
+    // look-ahead loads in bounds
+    c.jl.ensure(((size_t)rows * CL + JL_TAIL) * 4 * rsz(c));
+    if (c.fp64)
+        PQ_LAUNCH(k_far_entries<double>, 1, 256, 0, s, as<double4>(c.jl) + (size_t)rows * CL, JL_TAIL);
+    else
+        PQ_LAUNCH(k_far_entries<float>, 1, 256, 0, s, as<float4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     if (c.fp64)
         PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
                   c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));

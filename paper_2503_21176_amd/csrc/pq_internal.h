@@ -172,6 +172,7 @@ struct DBuf {
 };
 
 constexpr int CL = 8;           // atoms per cluster
+constexpr int JL_TAIL = 256;    // padding entries after the atom-level j lists
 constexpr int RED_BLOCKS = 512; // blocks of the FP64 partial-sum reductions
 
 // Geometry of the cluster (column) decomposition used by the neighbour list.
