@@ -136,15 +136,19 @@ __global__ void k_pme_weights(int n, const V4<T>* __restrict__ pme_frac, T* __re
 // takes one atom per step, lane (y, z) updating stencil row (y, z): the
 // updates of one step hit distinct addresses, so plain read-modify-writes
 // replace atomics; the copies are summed at the end. No atomics at all.
+// A wavefront first loads a batch of up to SPREAD_BATCH of its atoms (weights,
+// base index, charge; one atom per lane) into an LDS table, so its update
+// steps wait on LDS only.
+constexpr int SPREAD_BATCH = 16;
 template <int P, class T>
 __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __restrict__ brick_start,
-                                                      const int* __restrict__ pme_idx,
                                                       const V4<T>* __restrict__ pme_frac,
-                                                      const T* __restrict__ pme_w, const double* __restrict__ q,
+                                                      const T* __restrict__ pme_w, const T* __restrict__ qbrick,
                                                       T* __restrict__ stage) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
     __shared__ T lds[4][R3];
+    __shared__ T tab[4][SPREAD_BATCH][32];   // per atom: weights x, y, z (8 each), base, charge
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
@@ -156,26 +160,43 @@ __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __res
     const int ty = lane & 7, tz = lane >> 3;
     const bool active = (ty < P) && (tz < P);
     T* my = lds[wv];
-    for (int k = s0 + wv; k < s1; k += 4) {
-        const V4<T> f4 = pme_frac[k];
-        const T qq = (T)q[pme_idx[k]];
-        const T* wk = pme_w + (size_t)k * 24;
-        const int pk = unpack_int(f4.w);
-        const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
-        T wx[P];
+    T(*tb)[32] = tab[wv];
+    // the wave's atoms are s0 + wv, s0 + wv + 4, ...
+    for (int k0 = s0 + wv; k0 < s1; k0 += 4 * SPREAD_BATCH) {
+        const int nb = min(SPREAD_BATCH, (s1 - k0 + 3) / 4);
+        if (lane < nb) {
+            const int k = k0 + 4 * lane;
+            const V4<T>* wk = reinterpret_cast<const V4<T>*>(pme_w + (size_t)k * 24);
+            T* row = tb[lane];
 #pragma unroll
-        for (int t = 0; t < P; ++t) wx[t] = wk[t];
-        if (active) {
-            const T c = qq * wk[8 + ty] * wk[16 + tz];
-            T* row = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
-            T v[P];
-#pragma unroll
-            for (int tx = 0; tx < P; ++tx) v[tx] = row[-tx];
-#pragma unroll
-            for (int tx = 0; tx < P; ++tx) row[-tx] = fma(c, wx[tx], v[tx]);
+            for (int u = 0; u < 6; ++u) {
+                const V4<T> w4 = wk[u];
+                row[4 * u + 0] = w4.x;
+                row[4 * u + 1] = w4.y;
+                row[4 * u + 2] = w4.z;
+                row[4 * u + 3] = w4.w;
+            }
+            row[24] = pme_frac[k].w;
+            row[25] = qbrick[k];
         }
-        // the next atom may update the same rows
+        // the table is written and read by different lanes
         __builtin_amdgcn_wave_barrier();
+        for (int i = 0; i < nb; ++i) {
+            const T* at = tb[i];
+            const int pk = unpack_int(at[24]);
+            const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
+            if (active) {
+                const T c = at[25] * at[8 + ty] * at[16 + tz];
+                T* rowp = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
+                T v[P];
+#pragma unroll
+                for (int tx = 0; tx < P; ++tx) v[tx] = rowp[-tx];
+#pragma unroll
+                for (int tx = 0; tx < P; ++tx) rowp[-tx] = fma(c, at[tx], v[tx]);
+            }
+            // the next atom may update the same rows
+            __builtin_amdgcn_wave_barrier();
+        }
     }
     __syncthreads();
     T* out = stage + (size_t)bid * R3;
@@ -240,7 +261,7 @@ __global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const T* __rest
 template <int P, bool FORCE, class T>
 __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
                                                 const int* __restrict__ pme_idx, const V4<T>* __restrict__ pme_frac,
-                                                const double* __restrict__ q, const T* __restrict__ grid,
+                                                const T* __restrict__ qbrick, const T* __restrict__ grid,
                                                 T* __restrict__ phi_out, V4<T>* __restrict__ f_out) {
     constexpr int R = PME_B + P - 1;
     __shared__ T lds[R * R * R];
@@ -270,7 +291,9 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         const bool valid = k < s1;
         T phi = 0, gxs = 0, gys = 0, gzs = 0;
         int i = -1;
+        T qq = 0;
         if (valid) {
+            qq = qbrick[k];
             const V4<T> f4 = pme_frac[k];
             i = pme_idx[k];
             const int pk = unpack_int(f4.w);
@@ -311,10 +334,7 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         }
         if (valid && sub == 0) {
             phi_out[i] = phi;
-            if (FORCE) {
-                const T qq = (T)q[i];
-                f_out[i] = mk4<T>(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, T(0));
-            }
+            if (FORCE) f_out[i] = mk4<T>(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, T(0));
         }
     }
 }
@@ -376,6 +396,7 @@ void pme_setup(Ctx& c) {
     c.brick_fill.ensure(c.nbrick);
     c.brick_start.ensure(c.nbrick + 1);
     c.pme_idx.ensure(n);
+    c.qbrick.ensure((size_t)n * rsz(c));
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     c.grid.ensure(ng * rsz(c));
     const int R = PME_B + c.P - 1;
@@ -394,8 +415,8 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
     PmeGeo G = geo(c);
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
-    PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-              as<T>(c.pme_w), q, as<T>(c.stage));
+    PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac), as<T>(c.pme_w),
+              as<T>(c.qbrick), as<T>(c.stage));
     PQ_LAUNCH((k_spread_reduce<P, T>), std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, as<T>(c.stage),
               as<T>(c.grid));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD + 1], s));
@@ -405,10 +426,10 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER], s));
     if (force)
         PQ_LAUNCH((k_gather<P, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  q, as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+                  as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     else
         PQ_LAUNCH((k_gather<P, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  q, as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+                  as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER + 1], s));
 }
 

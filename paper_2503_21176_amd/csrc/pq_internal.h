@@ -243,6 +243,7 @@ struct Ctx {
     int nb[3] = {0, 0, 0}, nbrick = 0;
     DBuf<int> brick_of, brick_cnt, brick_start, brick_fill;
     DBuf<int> pme_idx;       // brick-ordered original indices
+    DBuf<unsigned char> qbrick;   // T: charges in brick order (staged per evaluation)
     DBuf<unsigned char> pme_frac; // V4<T>: fractional parts + packed base index
     DBuf<unsigned char> pme_w;    // T: B-spline weights per atom, 3 x 8 (brick order)
     DBuf<unsigned char> grid;     // T: real grid K1*K2*K3 (x fastest)
