@@ -220,19 +220,25 @@ pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const do
  * reciprocal-space kernels that run concurrently on the context's other
  * stream. Every shape gives bitwise-identical results. */
 typedef struct pq_tune_result {
-    int32_t pair_wg_per_cu;   /* chosen shape (0 or workgroups per CU)                 */
-    int32_t candidates;       /* shapes timed                                          */
-    double ms;                /* mean phi+F evaluation time of the chosen shape, ms    */
-    double ms_default;        /* the same for shape 0                                  */
+    int32_t pair_wg_per_cu;   /* chosen pair-kernel shape (0 or workgroups per CU)     */
+    int32_t candidates;       /* configurations timed                                  */
+    double ms;                /* mean phi+F evaluation time of the choice, ms          */
+    double ms_default;        /* the same for shape 0 and the default FFT tiles        */
+    int32_t fft_lds_bytes;    /* LDS bytes per FFT ping-pong buffer (0: default 18432); */
+                              /* smaller tiles let FFT workgroups run beside the pair  */
+                              /* kernel; the results do not depend on it               */
+    int32_t reserved;
 } pq_tune_result;
 
-/* Times the pair-kernel shapes 0, 1, 2, 3, 4, 6, 8 on `reps` (1..1000)
- * potential + force evaluations each, after one warm-up, of the current system
- * with charges q (device, n), and keeps the fastest for this context (also
- * across later pq_set_system calls). Phase timing must be off. Host-
- * synchronising; out may be NULL. */
+/* Times the pair-kernel shapes 0, 1, 2, 3, 4, 6, 8 jointly with FFT buffer
+ * sizes of 18432, 9216 and 4608 bytes on `reps` (1..1000) potential + force
+ * evaluations each, after one warm-up, of the current system with charges q
+ * (device, n), and keeps the fastest for this context (also across later
+ * pq_set_system calls). Phase timing must be off. Host-synchronising; out may
+ * be NULL. */
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out);
-/* Applies a stored choice (only pair_wg_per_cu is read; 0..64). */
+/* Applies a stored choice (pair_wg_per_cu in 0..64; fft_lds_bytes 0 or
+ * 1024..65536). */
 pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
 
 /* ---- continuous-batching QEQ server -------------------------------------- */

@@ -1,6 +1,7 @@
 // C ABI of the pmeqeq library: contexts, systems and Coulomb evaluation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -73,8 +74,13 @@ void ensure_eval(Ctx& c) {
     c.f_r.ensure(n * 4 * rsz(c));
     c.f_k.ensure(n * 4 * rsz(c));
     c.scal.ensure(64);
-    // reduction partials: sized once for every reduction the solvers issue
-    c.part.ensure((size_t)RED_BLOCKS * 520 + 4096);
+    // reduction partials: sized once for every reduction the solvers issue and
+    // the PME energy partials (one per spectral column), so nothing grows while
+    // an evaluation is being recorded into a graph
+    size_t need = (size_t)RED_BLOCKS * 520 + 4096;
+    if (c.prm.method == PQ_METHOD_PME)
+        need = std::max(need, (size_t)(c.prm.grid[0] / 2 + 1) * (size_t)c.prm.grid[1] + 16);
+    c.part.ensure(need);
 }
 
 // Phase events of one timed evaluation (null when timing is off).
@@ -278,11 +284,15 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     PQ_HIP(hipEventCreate(&e0));
     PQ_HIP(hipEventCreate(&e1));
     const int cand[] = {0, 1, 2, 3, 4, 6, 8};
-    int best = 0;
+    const int budgets[] = {18432, 9216, 4608};
+    int best = 0, best_b = 18432, ntried = 0;
     double best_ms = 1e300, ms0 = 0.0;
     try {
+        for (int bgt : budgets)
         for (int k : cand) {
             c.pair_grid = k * ncu;
+            c.fft_budget = bgt;
+            ++ntried;
             coulomb_eval(c, q, phi.p, f.p, e.p, s);
             PQ_HIP(hipEventRecord(e0, s));
             for (int r = 0; r < reps; ++r) coulomb_eval(c, q, phi.p, f.p, e.p, s);
@@ -291,10 +301,11 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
             float el = 0.f;
             PQ_HIP(hipEventElapsedTime(&el, e0, e1));
             const double ms = (double)el / reps;
-            if (k == 0) ms0 = ms;
+            if (k == 0 && bgt == 18432) ms0 = ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = k;
+                best_b = bgt;
             }
         }
     } catch (...) {
@@ -305,12 +316,15 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c.pair_grid = best * ncu;
+    c.fft_budget = best_b;
     c.tune_ms = best_ms;
     if (out) {
         out->pair_wg_per_cu = best;
-        out->candidates = (int32_t)(sizeof(cand) / sizeof(cand[0]));
+        out->candidates = ntried;
         out->ms = best_ms;
         out->ms_default = ms0;
+        out->fft_lds_bytes = best_b;
+        out->reserved = 0;
     }
     return PQ_OK;
     PQ_API_END
@@ -320,7 +334,10 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && t != nullptr, PQ_ERR_INVALID, "ctx and t must not be NULL");
     PQ_REQUIRE(t->pair_wg_per_cu >= 0 && t->pair_wg_per_cu <= 64, PQ_ERR_INVALID, "pair_wg_per_cu must be in 0..64");
+    PQ_REQUIRE(t->fft_lds_bytes == 0 || (t->fft_lds_bytes >= 1024 && t->fft_lds_bytes <= 65536), PQ_ERR_INVALID,
+               "fft_lds_bytes must be 0 or in 1024..65536");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    c.fft_budget = t->fft_lds_bytes ? t->fft_lds_bytes : 18432;
     PQ_HIP(hipSetDevice(c.device));
     int ncu = 0;
     PQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));

@@ -11,9 +11,11 @@
 //      (one read and one write for the three steps);
 //   y inverse; x: two Hermitian half spectra combined into one complex
 //      sequence, inverse FFT, real and imaginary parts are the two rows.
-// Each 1-D transform runs in LDS as mixed-radix (2, 3, 4, 5) Stockham passes
-// (self-sorting, ping-pong buffers), twiddles from FP64 tables rounded to the
-// bulk precision.
+// Each 1-D transform runs in LDS as mixed-radix Stockham passes (self-sorting,
+// ping-pong buffers) with radices 16, 8, 9, 4, 2, 3, 5: the composite ones
+// (16 = 4 x 4, 8 = 2 x 4, 9 = 3 x 3) are done in registers, so 144 = 16 x 9
+// takes two passes. Twiddles come from FP64 tables rounded to the bulk
+// precision and are staged in LDS with the data.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -25,7 +27,7 @@
 namespace pq {
 
 struct FftDev {
-    int n, nst;
+    int n, nst, ntw;
     int radix[FFT_MAX_STAGES];
     int ns[FFT_MAX_STAGES];
     int twoff[FFT_MAX_STAGES];
@@ -56,15 +58,98 @@ __device__ __forceinline__ C mul_i(C a) {
     return SIGN > 0 ? cmk<C>(-a.y, a.x) : cmk<C>(a.y, -a.x);
 }
 
+// cos and sin of 2 pi j / N for the composite radices
+template <int N>
+__device__ __forceinline__ constexpr double twc(int j) {
+    if constexpr (N == 8) {
+        constexpr double c[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
+                                 -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
+        return c[j];
+    } else if constexpr (N == 9) {
+        constexpr double c[9] = {1.0, 0.76604444311897803520, 0.17364817766693034885, -0.5, -0.93969262078590838405,
+                                 -0.93969262078590838405, -0.5, 0.17364817766693034885, 0.76604444311897803520};
+        return c[j];
+    } else {
+        constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                  0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                  -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                                  0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+        return c[j];
+    }
+}
+template <int N>
+__device__ __forceinline__ constexpr double tws(int j) {
+    if constexpr (N == 8) {
+        constexpr double s[8] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440,
+                                 0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440};
+        return s[j];
+    } else if constexpr (N == 9) {
+        constexpr double s[9] = {0.0, 0.64278760968653932632, 0.98480775301220805936, 0.86602540378443864676,
+                                 0.34202014332566873304, -0.34202014332566873304, -0.86602540378443864676,
+                                 -0.98480775301220805936, -0.64278760968653932632};
+        return s[j];
+    } else {
+        constexpr double s[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                                  1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                                  0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                                  -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173};
+        return s[j];
+    }
+}
+
+template <int R, int SIGN, class C>
+__device__ __forceinline__ void dft(C* v);
+
+// In-register DFT of length N = P Q by Cooley-Tukey: P-point DFTs over the
+// inputs q + Q p, twiddles W_N^(q k1), Q-point DFTs, output k1 + P k2.
+template <int P, int Q, int SIGN, class C>
+__device__ __forceinline__ void dft_pq(C* v) {
+    using T = decltype(C::x);
+    constexpr int N = P * Q;
+    C y[N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        C t[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) t[p] = v[q + Q * p];
+        dft<P, SIGN>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < P; ++k1) {
+            const int e = (q * k1) % N;
+            if (e == 0) {
+                y[k1 * Q + q] = t[k1];
+            } else {
+                const C w = cmk<C>(T(twc<N>(e)), T(SIGN * tws<N>(e)));
+                y[k1 * Q + q] = cmul(t[k1], w);
+            }
+        }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+        C u[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) u[q] = y[k1 * Q + q];
+        dft<Q, SIGN>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < Q; ++k2) v[k1 + P * k2] = u[k2];
+    }
+}
+
 // In-register DFT of length R with kernel exp(SIGN 2 pi i r s / R).
 template <int R, int SIGN, class C>
 __device__ __forceinline__ void dft(C* v) {
     using T = decltype(C::x);
-    if (R == 2) {
+    if constexpr (R == 8) {
+        dft_pq<2, 4, SIGN>(v);
+    } else if constexpr (R == 9) {
+        dft_pq<3, 3, SIGN>(v);
+    } else if constexpr (R == 16) {
+        dft_pq<4, 4, SIGN>(v);
+    } else if constexpr (R == 2) {
         C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
-    } else if (R == 3) {
+    } else if constexpr (R == 3) {
         const T c = T(-0.5), s = T(0.86602540378443864676);
         C t1 = cadd(v[1], v[2]), t2 = csub(v[1], v[2]);
         C a = cmk<C>(v[0].x + c * t1.x, v[0].y + c * t1.y);
@@ -72,14 +157,14 @@ __device__ __forceinline__ void dft(C* v) {
         v[0] = cadd(v[0], t1);
         v[1] = cadd(a, b);
         v[2] = csub(a, b);
-    } else if (R == 4) {
+    } else if constexpr (R == 4) {
         C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
         C s13 = cadd(v[1], v[3]), d13 = mul_i<SIGN>(csub(v[1], v[3]));
         v[0] = cadd(s02, s13);
         v[2] = csub(s02, s13);
         v[1] = cadd(d02, d13);
         v[3] = csub(d02, d13);
-    } else if (R == 5) {
+    } else if constexpr (R == 5) {
         const T c1 = T(0.30901699437494742410), c2 = T(-0.80901699437494742410);
         const T s1 = T(0.95105651629515357212), s2 = T(0.58778525229247312917);
         C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
@@ -140,7 +225,10 @@ __device__ C* fft_lds(C* a, C* b, const FftDev& pl, const C* __restrict__ tw, in
                 case 2: butterfly<2, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
                 case 3: butterfly<3, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
                 case 4: butterfly<4, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
-                default: butterfly<5, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
+                case 5: butterfly<5, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
+                case 8: butterfly<8, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
+                case 9: butterfly<9, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
+                default: butterfly<16, SIGN>(a, b, twst, j, m, Ns, s, es, ss); break;
             }
         }
         __syncthreads();
@@ -161,6 +249,8 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(FftDev pl, const V2<T>* __res
     const int n = pl.n, X = n / 2 + 1;
     C* a = sm;
     C* b = sm + np * n;
+    C* tl = sm + 2 * np * n;   // twiddles of this axis
+    for (int i = threadIdx.x; i < pl.ntw; i += blockDim.x) tl[i] = tw[i];
     const int p0 = blockIdx.x * np;
     for (int idx = threadIdx.x; idx < np * n; idx += blockDim.x) {
         const int s = idx / n, k = idx % n;
@@ -170,7 +260,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(FftDev pl, const V2<T>* __res
         a[s * n + k] = cmk<C>(re, im);
     }
     __syncthreads();
-    const C* o = fft_lds<-1, false>(a, b, pl, tw, np, 1, n);
+    const C* o = fft_lds<-1, false>(a, b, pl, tl, np, 1, n);
     const T h = T(0.5);
     for (int idx = threadIdx.x; idx < np * X; idx += blockDim.x) {
         const int s = idx / X, m = idx % X;
@@ -193,6 +283,8 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(FftDev pl, const V2<T>* __res
     const int n = pl.n, X = n / 2 + 1;
     C* a = sm;
     C* b = sm + np * n;
+    C* tl = sm + 2 * np * n;   // twiddles of this axis
+    for (int i = threadIdx.x; i < pl.ntw; i += blockDim.x) tl[i] = tw[i];
     const int p0 = blockIdx.x * np;
     for (int idx = threadIdx.x; idx < np * n; idx += blockDim.x) {
         const int s = idx / n, m = idx % n;
@@ -210,7 +302,7 @@ __global__ __launch_bounds__(256) void k_fft_x_c2r(FftDev pl, const V2<T>* __res
         a[s * n + m] = cmk<C>(A.x - B.y, A.y + B.x);
     }
     __syncthreads();
-    const C* o = fft_lds<1, false>(a, b, pl, tw, np, 1, n);
+    const C* o = fft_lds<1, false>(a, b, pl, tl, np, 1, n);
     for (int idx = threadIdx.x; idx < np * n; idx += blockDim.x) {
         const int s = idx / n, k = idx % n;
         const int r0 = 2 * (p0 + s), r1 = r0 + 1;
@@ -239,10 +331,11 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
     using C = V2<T>;
     extern __shared__ __align__(16) unsigned char smraw[];
     C* sm = reinterpret_cast<C*>(smraw);
-    __shared__ double red[4];
     const int n = pl.n;
     C* a = sm;
     C* b = sm + n * tx;
+    C* tl = sm + 2 * n * tx;   // twiddles of this axis
+    for (int i = threadIdx.x; i < pl.ntw; i += blockDim.x) tl[i] = tw[i];
     const int mx0 = blockIdx.x * tx;
     const int o = blockIdx.y;
     C* base = spec + (size_t)o * ostride;
@@ -252,29 +345,43 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
         a[idx] = (mx < X) ? base[(size_t)k * estride + mx] : cmk<C>(T(0), T(0));
     }
     __syncthreads();
-    C* r = fft_lds<SIGN, true>(a, b, pl, tw, tx, tx, 1);
+    C* r = fft_lds<SIGN, true>(a, b, pl, tl, tx, tx, 1);
     if (CONV) {
-        // r holds F(mx, my = o, mz = k); multiply by G and sum the energy
-        double e = 0.0;
+        // r holds F(mx, my = o, mz = k). Energy: one partial per column
+        // (mx, my) from 16 threads (thread u sums mz = u, u + 16, ... in
+        // order, then a fixed xor tree over the 16), so E_rec does not depend
+        // on the tiling (tx <= 16); then multiply by G.
         const int my = o;
+        {
+            const int s = threadIdx.x >> 4, u = threadIdx.x & 15;
+            const int mx = mx0 + s;
+            double e = 0.0;
+            if (s < tx && mx < X) {
+                const double wgt = (mx == 0 || (2 * mx == cv.K0)) ? 1.0 : 2.0;
+                const double tx0 = cv.scale * cv.T0[mx] * cv.T1[my], sx0 = cv.S0[mx] + cv.S1[my];
+                for (int mz = u; mz < n; mz += 16) {
+                    if ((mx | my | mz) == 0) continue;
+                    const double g = tx0 * cv.T2[mz] / (sx0 + cv.S2[mz]);
+                    const C v = r[mz * tx + s];
+                    e += wgt * g * ((double)v.x * v.x + (double)v.y * v.y);
+                }
+            }
+#pragma unroll
+            for (int w = 8; w > 0; w >>= 1) e += __shfl_xor(e, w, 16);
+            if (u == 0 && s < tx && mx < X) epart[(size_t)my * X + mx] = 0.5 * e;
+        }
+        __syncthreads();
         for (int idx = threadIdx.x; idx < n * tx; idx += blockDim.x) {
             const int mz = idx / tx, s = idx % tx;
             const int mx = mx0 + s;
             T gk = T(0);
-            if (mx < X && (mx | my | mz) != 0) {
-                const double g = cv.scale * cv.T0[mx] * cv.T1[my] * cv.T2[mz] / (cv.S0[mx] + cv.S1[my] + cv.S2[mz]);
-                gk = (T)g;
-                const C v = r[idx];
-                const double wgt = (mx == 0 || (2 * mx == cv.K0)) ? 1.0 : 2.0;
-                e += wgt * g * ((double)v.x * v.x + (double)v.y * v.y);
-            }
+            if (mx < X && (mx | my | mz) != 0)
+                gk = (T)(cv.scale * cv.T0[mx] * cv.T1[my] * cv.T2[mz] / (cv.S0[mx] + cv.S1[my] + cv.S2[mz]));
             r[idx] = cmk<C>(r[idx].x * gk, r[idx].y * gk);
         }
-        e = block_sum<256>(e, red);
-        if (threadIdx.x == 0) epart[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = 0.5 * e;
         __syncthreads();
         C* other = (r == a) ? b : a;
-        r = fft_lds<-SIGN, true>(r, other, pl, tw, tx, tx, 1);
+        r = fft_lds<-SIGN, true>(r, other, pl, tl, tx, tx, 1);
     }
     for (int idx = threadIdx.x; idx < n * tx; idx += blockDim.x) {
         const int k = idx / tx, s = idx % tx;
@@ -296,6 +403,18 @@ __global__ void k_sum_part(const double* __restrict__ part, int n, double* __res
 // ---------------------------------------------------------------------------
 static void factorize(int n, std::vector<int>& r) {
     r.clear();
+    while (n % 16 == 0) {
+        r.push_back(16);
+        n /= 16;
+    }
+    if (n % 8 == 0) {
+        r.push_back(8);
+        n /= 8;
+    }
+    while (n % 9 == 0) {
+        r.push_back(9);
+        n /= 9;
+    }
     while (n % 4 == 0) {
         r.push_back(4);
         n /= 4;
@@ -345,6 +464,7 @@ static FftDev to_dev(const Fft1D& f) {
     FftDev d;
     d.n = f.n;
     d.nst = f.nst;
+    d.ntw = f.ntw;
     for (int i = 0; i < FFT_MAX_STAGES; ++i) {
         d.radix[i] = f.radix[i];
         d.ns[i] = f.ns[i];
@@ -388,6 +508,7 @@ void fft_setup(Ctx& c) {
             ns *= R;
         }
         for (int st = f.nst; st < FFT_MAX_STAGES; ++st) f.radix[st] = f.ns[st] = f.twoff[st] = 0;
+        f.ntw = (int)tw.size() / 2 - off[d];
     }
     if (c.fp64)
         upload_twiddles<double>(c, tw, off);
@@ -424,9 +545,11 @@ void fft_setup(Ctx& c) {
     c.inf.scale = 1.0 / (PI * V);
 }
 
-// LDS budget of one FFT workgroup: two ping-pong buffers of 18 KiB.
-static int col_tile(int n, size_t esz) { return std::max(1, std::min(16, (int)(18432 / (n * esz)))); }
-static int row_pairs(int n, size_t esz) { return std::max(1, (int)(18432 / (n * esz))); }
+// LDS budget of one FFT workgroup: two ping-pong buffers of `budget` bytes
+// each (a tuning choice: smaller tiles leave room for kernels running beside
+// the FFT; every tile gives the same results).
+static int col_tile(int n, size_t esz, int budget) { return std::max(1, std::min(16, (int)(budget / (n * esz)))); }
+static int row_pairs(int n, size_t esz, int budget) { return std::max(1, (int)(budget / (n * esz))); }
 
 template <class T>
 static void fft_convolve_t(Ctx& c, hipStream_t s) {
@@ -442,26 +565,27 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     T* grid = as<T>(c.grid);
     C* spec = as<C>(c.spec);
     ConvArgs cv{c.inf.T[0], c.inf.T[1], c.inf.T[2], c.inf.S[0], c.inf.S[1], c.inf.S[2], c.inf.scale, K0};
-    const int np = row_pairs(K0, esz);
+    const int np = row_pairs(K0, esz, c.fft_budget);
     const int npairs = (nrows + 1) / 2;
     // x forward
-    PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, 2 * np * K0 * esz, s, px, tw0, nrows, np, grid, spec);
+    PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, grid, spec);
     // y forward: sequences over (z, mx), elements stride X
-    const int ty = col_tile(K1, esz);
-    PQ_LAUNCH((k_fft_col<-1, false, T>), dim3(cdiv(X, ty), K2), 256, 2 * K1 * ty * esz, s, py, tw1, X, ty,
+    const int ty = col_tile(K1, esz, c.fft_budget);
+    PQ_LAUNCH((k_fft_col<-1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X, ty,
               (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
     // z forward + convolution + z inverse: sequences over (y, mx), elements stride X*K1
-    const int tz = col_tile(K2, esz);
+    const int tz = col_tile(K2, esz, c.fft_budget);
     const dim3 gz(cdiv(X, tz), K1);
-    c.part.ensure((size_t)gz.x * gz.y + 16);
-    PQ_LAUNCH((k_fft_col<-1, true, T>), gz, 256, 2 * K2 * tz * esz, s, pz, tw2, X, tz, (size_t)X * K1, (size_t)X,
+    // one energy partial per spectral column (mx, my); sized by set_system
+    PQ_REQUIRE(c.part.n >= (size_t)X * K1 + 16, PQ_ERR_STATE, "energy partials not sized");
+    PQ_LAUNCH((k_fft_col<-1, true, T>), gz, 256, (2 * K2 * tz + pz.ntw) * esz, s, pz, tw2, X, tz, (size_t)X * K1, (size_t)X,
               spec, cv, c.part.p);
-    PQ_LAUNCH(k_sum_part, 1, 256, 0, s, c.part.p, (int)(gz.x * gz.y), c.scal.p + 1);
+    PQ_LAUNCH(k_sum_part, 1, 256, 0, s, c.part.p, X * K1, c.scal.p + 1);
     // y inverse
-    PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, 2 * K1 * ty * esz, s, py, tw1, X, ty, (size_t)X,
+    PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X, ty, (size_t)X,
               (size_t)X * K1, spec, cv, (double*)nullptr);
     // x inverse
-    PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, 2 * np * K0 * esz, s, px, tw0, nrows, np, spec, grid);
+    PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, spec, grid);
 }
 
 // grid (real, Q) -> grid (real, psi = conv(Q)); E_rec (without KE) into c.scal[1]

@@ -140,19 +140,23 @@ __global__ void k_pme_weights(int n, const V4<T>* __restrict__ pme_frac, T* __re
 // base index, charge; one atom per lane) into an LDS table, so its update
 // steps wait on LDS only.
 constexpr int SPREAD_BATCH = 16;
+#ifndef SPREAD_WAVES
+#define SPREAD_WAVES 2
+#endif
+constexpr int SW = SPREAD_WAVES;   // wavefronts (and private region copies) per brick
 template <int P, class T>
-__global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __restrict__ brick_start,
+__global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* __restrict__ brick_start,
                                                       const V4<T>* __restrict__ pme_frac,
                                                       const T* __restrict__ pme_w, const T* __restrict__ qbrick,
                                                       T* __restrict__ stage) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
-    __shared__ T lds[4][R3];
-    __shared__ T tab[4][SPREAD_BATCH][32];   // per atom: weights x, y, z (8 each), base, charge
+    __shared__ T lds[SW][R3];
+    __shared__ T tab[SW][SPREAD_BATCH][32];   // per atom: weights x, y, z (8 each), base, charge
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
-    for (int t = threadIdx.x; t < 4 * R3; t += 256) (&lds[0][0])[t] = T(0);
+    for (int t = threadIdx.x; t < SW * R3; t += 64 * SW) (&lds[0][0])[t] = T(0);
     __syncthreads();
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
     const int lane = threadIdx.x & 63;
@@ -161,11 +165,11 @@ __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __res
     const bool active = (ty < P) && (tz < P);
     T* my = lds[wv];
     T(*tb)[32] = tab[wv];
-    // the wave's atoms are s0 + wv, s0 + wv + 4, ...
-    for (int k0 = s0 + wv; k0 < s1; k0 += 4 * SPREAD_BATCH) {
-        const int nb = min(SPREAD_BATCH, (s1 - k0 + 3) / 4);
+    // the wave's atoms are s0 + wv, s0 + wv + SW, ...
+    for (int k0 = s0 + wv; k0 < s1; k0 += SW * SPREAD_BATCH) {
+        const int nb = min(SPREAD_BATCH, (s1 - k0 + SW - 1) / SW);
         if (lane < nb) {
-            const int k = k0 + 4 * lane;
+            const int k = k0 + SW * lane;
             const V4<T>* wk = reinterpret_cast<const V4<T>*>(pme_w + (size_t)k * 24);
             T* row = tb[lane];
 #pragma unroll
@@ -200,7 +204,12 @@ __global__ __launch_bounds__(256) void k_spread_stage(PmeGeo G, const int* __res
     }
     __syncthreads();
     T* out = stage + (size_t)bid * R3;
-    for (int t = threadIdx.x; t < R3; t += 256) out[t] = (lds[0][t] + lds[1][t]) + (lds[2][t] + lds[3][t]);
+    for (int t = threadIdx.x; t < R3; t += 64 * SW) {
+        T v = lds[0][t];
+#pragma unroll
+        for (int w = 1; w < SW; ++w) v += lds[w][t];
+        out[t] = v;
+    }
 }
 
 // Bricks b (and local coordinates l in [0, R)) whose region holds grid
@@ -415,7 +424,7 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
     PmeGeo G = geo(c);
     const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
-    PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac), as<T>(c.pme_w),
+    PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 64 * SW, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac), as<T>(c.pme_w),
               as<T>(c.qbrick), as<T>(c.stage));
     PQ_LAUNCH((k_spread_reduce<P, T>), std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, as<T>(c.stage),
               as<T>(c.grid));

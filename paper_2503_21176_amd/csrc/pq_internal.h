@@ -189,6 +189,7 @@ constexpr int FFT_MAX_STAGES = 12;
 struct Fft1D {
     int n = 0;
     int nst = 0;
+    int ntw = 0;                // twiddles of all stages
     int radix[FFT_MAX_STAGES];
     int ns[FFT_MAX_STAGES];     // product of the radices of earlier stages
     int twoff[FFT_MAX_STAGES];  // offset of the stage's twiddles in the table
@@ -269,6 +270,7 @@ struct Ctx {
 
     // --- tuned launch shapes (pq_autotune) ---
     int pair_grid = 0;       // pair kernel workgroups (0: one wavefront per i-cluster)
+    int fft_budget = 18432;  // bytes per FFT ping-pong buffer (sets the tile sizes)
     double tune_ms = 0.0;    // evaluation time of the chosen shape
 
     // --- second stream: the pair kernel overlaps the PME chain ---

@@ -58,7 +58,7 @@ def test_result_and_tune_struct_layouts():
     # q pointer, energy, solve info (24), status + pad, three doubles, message[256]
     assert P.Result.message.offset == 8 + 8 + 24 + 8 + 24
     assert ctypes.sizeof(P.Result) == 8 + 8 + 24 + 8 + 24 + 256
-    assert ctypes.sizeof(P.TuneResult) == 24
+    assert ctypes.sizeof(P.TuneResult) == 32 and P.TuneResult.fft_lds_bytes.offset == 24
 
 
 def test_request_footprint_is_host_only_and_sane():
