@@ -81,6 +81,7 @@ void ensure_eval(Ctx& c) {
     if (c.prm.method == PQ_METHOD_PME)
         need = std::max(need, (size_t)(c.prm.grid[0] / 2 + 1) * (size_t)c.prm.grid[1] + 16);
     c.part.ensure(need);
+    c.qpart.ensure(std::max<size_t>((size_t)c.ncl * CL, n) / 256 + 2);
 }
 
 // Phase events of one timed evaluation (null when timing is off).
@@ -126,7 +127,6 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     E.begin(PQ_PHASE_TOTAL);
     E.begin(PQ_PHASE_STAGE);
     stage_charges(c, q, s);
-    sum_vector(c, q, c.n, c.scal.p + 0, s);
     E.end(PQ_PHASE_STAGE);
     // the real-space pair kernel (ALU bound) runs on the context's second
     // stream, concurrently with the memory-bound reciprocal-space chain
@@ -151,7 +151,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     }
     stream_wait(s, c.ev_join);
     E.begin(PQ_PHASE_COMBINE);
-    combine(c, q, c.scal.p + 0, phi, force, energy, s);
+    combine(c, q, phi, force, energy, s);
     E.end(PQ_PHASE_COMBINE);
     E.end(PQ_PHASE_TOTAL);
     E.commit();

@@ -265,6 +265,8 @@ struct Ctx {
     DBuf<unsigned char> phi_r, phi_k;   // T per atom (original order, without KE)
     DBuf<unsigned char> f_r, f_k;       // V4<T> per atom
     DBuf<double> part;       // reduction partials
+    DBuf<double> qpart;      // total-charge partials of the charge-staging kernel
+    int nqpart = 0;
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
 
@@ -334,8 +336,8 @@ void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s);   // into c
 // vec.hip
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s);
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s);
-void combine(Ctx& c, const double* q, const double* Q, double* phi, double* force,
-             double* energy, hipStream_t s);
+// after stage_charges (which leaves the total-charge partials in c.qpart)
+void combine(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s);
 
 // high-level evaluation used by the ABI and the Krylov solvers (abi.cpp)
 void ensure_side(Ctx& c);   // creates the pair kernel's stream and fork/join events
