@@ -81,7 +81,7 @@ void ensure_eval(Ctx& c) {
     if (c.prm.method == PQ_METHOD_PME)
         need = std::max(need, (size_t)(c.prm.grid[0] / 2 + 1) * (size_t)c.prm.grid[1] + 16);
     c.part.ensure(need);
-    c.qpart.ensure(std::max<size_t>((size_t)c.ncl * CL, n) / 256 + 2);
+    c.qpart.ensure((size_t)RED_BLOCKS + 16);
 }
 
 // Phase events of one timed evaluation (null when timing is off).
@@ -123,6 +123,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     ensure_eval(c);
     const bool fo = force != nullptr;
+    c.want_energy = energy != nullptr;
     PhaseEvents E(c, s);
     E.begin(PQ_PHASE_TOTAL);
     E.begin(PQ_PHASE_STAGE);
@@ -136,6 +137,9 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     stream_wait(ps, c.ev_fork);
     E.begin(PQ_PHASE_PAIR, ps);
     pair_sum(c, fo, ps);
+    // the total charge (background term) is only needed by the final combine:
+    // summed after the pair kernel, off the reciprocal-space chain
+    sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
     E.end(PQ_PHASE_PAIR, ps);
     ev_record(c.ev_join, ps);
     if (c.prm.method == PQ_METHOD_PME) {

@@ -328,6 +328,7 @@ template <int SIGN, bool CONV, class T>
 __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restrict__ tw, int X, int tx,
                                                  size_t estride, size_t ostride, V2<T>* __restrict__ spec,
                                                  ConvArgs cv, double* __restrict__ epart) {
+    // CONV: epart == NULL skips the energy
     using C = V2<T>;
     extern __shared__ __align__(16) unsigned char smraw[];
     C* sm = reinterpret_cast<C*>(smraw);
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
         // order, then a fixed xor tree over the 16), so E_rec does not depend
         // on the tiling (tx <= 16); then multiply by G.
         const int my = o;
-        {
+        if (epart) {
             const int s = threadIdx.x >> 4, u = threadIdx.x & 15;
             const int mx = mx0 + s;
             double e = 0.0;
@@ -390,11 +391,20 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
     }
 }
 
-__global__ void k_sum_part(const double* __restrict__ part, int n, double* __restrict__ out) {
-    __shared__ double red[4];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
-    v = block_sum<256>(v, red);
+// Sum of n partials in a fixed order: thread t adds t, t + 1024, ... with four
+// independent accumulators (loads in flight together), then a block tree.
+__global__ __launch_bounds__(1024) void k_sum_part(const double* __restrict__ part, int n, double* __restrict__ out) {
+    __shared__ double red[16];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * 1024 < n; i += 4 * 1024) {
+        a0 += part[i];
+        a1 += part[i + 1024];
+        a2 += part[i + 2 * 1024];
+        a3 += part[i + 3 * 1024];
+    }
+    for (; i < n; i += 1024) a0 += part[i];
+    const double v = block_sum<1024>((a0 + a1) + (a2 + a3), red);
     if (threadIdx.x == 0) *out = v;
 }
 
@@ -579,8 +589,8 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     // one energy partial per spectral column (mx, my); sized by set_system
     PQ_REQUIRE(c.part.n >= (size_t)X * K1 + 16, PQ_ERR_STATE, "energy partials not sized");
     PQ_LAUNCH((k_fft_col<-1, true, T>), gz, 256, (2 * K2 * tz + pz.ntw) * esz, s, pz, tw2, X, tz, (size_t)X * K1, (size_t)X,
-              spec, cv, c.part.p);
-    PQ_LAUNCH(k_sum_part, 1, 256, 0, s, c.part.p, X * K1, c.scal.p + 1);
+              spec, cv, c.want_energy ? c.part.p : nullptr);
+    if (c.want_energy) PQ_LAUNCH(k_sum_part, 1, 1024, 0, s, c.part.p, X * K1, c.scal.p + 1);
     // y inverse
     PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X, ty, (size_t)X,
               (size_t)X * K1, spec, cv, (double*)nullptr);
@@ -589,6 +599,7 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
 }
 
 // grid (real, Q) -> grid (real, psi = conv(Q)); E_rec (without KE) into c.scal[1]
+// when c.want_energy
 void fft_convolve(Ctx& c, hipStream_t s) {
     if (c.fp64)
         fft_convolve_t<double>(c, s);

@@ -265,12 +265,12 @@ struct Ctx {
     DBuf<unsigned char> phi_r, phi_k;   // T per atom (original order, without KE)
     DBuf<unsigned char> f_r, f_k;       // V4<T> per atom
     DBuf<double> part;       // reduction partials
-    DBuf<double> qpart;      // total-charge partials of the charge-staging kernel
-    int nqpart = 0;
+    DBuf<double> qpart;      // partials of the total-charge sum (on the pair kernel's stream)
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
 
     // --- tuned launch shapes (pq_autotune) ---
+    bool want_energy = true; // the current evaluation reports energies (E_rec reduction)
     int pair_grid = 0;       // pair kernel workgroups (0: one wavefront per i-cluster)
     int fft_budget = 18432;  // bytes per FFT ping-pong buffer (sets the tile sizes)
     double tune_ms = 0.0;    // evaluation time of the chosen shape
@@ -335,8 +335,10 @@ void ewald_setup(Ctx& c);
 void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s);   // into c.phi_k, c.f_k
 // vec.hip
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s);
+// the same with a caller-provided partial buffer (>= RED_BLOCKS + 16 doubles)
+void sum_vector_into(const double* x, int64_t n, double* out, double* part, hipStream_t s);
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s);
-// after stage_charges (which leaves the total-charge partials in c.qpart)
+// after the total charge is in c.scal[0]
 void combine(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s);
 
 // high-level evaluation used by the ABI and the Krylov solvers (abi.cpp)

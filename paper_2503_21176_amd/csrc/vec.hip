@@ -61,6 +61,11 @@ void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, doubl
 }
 
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s) { reduce(c, x, nullptr, n, 0, 1.0, out, s); }
+void sum_vector_into(const double* x, int64_t n, double* out, double* part, hipStream_t s) {
+    const int nb = red_blocks(n);
+    PQ_LAUNCH(k_part_sum, nb, VB, 0, s, x, (const double*)nullptr, n, 0, part);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, part, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0);
+}
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
     reduce(c, x, y, n, 1, 1.0, out, s);
 }
@@ -69,23 +74,13 @@ void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out
 // phi_i = KE (phi_real + phi_rec + self_i + background), F_i = KE (F_real + F_rec)
 // part: 3 partial sums per block of q_i * (real, rec, self+bg) potentials.
 template <class T>
-__global__ __launch_bounds__(VB) void k_combine(int64_t n, const double* __restrict__ q,
-                                                const double* __restrict__ qpart, int nqpart,
+__global__ __launch_bounds__(VB) void k_combine(int64_t n, const double* __restrict__ q, const double* __restrict__ Q,
                                                 const T* __restrict__ pr, const V4<T>* __restrict__ fr,
                                                 const T* __restrict__ pk, const V4<T>* __restrict__ fk,
                                                 double cself, double cbg, double* __restrict__ phi,
                                                 double* __restrict__ force, double* __restrict__ part) {
     __shared__ double red[VB / 64];
-    __shared__ double qtot;
-    // total charge from the staging kernel's block partials (same order in every block)
-    {
-        double t = 0.0;
-        for (int i = threadIdx.x; i < nqpart; i += VB) t += qpart[i];
-        t = block_sum<VB>(t, red);
-        if (threadIdx.x == 0) qtot = t;
-        __syncthreads();
-    }
-    const double Qs = qtot;
+    const double Qs = *Q;
     double e0 = 0.0, e1 = 0.0, e2 = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
         const double qi = q[i];
@@ -141,10 +136,10 @@ void combine(Ctx& c, const double* q, double* phi, double* force, double* energy
     const double cself = -2.0 * a / std::sqrt(PI);
     const double cbg = -PI / (V * a * a);
     if (c.fp64)
-        PQ_LAUNCH(k_combine<double>, nb, VB, 0, s, n, q, c.qpart.p, c.nqpart, as<double>(c.phi_r), as<double4>(c.f_r),
+        PQ_LAUNCH(k_combine<double>, nb, VB, 0, s, n, q, c.scal.p + 0, as<double>(c.phi_r), as<double4>(c.f_r),
                   as<double>(c.phi_k), as<double4>(c.f_k), cself, cbg, phi, force, c.part.p);
     else
-        PQ_LAUNCH(k_combine<float>, nb, VB, 0, s, n, q, c.qpart.p, c.nqpart, as<float>(c.phi_r), as<float4>(c.f_r),
+        PQ_LAUNCH(k_combine<float>, nb, VB, 0, s, n, q, c.scal.p + 0, as<float>(c.phi_r), as<float4>(c.f_r),
                   as<float>(c.phi_k),
                   as<float4>(c.f_k), cself, cbg, phi, force, c.part.p);
     if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.part.p, nb, c.scal.p + 1, energy);
