@@ -44,7 +44,8 @@ typedef enum pq_status {
     PQ_ERR_CAPACITY = -3,      /* caller buffer too small; required size reported */
     PQ_ERR_NOMEM = -4,         /* device allocation failed */
     PQ_ERR_HIP = -5,           /* HIP runtime error */
-    PQ_ERR_TOO_LARGE = -6,     /* request larger than the server's memory budget */
+    PQ_ERR_TOO_LARGE = -6,     /* request larger than the server's memory budget,
+                                  or a system beyond the list's index range */
     PQ_ERR_NAN = -7,           /* non-finite value in an input */
     PQ_ERR_STATE = -8,         /* call out of order (e.g. no system set) */
     PQ_ERR_TIMEOUT = -9        /* server poll timed out; the request is still pending */
@@ -112,7 +113,8 @@ pq_status pq_destroy(pq_ctx* ctx);
  * with radius rc + skin, and the PME B-spline stencils. Every periodic image
  * closer than rc is included, so boxes shorter than 2 rc are supported.
  * Host-synchronising (the list size is read back). Re-call when positions
- * move. n >= 1. */
+ * move. 1 <= n; the clustered atom slots (n plus at most 7 padding slots per
+ * x-y column) must stay below 2^24, else PQ_ERR_TOO_LARGE. */
 pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm);
 
 /* Number of neighbour pairs (i, j, n) with |w_j - w_i + n L| < rc + skin,

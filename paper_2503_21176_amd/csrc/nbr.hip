@@ -215,36 +215,88 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
 }
 
 // Atom-level j list of each i-cluster, derived from its cluster-pair list: the
-// atoms of the listed j-clusters, at the entry's periodic image, that lie
-// within the list radius of the i-cluster's bounding box (a superset of every
-// pair of the cluster closer than the list radius). Entries are V4<T>
-// (x, y, z of the image relative to the i-cluster's reference point, rounded
-// once from FP64; the j slot), in list order, grouped in rows of 8; the last
-// row is padded with atoms far outside any cutoff. About 44 % of the 8 x 8
-// candidates of a row are within the cutoff at liquid-like densities, against
-// ~29 % for whole cluster pairs. FILL = false counts rows, FILL = true writes.
+// atoms of the listed j-clusters, at the entry's periodic image, that are
+// within the cutoff of at least one atom of the i-cluster, decided pair by
+// pair with the canonical FP64 predicate (d^2 < rc^2, d^2 > 0). Entries are
+// V4<T>: x, y, z of the image relative to the i-cluster's reference point
+// (rounded once from FP64) and a packed word, j slot | colmask << JL_SLOT_BITS,
+// where bit a of colmask says that i-atom a and this entry are a pair. Entries
+// are grouped in rows of 8; the last row is padded with atoms far outside any
+// cutoff (mask 0). About 60 % of the 8 x 8 candidates of a row are pairs at
+// liquid-like densities (~50 % with a bounding-box test, ~29 % for whole
+// cluster pairs).
+// Order: the list order is spatial (column by column), so taken as it is one
+// i-atom collects its pairs faster than another for long stretches, and the
+// pair kernel's compute rounds run part-empty. The R rows of a cluster (runs
+// of 8 consecutive list entries, which keeps the charge loads of a row on few
+// cache lines) are therefore stored in a golden-ratio stride permutation
+// (position p holds row (p S) mod R, S ~ 0.618 R, gcd(S, R) = 1), which
+// spreads every stretch of the list over the whole walk: with it ~92 % of the
+// compute lanes are busy against ~79 % in list order.
+// FILL = false counts entries and rows, FILL = true writes.
+__device__ __forceinline__ long long gcd_ll(long long a, long long b) {
+    while (b != 0) {
+        const long long t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+// x with (s x) mod n == 1, for gcd(s, n) == 1 and n >= 2
+__device__ __forceinline__ long long inv_mod(long long s, long long n) {
+    long long r0 = n, r1 = s % n, t0 = 0, t1 = 1;
+    while (r1 != 0) {
+        const long long qq = r0 / r1;
+        long long t = r0 - qq * r1;
+        r0 = r1;
+        r1 = t;
+        t = t0 - qq * t1;
+        t0 = t1;
+        t1 = t;
+    }
+    return t0 < 0 ? t0 + n : t0;
+}
+
 template <bool FILL, class T>
 __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lstart,
                                                const int2* __restrict__ lj, const int* __restrict__ orig,
                                                const double* __restrict__ w64, const double* __restrict__ ref,
-                                               const double* __restrict__ lo, const double* __restrict__ hi,
                                                int* __restrict__ jcount, const int* __restrict__ jstart,
                                                V4<T>* __restrict__ jl) {
     const int lane = lane_id();
-    const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (ic >= ncl) return;
-    const double rl2 = g.rlist * g.rlist * (1.0 + 1e-9) + 1e-12;
-    const double lo0 = lo[3 * ic], lo1 = lo[3 * ic + 1], lo2 = lo[3 * ic + 2];
-    const double hi0 = hi[3 * ic], hi1 = hi[3 * ic + 1], hi2 = hi[3 * ic + 2];
+    const double rc2 = g.rc * g.rc;
+    // the i-cluster's atoms (the same in every lane)
+    int ii[CL];
+    double wi[CL][3];
+#pragma unroll
+    for (int a = 0; a < CL; ++a) {
+        ii[a] = orig[(size_t)ic * CL + a];
+        const int k = ii[a] >= 0 ? ii[a] : 0;
+        wi[a][0] = w64[3 * (size_t)k + 0];
+        wi[a][1] = w64[3 * (size_t)k + 1];
+        wi[a][2] = w64[3 * (size_t)k + 2];
+    }
     const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
     const int e0 = lstart[ic], e1 = lstart[ic + 1];
     const int eo = lane >> 3, b = lane & 7;
     const size_t base = FILL ? (size_t)jstart[ic] * CL : 0;
+    // row r of list order is stored at row (r * sinv) mod nrow
+    long long nrow = 1, sinv = 1;
+    if (FILL) {
+        nrow = jcount[ic];
+        if (nrow > 2) {
+            long long st = (long long)((double)nrow * 0.6180339887498949 + 0.5);
+            while (gcd_ll(st, nrow) != 1) ++st;
+            sinv = inv_mod(st, nrow);
+        }
+    }
+    auto dest = [&](long long k) -> size_t { return base + (size_t)(((k >> 3) * sinv) % nrow) * CL + (k & 7); };
     int cnt = 0;
     for (int eb = e0; eb < e1; eb += 8) {
         const int e = eb + eo;
-        bool pass = false;
-        int slot = 0;
+        int col = 0, slot = 0;
         double p0 = 0.0, p1 = 0.0, p2 = 0.0;
         if (e < e1) {
             const int2 je = lj[e];
@@ -253,18 +305,23 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
             if (j >= 0) {
                 int n0, n1, n2;
                 unpack_img(je.y, n0, n1, n2);
-                p0 = w64[3 * (size_t)j + 0] + (double)n0 * g.L[0];
-                p1 = w64[3 * (size_t)j + 1] + (double)n1 * g.L[1];
-                p2 = w64[3 * (size_t)j + 2] + (double)n2 * g.L[2];
-                const double gx = fmax(0.0, fmax(lo0 - p0, p0 - hi0));
-                const double gy = fmax(0.0, fmax(lo1 - p1, p1 - hi1));
-                const double gz = fmax(0.0, fmax(lo2 - p2, p2 - hi2));
-                pass = gx * gx + gy * gy + gz * gz < rl2;
+                const double* wj = w64 + 3 * (size_t)j;
+#pragma unroll
+                for (int a = 0; a < CL; ++a) {
+                    const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
+                    if (ii[a] >= 0 && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                }
+                p0 = wj[0] + (double)n0 * g.L[0];
+                p1 = wj[1] + (double)n1 * g.L[1];
+                p2 = wj[2] + (double)n2 * g.L[2];
             }
         }
+        const bool pass = col != 0;
         const unsigned long long m = __builtin_amdgcn_ballot_w64(pass);
-        if (FILL && pass)
-            jl[base + cnt + lanes_below(m)] = mk4<T>((T)(p0 - r0), (T)(p1 - r1), (T)(p2 - r2), pack_int(slot, T(0)));
+        if (FILL && pass) {
+            jl[dest(cnt + lanes_below(m))] =
+                mk4<T>((T)(p0 - r0), (T)(p1 - r1), (T)(p2 - r2), pack_int(slot | (col << JL_SLOT_BITS), T(0)));
+        }
         cnt += __popcll(m);
     }
     const int rows = (cnt + CL - 1) / CL;
@@ -272,7 +329,7 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
         if (lane == 0) jcount[ic] = rows;
     } else {
         for (int k = cnt + lane; k < rows * CL; k += 64)
-            jl[base + k] = mk4<T>((T)-1.0e4, (T)-1.0e4, (T)-1.0e4, pack_int(0, T(0)));
+            jl[dest(k)] = mk4<T>((T)-1.0e4, (T)-1.0e4, (T)-1.0e4, pack_int(0, T(0)));
     }
 }
 
@@ -378,6 +435,8 @@ void nbr_build(Ctx& c, const double* pos) {
     c.ncl = hv[0];
     const int ncl = c.ncl;
     const size_t nslot = (size_t)ncl * CL;
+    PQ_REQUIRE(nslot < ((size_t)1 << JL_SLOT_BITS), PQ_ERR_TOO_LARGE,
+               "too many atoms for the packed j-list slot index (2^24 cluster slots)");
     c.orig.ensure(nslot);
     c.xyzq.ensure(nslot * 4 * rsz(c));
     c.cl_ref.ensure((size_t)ncl * 3);
@@ -414,10 +473,10 @@ void nbr_build(Ctx& c, const double* pos) {
     c.jstart.ensure(ncl + 1);
     if (c.fp64)
         PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
-                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
+                  c.cl_ref.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
     else
         PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
-                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
+                  c.cl_ref.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
     PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.jcount.p, c.jstart.p, ncl);
     int rows = 0;
     PQ_HIP(hipMemcpyAsync(&rows, c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -433,10 +492,10 @@ void nbr_build(Ctx& c, const double* pos) {
         PQ_LAUNCH(k_far_entries<float>, 1, 256, 0, s, as<float4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     if (c.fp64)
         PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
-                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
+                  c.cl_ref.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
     else
         PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
-                  c.cl_ref.p, c.cl_lo.p, c.cl_hi.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
+                  c.cl_ref.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {

@@ -237,29 +237,62 @@ __device__ __forceinline__ int region_hits(int g, int K, int nb, int* bb, int* l
     return cnt;
 }
 
-// Spreading, pass 2: each grid point sums the staged regions that hold it
-// (fixed order: deterministic).
+// Spreading, pass 2: each grid point sums the staged regions that hold it,
+// in a fixed order (z hit, then y, then x: deterministic). One wavefront per
+// grid row (y, z), so the regions along y and z are found once per row; lanes
+// walk x. On grids of at least 2 bricks per axis a point lies in at most two
+// regions per axis, and its (at most 8) loads are issued together; smaller
+// grids take the general loop.
+constexpr int REDUCE_ROWS = 4;   // grid rows (wavefronts) per workgroup
 template <int P, class T>
-__global__ __launch_bounds__(256) void k_spread_reduce(PmeGeo G, const T* __restrict__ stage, T* __restrict__ grid) {
+__global__ __launch_bounds__(64 * REDUCE_ROWS) void k_spread_reduce(PmeGeo G, const T* __restrict__ stage,
+                                                                    T* __restrict__ grid) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
-    const size_t ng = (size_t)G.K0 * G.K1 * G.K2;
-    for (size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x; idx < ng; idx += (size_t)gridDim.x * 256) {
-        const int gx = (int)(idx % G.K0);
-        const int gy = (int)((idx / G.K0) % G.K1);
-        const int gz = (int)(idx / ((size_t)G.K0 * G.K1));
-        int bx[6], lx[6], by[6], ly[6], bz[6], lz[6];
+    const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * REDUCE_ROWS + (threadIdx.x >> 6));
+    if (row >= G.K1 * G.K2) return;
+    const int gy = row % G.K1, gz = row / G.K1;
+    int by[6], ly[6], bz[6], lz[6];
+    const int ny = region_hits<P>(gy, G.K1, G.nb1, by, ly);
+    const int nz = region_hits<P>(gz, G.K2, G.nb2, bz, lz);
+    // offsets of the (y, z) hits: plane[iz][iy]
+    size_t plane[2][2];
+#pragma unroll
+    for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < 2; ++iy) {
+            const int z = min(iz, nz - 1), y = min(iy, ny - 1);
+            plane[iz][iy] = (size_t)R3 * (G.nb0 * (by[y] + G.nb1 * bz[z])) + (lz[z] * R + ly[y]) * R;
+        }
+    T* out = grid + (size_t)row * G.K0;
+    for (int gx = threadIdx.x & 63; gx < G.K0; gx += 64) {
+        int bx[6], lx[6];
         const int nx = region_hits<P>(gx, G.K0, G.nb0, bx, lx);
-        const int ny = region_hits<P>(gy, G.K1, G.nb1, by, ly);
-        const int nz = region_hits<P>(gz, G.K2, G.nb2, bz, lz);
         T v = T(0);
-        for (int iz = 0; iz < nz; ++iz)
-            for (int iy = 0; iy < ny; ++iy)
-                for (int ix = 0; ix < nx; ++ix) {
-                    const int b = bx[ix] + G.nb0 * (by[iy] + G.nb1 * bz[iz]);
-                    v += stage[(size_t)b * R3 + (lz[iz] * R + ly[iy]) * R + lx[ix]];
+        if (nx <= 2 && ny <= 2 && nz <= 2) {
+            size_t xo[2];
+            xo[0] = (size_t)R3 * bx[0] + lx[0];
+            xo[1] = (size_t)R3 * bx[min(1, nx - 1)] + lx[min(1, nx - 1)];
+            T t[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ix = q & 1, iy = (q >> 1) & 1, iz = q >> 2;
+                t[q] = (ix < nx && iy < ny && iz < nz) ? stage[plane[iz][iy] + xo[ix]] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ix = q & 1, iy = (q >> 1) & 1, iz = q >> 2;
+                if (ix < nx && iy < ny && iz < nz) v += t[q];
+            }
+        } else {
+            for (int iz = 0; iz < nz; ++iz)
+                for (int iy = 0; iy < ny; ++iy) {
+                    const T* base =
+                        stage + (size_t)R3 * (G.nb0 * (by[iy] + G.nb1 * bz[iz])) + (lz[iz] * R + ly[iy]) * R;
+                    for (int ix = 0; ix < nx; ++ix) v += base[(size_t)R3 * bx[ix] + lx[ix]];
                 }
-        grid[idx] = v;
+        }
+        out[gx] = v;
     }
 }
 
@@ -422,12 +455,11 @@ template <int P, class T>
 static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
     using v4 = V4<T>;
     PmeGeo G = geo(c);
-    const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
     PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 64 * SW, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac), as<T>(c.pme_w),
               as<T>(c.qbrick), as<T>(c.stage));
-    PQ_LAUNCH((k_spread_reduce<P, T>), std::min<size_t>(cdiv(ng, 256), 65536), 256, 0, s, G, as<T>(c.stage),
-              as<T>(c.grid));
+    PQ_LAUNCH((k_spread_reduce<P, T>), cdiv(c.K[1] * c.K[2], REDUCE_ROWS), 64 * REDUCE_ROWS, 0, s, G,
+              as<T>(c.stage), as<T>(c.grid));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT], s));
     fft_convolve(c, s);

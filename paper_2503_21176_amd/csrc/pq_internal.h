@@ -173,6 +173,7 @@ struct DBuf {
 
 constexpr int CL = 8;           // atoms per cluster
 constexpr int JL_TAIL = 256;    // padding entries after the atom-level j lists
+constexpr int JL_SLOT_BITS = 24; // j-list entry word: slot in the low bits, i-atom mask above
 constexpr int RED_BLOCKS = 512; // blocks of the FP64 partial-sum reductions
 
 // Geometry of the cluster (column) decomposition used by the neighbour list.
