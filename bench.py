@@ -52,6 +52,55 @@ def measured_traffic():
     return int(m.group(2)) if sha == m.group(1) else None
 
 
+def crossover(sizes=(250, 500, 1000, 2000, 3000, 4000, 5000, 6000, 8000, 12000, 20000), delta=5e-4, rc=10.0,
+              order=6, reps=30):
+    """Direct Ewald vs PME at the accuracy-driven parameters of the same
+    target accuracy (pq_choose_params), phi + force + energy per evaluation,
+    random ionic systems at 0.1 atoms/A^3. One JSON line per size, then the
+    crossover (first size at which PME is the faster, interpolated in log N)."""
+    import torch
+
+    import paper_2503_21176_amd as P
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)  # noqa: E731
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for n in sizes:
+        s = W.random_ionic(n=n, seed=7000 + n, grid=None, order=order)
+        pos, q = t(s.pos), t(s.q)
+        ms = {}
+        for method in ("ewald", "pme"):
+            prm = P.choose_params(s.box, n, rc, delta, order, method)
+            ctx = P.Context(0)
+            ctx.set_system(pos, prm)
+            for _ in range(5):
+                ctx.coulomb(q)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                ctx.coulomb(q)
+            e1.record()
+            torch.cuda.synchronize()
+            ms[method] = e0.elapsed_time(e1) / reps
+            ms[method + "_params"] = list(prm.grid) if method == "pme" else list(prm.kmax)
+            ctx.close()
+        row = {"n": n, "L": round(float(s.box[0]), 3), "ewald_ms": round(ms["ewald"], 4), "pme_ms": round(ms["pme"], 4),
+               "kmax": ms["ewald_params"], "grid": ms["pme_params"]}
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    cross = None
+    for a, b in zip(rows, rows[1:]):
+        if a["pme_ms"] > a["ewald_ms"] and b["pme_ms"] <= b["ewald_ms"]:
+            # log-linear interpolation of the time ratio
+            ra, rb = math.log(a["pme_ms"] / a["ewald_ms"]), math.log(b["pme_ms"] / b["ewald_ms"])
+            la, lb = math.log(a["n"]), math.log(b["n"])
+            cross = int(round(math.exp(la + (lb - la) * ra / (ra - rb))))
+            break
+    print(json.dumps({"crossover_atoms": cross, "delta": delta, "cutoff": rc, "order": order,
+                      "library_auto_pme_min_atoms": P.auto_pme_min_atoms()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -65,7 +114,12 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (counter calibration for rocprofv3 --pmc)")
     ap.add_argument("--serve-only", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--crossover", action="store_true",
+                    help="time direct Ewald against PME at equal accuracy over system sizes and exit")
     args = ap.parse_args()
+    if args.crossover:
+        crossover()
+        return
     if args.serve_only:
         import paper_2503_21176_amd as P
         import workloads as W

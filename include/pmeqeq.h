@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define PQ_ABI_VERSION 2
+#define PQ_ABI_VERSION 3
 
 typedef enum pq_status {
     PQ_OK = 0,
@@ -51,7 +51,7 @@ typedef enum pq_status {
     PQ_ERR_TIMEOUT = -9        /* server poll timed out; the request is still pending */
 } pq_status;
 
-enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1 };
+enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1, PQ_METHOD_AUTO = 2 /* pq_choose_params only */ };
 
 /* pq_params.flags bits.
  * PQ_FLAG_FP64: the per-atom bulk arithmetic (pair sum, spreading, FFT,
@@ -77,6 +77,29 @@ typedef struct pq_params {
     int32_t method;   /* PQ_METHOD_PME (grid, order used) or PQ_METHOD_EWALD (kmax)   */
     int32_t flags;    /* 0 or PQ_FLAG_FP64; other bits are rejected (PQ_ERR_INVALID)  */
 } pq_params;
+
+/* Accuracy-driven parameters. The paper tunes the number of k-vectors of the
+ * regular Ewald sum and the PME grid from a target Ewald accuracy delta with
+ * the heuristics of OpenMM (Sections "Regular Ewald Summation", "Particle
+ * Mesh Ewald Summation" and "Ewald Summation"; runs at delta = 5e-4, rc = 10).
+ * The heuristics, as OpenMM documents them:
+ *   alpha = sqrt(-ln(2 delta)) / rc
+ *   Ewald: kmax_d = the smallest k >= max(1, ceil(L_d alpha / (pi sqrt 2)))
+ *          (past the maximum of the estimate) with
+ *          0.05 sqrt(L_d alpha) k exp(-(pi k / (L_d alpha))^2) <= delta
+ *   PME:   K_d = the smallest 2^a 3^b 5^c >= max(ceil(2 alpha L_d / (3 delta^(1/5))), 2 p)
+ * Inputs (host): box[3] > 0 (A), n >= 1 atoms, cutoff > 0 (A), 0 < delta <
+ * 0.5, order p in 3..8, method PQ_METHOD_PME, PQ_METHOD_EWALD or
+ * PQ_METHOD_AUTO. AUTO takes the direct Ewald sum below
+ * pq_auto_pme_min_atoms() atoms (when its kmax fits 0..64) and PME from there
+ * on: the crossover measured on MI355X for random ionic systems at rho 0.1/A^3,
+ * delta 5e-4, rc 10 A, p 6. Writes *out completely (grid and kmax are both
+ * filled; skin 0, flags 0). PQ_ERR_BOX if the chosen method's grid exceeds
+ * 1024 or its kmax 64, PQ_ERR_INVALID for bad inputs. No device work. */
+pq_status pq_choose_params(const double* box, int64_t n, double cutoff, double delta, int32_t order,
+                           int32_t method, struct pq_params* out);
+/* Atom count from which PQ_METHOD_AUTO chooses PME. */
+int64_t pq_auto_pme_min_atoms(void);
 
 /* Outcome of a Krylov solve (host struct filled by the library). */
 typedef struct pq_solve_info {

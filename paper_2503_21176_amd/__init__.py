@@ -17,19 +17,20 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 PQ_OK = 0
 FLAG_FP64 = 1
 PQ_WARN_NOT_CONVERGED = 1
 STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_ERR_BOX",
           -3: "PQ_ERR_CAPACITY", -4: "PQ_ERR_NOMEM", -5: "PQ_ERR_HIP", -6: "PQ_ERR_TOO_LARGE",
           -7: "PQ_ERR_NAN", -8: "PQ_ERR_STATE", -9: "PQ_ERR_TIMEOUT"}
-METHOD_PME, METHOD_EWALD = 0, 1
+METHOD_PME, METHOD_EWALD, METHOD_AUTO = 0, 1, 2
 
 EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create", "pq_set_stream",
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
-           "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning"]
+           "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
+           "pq_choose_params", "pq_auto_pme_min_atoms"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -106,6 +107,8 @@ def load() -> ctypes.CDLL:
         "pq_request_footprint": (dbl, [i64, ctypes.POINTER(Params), i32]),
         "pq_autotune": (i32, [vp, vp, i32, ctypes.POINTER(TuneResult)]),
         "pq_set_tuning": (i32, [vp, ctypes.POINTER(TuneResult)]),
+        "pq_choose_params": (i32, [ctypes.POINTER(dbl), i64, dbl, dbl, i32, i32, ctypes.POINTER(Params)]),
+        "pq_auto_pme_min_atoms": (i64, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -147,6 +150,23 @@ def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, met
         raise ValueError(method)
     p.flags = FLAG_FP64 if fp64 else 0
     return p
+
+
+def choose_params(box, n, cutoff, delta=5e-4, order=6, method="auto", fp64=False) -> Params:
+    """Accuracy-driven parameters (pq_choose_params): alpha, the PME grid and
+    the direct-Ewald range from the target accuracy delta; ``method`` is
+    "pme", "ewald" or "auto" (by atom count)."""
+    m = {"pme": METHOD_PME, "ewald": METHOD_EWALD, "auto": METHOD_AUTO}[method]
+    b = (ctypes.c_double * 3)(*[float(x) for x in (box if hasattr(box, "__len__") else (box, box, box))])
+    p = Params()
+    _check(load().pq_choose_params(b, int(n), float(cutoff), float(delta), int(order), m, ctypes.byref(p)))
+    if fp64:
+        p.flags = FLAG_FP64
+    return p
+
+
+def auto_pme_min_atoms() -> int:
+    return int(load().pq_auto_pme_min_atoms())
 
 
 def _ptr(t):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <string>
 
 #include "pmeqeq.h"
@@ -65,6 +66,62 @@ static void validate(int64_t n, const pq_params* p) {
         for (int d = 0; d < 3; ++d)
             PQ_REQUIRE(p->kmax[d] >= 0 && p->kmax[d] <= 64, PQ_ERR_INVALID, "kmax must be in 0..64");
     }
+}
+
+// Atom count from which the accuracy-driven choice takes PME (measured
+// crossover of the two reciprocal-space methods on MI355X, random ionic
+// systems at 0.1 atoms/A^3, delta 5e-4, rc 10 A, order 6).
+constexpr int64_t AUTO_PME_MIN_ATOMS = 3500;
+
+// OpenMM's estimate of the direct-Ewald error with |n_d| <= k on an edge L
+static double ewald_err(double L, double alpha, int k) {
+    const double t = M_PI * k / (L * alpha);
+    return 0.05 * std::sqrt(L * alpha) * k * std::exp(-t * t);
+}
+
+static void choose_params(const double* box, int64_t n, double rc, double delta, int order, int method,
+                          pq_params* out) {
+    PQ_REQUIRE(box != nullptr && out != nullptr, PQ_ERR_INVALID, "box and out must not be NULL");
+    for (int d = 0; d < 3; ++d)
+        PQ_REQUIRE(std::isfinite(box[d]) && box[d] > 0.0, PQ_ERR_INVALID, "box edges must be finite and > 0");
+    PQ_REQUIRE(n >= 1, PQ_ERR_INVALID, "n must be >= 1");
+    PQ_REQUIRE(std::isfinite(rc) && rc > 0.0, PQ_ERR_INVALID, "cutoff must be > 0");
+    PQ_REQUIRE(std::isfinite(delta) && delta > 0.0 && delta < 0.5, PQ_ERR_INVALID, "delta must be in (0, 0.5)");
+    PQ_REQUIRE(order >= 3 && order <= 8, PQ_ERR_INVALID, "order must be in 3..8");
+    PQ_REQUIRE(method == PQ_METHOD_PME || method == PQ_METHOD_EWALD || method == PQ_METHOD_AUTO, PQ_ERR_INVALID,
+               "unknown method");
+    pq_params p;
+    std::memset(&p, 0, sizeof(p));
+    const double alpha = std::sqrt(-std::log(2.0 * delta)) / rc;
+    bool grid_ok = true, kmax_ok = true;
+    for (int d = 0; d < 3; ++d) {
+        p.box[d] = box[d];
+        const double L = box[d];
+        // PME grid
+        const double want = std::ceil(2.0 * alpha * L / (3.0 * std::pow(delta, 0.2)));
+        int K = (int)std::min(want, 4096.0);
+        K = std::max(K, 2 * order);
+        while (!smooth235(K)) ++K;
+        p.grid[d] = K;
+        grid_ok = grid_ok && K <= 1024;
+        // direct Ewald range, searched from past the maximum of the estimate
+        int k = std::max(1, (int)std::ceil(L * alpha / (M_PI * std::sqrt(2.0))));
+        while (k <= 64 && ewald_err(L, alpha, k) > delta) ++k;
+        p.kmax[d] = k;
+        kmax_ok = kmax_ok && k <= 64;
+    }
+    p.cutoff = rc;
+    p.skin = 0.0;
+    p.alpha = alpha;
+    p.order = order;
+    p.flags = 0;
+    if (method == PQ_METHOD_AUTO) method = (n < AUTO_PME_MIN_ATOMS && kmax_ok) ? PQ_METHOD_EWALD : PQ_METHOD_PME;
+    p.method = method;
+    if (method == PQ_METHOD_PME)
+        PQ_REQUIRE(grid_ok, PQ_ERR_BOX, "PME grid for this accuracy exceeds 1024 points per axis");
+    else
+        PQ_REQUIRE(kmax_ok, PQ_ERR_BOX, "direct Ewald range for this accuracy exceeds kmax 64");
+    *out = p;
 }
 
 void ensure_eval(Ctx& c) {
@@ -184,6 +241,16 @@ using namespace pq;
 extern "C" {
 
 int pq_abi_version(void) { return PQ_ABI_VERSION; }
+
+pq_status pq_choose_params(const double* box, int64_t n, double cutoff, double delta, int32_t order, int32_t method,
+                           pq_params* out) {
+    PQ_API_BEGIN
+    choose_params(box, n, cutoff, delta, order, method, out);
+    return PQ_OK;
+    PQ_API_END
+}
+
+int64_t pq_auto_pme_min_atoms(void) { return AUTO_PME_MIN_ATOMS; }
 
 double pq_coulomb_constant(void) { return KE; }
 

@@ -22,6 +22,7 @@
 namespace pq {
 
 constexpr int EW_TILE = 256;
+constexpr int EW_BLOCKS = 2048;   // target workgroups per direct-Ewald sum
 
 __device__ __forceinline__ void phase(const int4 nk, double s0, double s1, double s2, float& sn, float& cs) {
     double t = (double)nk.x * s0 + (double)nk.y * s1 + (double)nk.z * s2;
@@ -34,40 +35,61 @@ __device__ __forceinline__ void phase(const int4 nk, double s0, double s1, doubl
     sincospi(2.0 * t, &sn, &cs);
 }
 
-// Structure factors: one thread per k vector, atoms staged through LDS.
+// Both sums run over a second grid dimension so that small systems still
+// fill the device: the structure factors over chunks of atoms, the
+// potentials and forces over chunks of k vectors; the chunk partials are then
+// added in chunk order (deterministic, independent of the launch).
+
+// Structure-factor partials: one thread per k vector, blockIdx.y = atom chunk
+// [y cs, (y+1) cs), atoms staged through LDS.
 template <class T>
-__global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __restrict__ kn,
-                                                 const double* __restrict__ kc, const double* __restrict__ w64,
-                                                 double inv0, double inv1, double inv2, const double* __restrict__ q,
-                                                 double2* __restrict__ sfac, double* __restrict__ epart) {
+__global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, int cs, const int4* __restrict__ kn,
+                                                 const double* __restrict__ w64, double inv0, double inv1,
+                                                 double inv2, const double* __restrict__ q,
+                                                 double2* __restrict__ spart) {
     __shared__ double s_s[EW_TILE * 3];
     __shared__ double s_q[EW_TILE];
-    __shared__ double red[EW_TILE / 64];
     const int kidx = blockIdx.x * EW_TILE + threadIdx.x;
     const bool valid = kidx < nk;
     const int4 nv = valid ? kn[kidx] : make_int4(0, 0, 0, 0);
+    const int jb = blockIdx.y * cs, je = min(n, jb + cs);
     double re = 0.0, im = 0.0;
-    for (int j0 = 0; j0 < n; j0 += EW_TILE) {
+    for (int j0 = jb; j0 < je; j0 += EW_TILE) {
         const int j = j0 + threadIdx.x;
-        if (j < n) {
+        if (j < je) {
             s_s[3 * threadIdx.x + 0] = w64[3 * (size_t)j + 0] * inv0;
             s_s[3 * threadIdx.x + 1] = w64[3 * (size_t)j + 1] * inv1;
             s_s[3 * threadIdx.x + 2] = w64[3 * (size_t)j + 2] * inv2;
             s_q[threadIdx.x] = q[j];
         }
         __syncthreads();
-        const int m = min(EW_TILE, n - j0);
+        const int m = min(EW_TILE, je - j0);
         if (valid)
             for (int t = 0; t < m; ++t) {
-                T sn, cs;
-                phase(nv, s_s[3 * t], s_s[3 * t + 1], s_s[3 * t + 2], sn, cs);
-                re += s_q[t] * (double)cs;
+                T sn, cs_;
+                phase(nv, s_s[3 * t], s_s[3 * t + 1], s_s[3 * t + 2], sn, cs_);
+                re += s_q[t] * (double)cs_;
                 im += s_q[t] * (double)sn;
             }
         __syncthreads();
     }
+    if (valid) spart[(size_t)blockIdx.y * nk + kidx] = make_double2(re, im);
+}
+
+// S(k) = sum of the chunk partials in chunk order; energy partial per block.
+__global__ __launch_bounds__(EW_TILE) void k_sfac_sum(int nk, int nch, const double* __restrict__ kc,
+                                                     const double2* __restrict__ spart,
+                                                     double2* __restrict__ sfac, double* __restrict__ epart) {
+    __shared__ double red[EW_TILE / 64];
+    const int kidx = blockIdx.x * EW_TILE + threadIdx.x;
     double e = 0.0;
-    if (valid) {
+    if (kidx < nk) {
+        double re = 0.0, im = 0.0;
+        for (int c = 0; c < nch; ++c) {
+            const double2 v = spart[(size_t)c * nk + kidx];
+            re += v.x;
+            im += v.y;
+        }
         sfac[kidx] = make_double2(re, im);
         e = kc[kidx] * (re * re + im * im);
     }
@@ -75,14 +97,14 @@ __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, const int4* __r
     if (threadIdx.x == 0) epart[blockIdx.x] = e;
 }
 
-// Potentials and forces: one thread per atom, k vectors staged through LDS.
+// Potential / force partials: one thread per atom, blockIdx.y = k chunk
+// [y kcs, (y+1) kcs), k vectors staged through LDS.
 template <bool FORCE, class T>
-__global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* __restrict__ kn,
+__global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, int kcs, const int4* __restrict__ kn,
                                                     const double* __restrict__ kc,
                                                     const double2* __restrict__ sfac, const double* __restrict__ w64,
                                                     double inv0, double inv1, double inv2,
-                                                    const double* __restrict__ q, T* __restrict__ phi_out,
-                                                    V4<T>* __restrict__ f_out) {
+                                                    double4* __restrict__ gpart) {
     __shared__ int4 s_n[EW_TILE];
     __shared__ double s_c[EW_TILE];
     __shared__ double2 s_S[EW_TILE];
@@ -94,16 +116,17 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* 
         s1 = w64[3 * (size_t)i + 1] * inv1;
         s2 = w64[3 * (size_t)i + 2] * inv2;
     }
+    const int kb = blockIdx.y * kcs, ke = min(nk, kb + kcs);
     double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-    for (int k0 = 0; k0 < nk; k0 += EW_TILE) {
+    for (int k0 = kb; k0 < ke; k0 += EW_TILE) {
         const int k = k0 + threadIdx.x;
-        if (k < nk) {
+        if (k < ke) {
             s_n[threadIdx.x] = kn[k];
             s_c[threadIdx.x] = kc[k];
             s_S[threadIdx.x] = sfac[k];
         }
         __syncthreads();
-        const int m = min(EW_TILE, nk - k0);
+        const int m = min(EW_TILE, ke - k0);
         if (valid)
             for (int t = 0; t < m; ++t) {
                 T sn, cs;
@@ -121,13 +144,29 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, const int4* 
             }
         __syncthreads();
     }
-    if (valid) {
-        phi_out[i] = (T)(2.0 * phi);
-        if (FORCE) {
-            const double qi = q[i];
-            const double f = 2.0 * qi * 2.0 * PI;
-            f_out[i] = mk4<T>((T)(f * g0 * inv0), (T)(f * g1 * inv1), (T)(f * g2 * inv2), T(0));
-        }
+    if (valid) gpart[(size_t)blockIdx.y * n + i] = make_double4(phi, g0, g1, g2);
+}
+
+// Per atom: the k-chunk partials in chunk order, then phi and F.
+template <bool FORCE, class T>
+__global__ __launch_bounds__(EW_TILE) void k_kgather_sum(int n, int nkch, const double4* __restrict__ gpart,
+                                                        double inv0, double inv1, double inv2,
+                                                        const double* __restrict__ q, T* __restrict__ phi_out,
+                                                        V4<T>* __restrict__ f_out) {
+    const int i = blockIdx.x * EW_TILE + threadIdx.x;
+    if (i >= n) return;
+    double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int c = 0; c < nkch; ++c) {
+        const double4 v = gpart[(size_t)c * n + i];
+        phi += v.x;
+        g0 += v.y;
+        g1 += v.z;
+        g2 += v.w;
+    }
+    phi_out[i] = (T)(2.0 * phi);
+    if (FORCE) {
+        const double f = 2.0 * q[i] * 2.0 * PI;
+        f_out[i] = mk4<T>((T)(f * g0 * inv0), (T)(f * g1 * inv1), (T)(f * g2 * inv2), T(0));
     }
 }
 
@@ -159,6 +198,17 @@ void ewald_setup(Ctx& c) {
     c.kn.ensure(std::max(1, c.nk));
     c.kc.ensure(std::max(1, c.nk));
     c.sfac.ensure(std::max(1, c.nk));
+    // chunking: about EW_BLOCKS workgroups per sum, chunks of at least 32
+    const int n = (int)c.n, nk = std::max(1, c.nk);
+    const int kblk = (int)cdiv(nk, EW_TILE), ablk = (int)cdiv(std::max(1, n), EW_TILE);
+    c.ew_nch = std::max(1, std::min((int)cdiv(std::max(1, n), 32), (int)cdiv(EW_BLOCKS, kblk)));
+    c.ew_cs = (int)cdiv(std::max(1, n), c.ew_nch);
+    c.ew_nch = (int)cdiv(std::max(1, n), c.ew_cs);
+    c.ew_nkch = std::max(1, std::min((int)cdiv(nk, 32), (int)cdiv(EW_BLOCKS, ablk)));
+    c.ew_kcs = (int)cdiv(nk, c.ew_nkch);
+    c.ew_nkch = (int)cdiv(nk, c.ew_kcs);
+    c.spart.ensure((size_t)c.ew_nch * nk);
+    c.gpart.ensure((size_t)c.ew_nkch * std::max(1, n));
     if (c.nk) {
         PQ_HIP(hipMemcpy(c.kn.p, nv.data(), nv.size() * sizeof(int4), hipMemcpyHostToDevice));
         PQ_HIP(hipMemcpy(c.kc.p, cv.data(), cv.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -188,16 +238,26 @@ static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
         return;
     }
     const int nb = cdiv(c.nk, EW_TILE);
-    c.part.ensure(nb + 16);
-    PQ_LAUNCH(k_sfac<T>, nb, EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.w64.p, i0, i1, i2, q, c.sfac.p, c.part.p);
+    PQ_REQUIRE(c.part.n >= (size_t)nb + 16 && c.spart.n >= (size_t)c.ew_nch * c.nk &&
+                   c.gpart.n >= (size_t)c.ew_nkch * n,
+               PQ_ERR_STATE, "direct-Ewald workspaces not sized");
+    PQ_LAUNCH(k_sfac<T>, dim3(nb, c.ew_nch), EW_TILE, 0, s, n, c.nk, c.ew_cs, c.kn.p, c.w64.p, i0, i1, i2, q,
+              c.spart.p);
+    PQ_LAUNCH(k_sfac_sum, nb, EW_TILE, 0, s, c.nk, c.ew_nch, c.kc.p, c.spart.p, c.sfac.p, c.part.p);
     PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.part.p, nb, c.scal.p + 1);
     if (n == 0) return;
-    if (force)
-        PQ_LAUNCH((k_kgather<true, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p,
-                  i0, i1, i2, q, phi, f);
-    else
-        PQ_LAUNCH((k_kgather<false, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.nk, c.kn.p, c.kc.p, c.sfac.p, c.w64.p,
-                  i0, i1, i2, q, phi, f);
+    const dim3 g(cdiv(n, EW_TILE), c.ew_nkch);
+    if (force) {
+        PQ_LAUNCH((k_kgather<true, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0, i1,
+                  i2, c.gpart.p);
+        PQ_LAUNCH((k_kgather_sum<true, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, i0, i1, i2, q,
+                  phi, f);
+    } else {
+        PQ_LAUNCH((k_kgather<false, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
+                  i1, i2, c.gpart.p);
+        PQ_LAUNCH((k_kgather_sum<false, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, i0, i1, i2, q,
+                  phi, f);
+    }
 }
 
 // phi, f (original order, without KE) into c.phi_k, c.f_k; E_rec (without KE) into c.scal[1]

@@ -261,6 +261,10 @@ struct Ctx {
     DBuf<int4> kn;           // half-space integer k vectors
     DBuf<double> kc;         // c_k = (4 pi / V) exp(-k^2/4a^2)/k^2
     DBuf<double2> sfac;      // structure factors
+    int ew_nch = 1, ew_cs = 1;     // atom chunks of the structure-factor sums (chunk size)
+    int ew_nkch = 1, ew_kcs = 1;   // k-vector chunks of the potential / force sums (chunk size)
+    DBuf<double2> spart;     // structure-factor partials, [atom chunk][k]
+    DBuf<double4> gpart;     // potential / force partials, [k chunk][atom]
 
     // --- per-evaluation scratch ---
     DBuf<unsigned char> phi_r, phi_k;   // T per atom (original order, without KE)

@@ -79,6 +79,10 @@ double request_footprint(int64_t n, const pq_params& p, int restart) {
         const double nbrick = std::ceil(p.grid[0] / 8.0) * std::ceil(p.grid[1] / 8.0) * std::ceil(p.grid[2] / 8.0);
         grid = K3 * rs + (p.grid[0] / 2 + 1) * (double)p.grid[1] * p.grid[2] * 2.0 * rs + nbrick * R * R * R * rs +
                (double)n * 24.0 * rs;
+    } else {
+        // k vectors, structure factors and the chunk partials of the direct sum
+        const double nk = ((2.0 * p.kmax[0] + 1) * (2.0 * p.kmax[1] + 1) * (2.0 * p.kmax[2] + 1)) / 2.0 + 1.0;
+        grid = nk * (16 + 8 + 16) + 2048.0 * 256.0 * (16 + 32);
     }
     const double kry = ((double)n + 64) * 8.0 * (9 + restart + 1);
     return 1.25 * (pairs + jatoms + atoms + grid + kry) + (1 << 20);

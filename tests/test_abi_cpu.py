@@ -31,7 +31,7 @@ def test_library_loads_and_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == _declared()
     L = P.load()
-    assert L.pq_abi_version() == P.ABI_VERSION == 2
+    assert L.pq_abi_version() == P.ABI_VERSION == 3
     assert L.pq_coulomb_constant() == 14.3996454784
 
 
