@@ -194,10 +194,10 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     stream_wait(ps, c.ev_fork);
     E.begin(PQ_PHASE_PAIR, ps);
     pair_sum(c, fo, ps);
+    E.end(PQ_PHASE_PAIR, ps);
     // the total charge (background term) is only needed by the final combine:
     // summed after the pair kernel, off the reciprocal-space chain
     sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
-    E.end(PQ_PHASE_PAIR, ps);
     ev_record(c.ev_join, ps);
     if (c.prm.method == PQ_METHOD_PME) {
         pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s);
