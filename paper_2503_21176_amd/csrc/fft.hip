@@ -391,6 +391,108 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
     }
 }
 
+// ---- strided column transforms, two register radices ----------------------
+// For n = R1 R2 with both factors register radices, a column transform takes
+// one LDS exchange. With j = R2 n1 + n2 and k = k1 + R1 k2,
+//   X[k1 + R1 k2] = sum_n2 w_R2^(n2 k2) w_n^(n2 k1) sum_n1 x[R2 n1 + n2] w_R1^(n1 k1),
+// w_m = exp(SIGN 2 pi i / m):
+//   stage A: thread (n2, column) loads its R1 points straight from the grid
+//            (CT consecutive columns: coalesced rows), R1-point DFT, twiddles,
+//            into LDS;
+//   stage B: thread (k1, column) reads its R2 values, R2-point DFT, holding
+//            X[k1 + R1 k2] for k2 < R2.
+// In the z pass (CONV) the thread multiplies its outputs by G, accumulates
+// the energy and runs the inverse transform back the same way:
+//   x[j2 + R2 j1] = sum_k1 w_R1^(-j1 k1) w_n^(-j2 k1) sum_k2 Y[k1 + R1 k2] w_R2^(-j2 k2).
+constexpr int CT = 16;   // columns per workgroup
+
+template <int R1, int R2, int SIGN, bool CONV, class T>
+__global__ __launch_bounds__(CT*(R1 > R2 ? R1 : R2)) void k_fft_col2(const V2<T>* __restrict__ wn, int X,
+                                                                     size_t estride, size_t ostride,
+                                                                     V2<T>* __restrict__ spec, ConvArgs cv,
+                                                                     double* __restrict__ epart) {
+    using C = V2<T>;
+    constexpr int N = R1 * R2;
+    __shared__ C sm[N * CT];   // element (a, b) of a column at (a * R2 + b) * CT + column
+    __shared__ double se[CONV ? R1 * CT : 1];
+    const int mx0 = blockIdx.x * CT;
+    const int o = blockIdx.y;
+    C* base = spec + (size_t)o * ostride;
+    const int s = threadIdx.x % CT, g = threadIdx.x / CT;
+    const int mx = mx0 + s;
+    const bool col = mx < X;
+    // w_n^e for the sign of the transform (wn holds exp(-2 pi i e / n))
+    auto tw = [&](int e, int sign) {
+        C w = wn[e % N];
+        if (sign > 0) w.y = -w.y;
+        return w;
+    };
+    if (g < R2) {
+        C v[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1)
+            v[n1] = col ? base[(size_t)(R2 * n1 + g) * estride + mx] : cmk<C>(T(0), T(0));
+        dft<R1, SIGN>(v);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) sm[(k1 * R2 + g) * CT + s] = (k1 == 0 || g == 0) ? v[k1] : cmul(v[k1], tw(g * k1, SIGN));
+    }
+    __syncthreads();
+    C u[R2];
+    if (g < R1) {
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) u[n2] = sm[(g * R2 + n2) * CT + s];
+        dft<R2, SIGN>(u);   // u[k2] = X[g + R1 k2]
+    }
+    if constexpr (!CONV) {
+        if (g < R1 && col) {
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) base[(size_t)(g + R1 * k2) * estride + mx] = u[k2];
+        }
+    } else {
+        // o = my; u[k2] holds mz = g + R1 k2. Energy: each thread sums its
+        // modes in k2 order, then the R1 threads of a column in g order.
+        const int my = o;
+        if (g < R1) {
+            double e = 0.0;
+            const double wgt = (mx == 0 || (2 * mx == cv.K0)) ? 1.0 : 2.0;
+            const double t01 = col ? cv.scale * cv.T0[mx] * cv.T1[my] : 0.0;
+            const double s01 = col ? cv.S0[mx] + cv.S1[my] : 1.0;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int mz = g + R1 * k2;
+                double gk = 0.0;
+                if (col && (mx | my | mz) != 0) gk = t01 * cv.T2[mz] / (s01 + cv.S2[mz]);
+                if (epart) e += wgt * gk * ((double)u[k2].x * u[k2].x + (double)u[k2].y * u[k2].y);
+                u[k2] = cmk<C>(u[k2].x * (T)gk, u[k2].y * (T)gk);
+            }
+            if (epart) se[g * CT + s] = 0.5 * e;
+            // inverse: R2-point transforms in registers, conjugate twiddles
+            dft<R2, -SIGN>(u);   // u[j2]
+        }
+        __syncthreads();   // stage B has read sm
+        if (g < R1) {
+#pragma unroll
+            for (int j2 = 0; j2 < R2; ++j2) sm[(g * R2 + j2) * CT + s] = (g == 0 || j2 == 0) ? u[j2] : cmul(u[j2], tw(j2 * g, -SIGN));
+        }
+        __syncthreads();
+        if (epart && g == 0 && col) {
+            double e = 0.0;
+            for (int k = 0; k < R1; ++k) e += se[k * CT + s];
+            epart[(size_t)my * X + mx] = e;
+        }
+        if (g < R2) {
+            C v[R1];
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) v[k1] = sm[(k1 * R2 + g) * CT + s];
+            dft<R1, -SIGN>(v);   // v[j1] = x[g + R2 j1]
+            if (col) {
+#pragma unroll
+                for (int j1 = 0; j1 < R1; ++j1) base[(size_t)(g + R2 * j1) * estride + mx] = v[j1];
+            }
+        }
+    }
+}
+
 // Sum of n partials in a fixed order: thread t adds t, t + 1024, ... with four
 // independent accumulators (loads in flight together), then a block tree.
 __global__ __launch_bounds__(1024) void k_sum_part(const double* __restrict__ part, int n, double* __restrict__ out) {
@@ -484,12 +586,27 @@ static FftDev to_dev(const Fft1D& f) {
 }
 
 template <class T>
-static void upload_twiddles(Ctx& c, const std::vector<double>& tw, const int* off) {
+static void upload_twiddles(Ctx& c, const std::vector<double>& tw, const int* off, const int* woff) {
     std::vector<V2<T>> h(tw.size() / 2);
     for (size_t i = 0; i < h.size(); ++i) h[i] = mk2<T>((T)tw[2 * i], (T)tw[2 * i + 1]);
     c.twid.ensure(std::max<size_t>(1, h.size()) * sizeof(V2<T>));
     PQ_HIP(hipMemcpy(c.twid.p, h.data(), h.size() * sizeof(V2<T>), hipMemcpyHostToDevice));
-    for (int d = 0; d < 3; ++d) c.fft[d].tw = as<V2<T>>(c.twid) + off[d];
+    for (int d = 0; d < 3; ++d) {
+        c.fft[d].tw = as<V2<T>>(c.twid) + off[d];
+        c.fft[d].wn = as<V2<T>>(c.twid) + woff[d];
+    }
+}
+
+// Register radices (R1 >= R2, the smallest R1) with R1 R2 = n, or 0, 0.
+static void col2_radices(int n, int& r1, int& r2) {
+    static const int R[] = {2, 3, 4, 5, 8, 9, 16};
+    r1 = r2 = 0;
+    for (int a : R)
+        for (int b : R)
+            if (b <= a && a * b == n && (r1 == 0 || a < r1)) {
+                r1 = a;
+                r2 = b;
+            }
 }
 
 void fft_setup(Ctx& c) {
@@ -520,10 +637,21 @@ void fft_setup(Ctx& c) {
         for (int st = f.nst; st < FFT_MAX_STAGES; ++st) f.radix[st] = f.ns[st] = f.twoff[st] = 0;
         f.ntw = (int)tw.size() / 2 - off[d];
     }
+    int woff[3];
+    for (int d = 0; d < 3; ++d) {
+        Fft1D& f = c.fft[d];
+        col2_radices(f.n, f.r1, f.r2);
+        woff[d] = (int)tw.size() / 2;
+        for (int e = 0; e < f.n; ++e) {
+            const double ang = -2.0 * PI * (double)e / f.n;
+            tw.push_back(std::cos(ang));
+            tw.push_back(std::sin(ang));
+        }
+    }
     if (c.fp64)
-        upload_twiddles<double>(c, tw, off);
+        upload_twiddles<double>(c, tw, off, woff);
     else
-        upload_twiddles<float>(c, tw, off);
+        upload_twiddles<float>(c, tw, off, woff);
 
     // influence tables
     const double a = c.prm.alpha;
@@ -561,6 +689,25 @@ void fft_setup(Ctx& c) {
 static int col_tile(int n, size_t esz, int budget) { return std::max(1, std::min(16, (int)(budget / (n * esz)))); }
 static int row_pairs(int n, size_t esz, int budget) { return std::max(1, (int)(budget / (n * esz))); }
 
+// The two-radix column transform for (r1, r2) of one axis; false if that
+// pair has no instance (the caller then takes the Stockham kernel).
+template <int SIGN, bool CONV, class T>
+static bool col2_launch(int r1, int r2, dim3 grid, hipStream_t s, const V2<T>* wn, int X, size_t es, size_t os,
+                        V2<T>* spec, const ConvArgs& cv, double* epart) {
+#define PQ_COL2(A, B)                                                                                       \
+    if (r1 == A && r2 == B) {                                                                               \
+        PQ_LAUNCH((k_fft_col2<A, B, SIGN, CONV, T>), grid, CT*(A > B ? A : B), 0, s, wn, X, es, os, spec, cv, \
+                  epart);                                                                                   \
+        return true;                                                                                        \
+    }
+    PQ_COL2(3, 2) PQ_COL2(4, 2) PQ_COL2(3, 3) PQ_COL2(5, 2) PQ_COL2(4, 3) PQ_COL2(5, 3) PQ_COL2(4, 4)
+    PQ_COL2(9, 2) PQ_COL2(5, 4) PQ_COL2(8, 3) PQ_COL2(5, 5) PQ_COL2(9, 3) PQ_COL2(8, 4) PQ_COL2(9, 4)
+    PQ_COL2(8, 5) PQ_COL2(9, 5) PQ_COL2(16, 3) PQ_COL2(8, 8) PQ_COL2(9, 8) PQ_COL2(16, 5) PQ_COL2(9, 9)
+    PQ_COL2(16, 8) PQ_COL2(16, 9) PQ_COL2(16, 16)
+#undef PQ_COL2
+    return false;
+}
+
 template <class T>
 static void fft_convolve_t(Ctx& c, hipStream_t s) {
     using C = V2<T>;
@@ -579,21 +726,29 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     const int npairs = (nrows + 1) / 2;
     // x forward
     PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, grid, spec);
+    const C* wn1 = static_cast<const C*>(c.fft[1].wn);
+    const C* wn2 = static_cast<const C*>(c.fft[2].wn);
+    const int y1 = c.fft[1].r1, y2 = c.fft[1].r2, z1 = c.fft[2].r1, z2 = c.fft[2].r2;
     // y forward: sequences over (z, mx), elements stride X
     const int ty = col_tile(K1, esz, c.fft_budget);
-    PQ_LAUNCH((k_fft_col<-1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X, ty,
-              (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
+    if (!col2_launch<-1, false, T>(y1, y2, dim3(cdiv(X, CT), K2), s, wn1, X, (size_t)X, (size_t)X * K1, spec, cv,
+                                   (double*)nullptr))
+        PQ_LAUNCH((k_fft_col<-1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X,
+                  ty, (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
     // z forward + convolution + z inverse: sequences over (y, mx), elements stride X*K1
     const int tz = col_tile(K2, esz, c.fft_budget);
-    const dim3 gz(cdiv(X, tz), K1);
     // one energy partial per spectral column (mx, my); sized by set_system
     PQ_REQUIRE(c.part.n >= (size_t)X * K1 + 16, PQ_ERR_STATE, "energy partials not sized");
-    PQ_LAUNCH((k_fft_col<-1, true, T>), gz, 256, (2 * K2 * tz + pz.ntw) * esz, s, pz, tw2, X, tz, (size_t)X * K1, (size_t)X,
-              spec, cv, c.want_energy ? c.part.p : nullptr);
+    double* ep = c.want_energy ? c.part.p : nullptr;
+    if (!col2_launch<-1, true, T>(z1, z2, dim3(cdiv(X, CT), K1), s, wn2, X, (size_t)X * K1, (size_t)X, spec, cv, ep))
+        PQ_LAUNCH((k_fft_col<-1, true, T>), dim3(cdiv(X, tz), K1), 256, (2 * K2 * tz + pz.ntw) * esz, s, pz, tw2, X,
+                  tz, (size_t)X * K1, (size_t)X, spec, cv, ep);
     if (c.want_energy) PQ_LAUNCH(k_sum_part, 1, 1024, 0, s, c.part.p, X * K1, c.scal.p + 1);
     // y inverse
-    PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X, ty, (size_t)X,
-              (size_t)X * K1, spec, cv, (double*)nullptr);
+    if (!col2_launch<1, false, T>(y1, y2, dim3(cdiv(X, CT), K2), s, wn1, X, (size_t)X, (size_t)X * K1, spec, cv,
+                                  (double*)nullptr))
+        PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X,
+                  ty, (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
     // x inverse
     PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, spec, grid);
 }

@@ -195,6 +195,8 @@ struct Fft1D {
     int ns[FFT_MAX_STAGES];     // product of the radices of earlier stages
     int twoff[FFT_MAX_STAGES];  // offset of the stage's twiddles in the table
     const void* tw = nullptr;   // V2<T> exp(-2 pi i k r / (ns*R)) for k < ns, 1 <= r < R
+    int r1 = 0, r2 = 0;         // register radices of the two-radix column transform (0: none)
+    const void* wn = nullptr;   // V2<T> exp(-2 pi i e / n) for e < n
 };
 
 // Per-axis influence-function tables (without KE and 1/(pi V)):
