@@ -21,6 +21,7 @@
 namespace pq {
 
 constexpr int PME_B = 8;
+constexpr int PME_WSTRIDE = 48;   // stored B-spline values per atom (weights, derivatives)
 
 // Cardinal B-spline weights M_p(f + t), t = 0..P-1 (grid point base - t), and
 // their derivatives, by the Cox-de Boor recursion, f in [0, 1).
@@ -110,21 +111,24 @@ __global__ void k_pme_order(int n, const int* __restrict__ brick_of, const int* 
     pme_frac[s0 + r] = frac_tmp[i];
 }
 
-// B-spline weights of every atom (brick order), computed once per set of
-// positions: pme_w[k] = {M_p(f_x + t)}_t, {M_p(f_y + t)}_t, {M_p(f_z + t)}_t,
-// each padded to 8 entries.
+// B-spline weights and derivatives of every atom (brick order), computed once
+// per set of positions: pme_w[48 k ...] = {M_p(f_x + t)}_t, {M_p(f_y + t)}_t,
+// {M_p(f_z + t)}_t, then the three derivative rows, each padded to 8 entries.
 template <int P, class T>
 __global__ void k_pme_weights(int n, const V4<T>* __restrict__ pme_frac, T* __restrict__ pme_w) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const V4<T> f4 = pme_frac[k];
     T w[P], dd[P];
-    T* out = pme_w + (size_t)k * 24;
+    T* out = pme_w + (size_t)k * PME_WSTRIDE;
     const T fr[3] = {f4.x, f4.y, f4.z};
     for (int d = 0; d < 3; ++d) {
         bspline<P, T>(fr[d], w, dd);
 #pragma unroll
-        for (int t = 0; t < 8; ++t) out[8 * d + t] = (t < P) ? w[t] : T(0);
+        for (int t = 0; t < 8; ++t) {
+            out[8 * d + t] = (t < P) ? w[t] : T(0);
+            out[24 + 8 * d + t] = (t < P) ? dd[t] : T(0);
+        }
     }
 }
 
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* _
         const int nb = min(SPREAD_BATCH, (s1 - k0 + SW - 1) / SW);
         if (lane < nb) {
             const int k = k0 + SW * lane;
-            const V4<T>* wk = reinterpret_cast<const V4<T>*>(pme_w + (size_t)k * 24);
+            const V4<T>* wk = reinterpret_cast<const V4<T>*>(pme_w + (size_t)k * PME_WSTRIDE);
             T* row = tb[lane];
 #pragma unroll
             for (int u = 0; u < 6; ++u) {
@@ -298,30 +302,38 @@ __global__ __launch_bounds__(64 * REDUCE_ROWS) void k_spread_reduce(PmeGeo G, co
 
 // Gathering (step 5): phi_rec,i = sum_k W_i(k) psi(k) and
 // F_rec,i = -q_i sum_k grad W_i(k) psi(k), from an LDS copy of the brick's
-// region of the convolved grid; eight lanes per atom, lane y < p walks the
-// (z, x) plane of stencil row y.
+// region of the convolved grid (staged row by row); eight lanes per atom,
+// lane y < p walks the (z, x) plane of stencil row y with the atom's stored
+// B-spline weights and derivatives.
 template <int P, bool FORCE, class T>
 __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
                                                 const int* __restrict__ pme_idx, const V4<T>* __restrict__ pme_frac,
-                                                const T* __restrict__ qbrick, const T* __restrict__ grid,
-                                                T* __restrict__ phi_out, V4<T>* __restrict__ f_out) {
+                                                const T* __restrict__ pme_w, const T* __restrict__ qbrick,
+                                                const T* __restrict__ grid, T* __restrict__ phi_out,
+                                                V4<T>* __restrict__ f_out) {
     constexpr int R = PME_B + P - 1;
+    static_assert(R <= 16, "a region row must fit 16 lanes");
     __shared__ T lds[R * R * R];
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
     if (s0 == s1) return;
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
-    for (int t = threadIdx.x; t < R * R * R; t += 256) {
-        const int lx = t % R, ly = (t / R) % R, lz = t / (R * R);
-        int X = x0 + lx, Y = y0 + ly, Z = z0 + lz;
+    {
+        // 16 lanes per region row, 16 rows per pass
+        const int lx = threadIdx.x & 15;
+        int X = x0 + lx;
         X += (X < 0) ? G.K0 : 0;
         X -= (X >= G.K0) ? G.K0 : 0;
-        Y += (Y < 0) ? G.K1 : 0;
-        Y -= (Y >= G.K1) ? G.K1 : 0;
-        Z += (Z < 0) ? G.K2 : 0;
-        Z -= (Z >= G.K2) ? G.K2 : 0;
-        lds[t] = grid[((size_t)Z * G.K1 + Y) * G.K0 + X];
+        for (int r = threadIdx.x >> 4; r < R * R; r += 16) {
+            const int ly = r % R, lz = r / R;
+            int Y = y0 + ly, Z = z0 + lz;
+            Y += (Y < 0) ? G.K1 : 0;
+            Y -= (Y >= G.K1) ? G.K1 : 0;
+            Z += (Z < 0) ? G.K2 : 0;
+            Z -= (Z >= G.K2) ? G.K2 : 0;
+            if (lx < R) lds[r * R + lx] = grid[((size_t)Z * G.K1 + Y) * G.K0 + X];
+        }
     }
     __syncthreads();
     const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
@@ -336,17 +348,21 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         T qq = 0;
         if (valid) {
             qq = qbrick[k];
-            const V4<T> f4 = pme_frac[k];
             i = pme_idx[k];
-            const int pk = unpack_int(f4.w);
+            const int pk = unpack_int(pme_frac[k].w);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
-            T wx[P], wy[P], wz[P], dx[P], dy[P], dz[P];
-            bspline<P, T>(f4.x, wx, dx);
-            bspline<P, T>(f4.y, wy, dy);
-            bspline<P, T>(f4.z, wz, dz);
             if (sub < P) {
+                const T* wk = pme_w + (size_t)k * PME_WSTRIDE;
+                T wx[P], wz[P], dx[P], dz[P];
+#pragma unroll
+                for (int t = 0; t < P; ++t) {
+                    wx[t] = wk[t];
+                    wz[t] = wk[16 + t];
+                    dx[t] = wk[24 + t];
+                    dz[t] = wk[40 + t];
+                }
+                const T wys = wk[8 + sub], dys = wk[32 + sub];
                 const int ly = gy - sub - y0;
-                const T wys = pick<P, T>(wy, sub), dys = pick<P, T>(dy, sub);
 #pragma unroll
                 for (int tz = 0; tz < P; ++tz) {
                     const T* row = lds + ((gz - tz - z0) * R + ly) * R + (gx - x0);
@@ -404,7 +420,7 @@ static void pme_setup_t(Ctx& c) {
     PmeGeo G = geo(c);
     c.f_k.ensure((size_t)n * sizeof(v4));   // temporary for the unsorted fractional parts
     c.pme_frac.ensure((size_t)n * sizeof(v4));
-    c.pme_w.ensure((size_t)n * 24 * sizeof(T));
+    c.pme_w.ensure((size_t)n * PME_WSTRIDE * sizeof(T));
     c.tmp_atoms.ensure(n);
     PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
     PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
@@ -467,10 +483,10 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER], s));
     if (force)
         PQ_LAUNCH((k_gather<P, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+                  as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     else
         PQ_LAUNCH((k_gather<P, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+                  as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER + 1], s));
 }
 

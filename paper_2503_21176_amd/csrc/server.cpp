@@ -78,7 +78,7 @@ double request_footprint(int64_t n, const pq_params& p, int restart) {
         const double R = 8 + p.order - 1;
         const double nbrick = std::ceil(p.grid[0] / 8.0) * std::ceil(p.grid[1] / 8.0) * std::ceil(p.grid[2] / 8.0);
         grid = K3 * rs + (p.grid[0] / 2 + 1) * (double)p.grid[1] * p.grid[2] * 2.0 * rs + nbrick * R * R * R * rs +
-               (double)n * 24.0 * rs;
+               (double)n * 48.0 * rs;
     } else {
         // k vectors, structure factors and the chunk partials of the direct sum
         const double nk = ((2.0 * p.kmax[0] + 1) * (2.0 * p.kmax[1] + 1) * (2.0 * p.kmax[2] + 1)) / 2.0 + 1.0;
