@@ -101,6 +101,47 @@ def crossover(sizes=(250, 500, 1000, 2000, 3000, 4000, 5000, 6000, 8000, 12000, 
                       "library_auto_pme_min_atoms": P.auto_pme_min_atoms()}), flush=True)
 
 
+def md_bench(n=3000, steps=200, dt=0.5, n_krylov=6, seed=41):
+    """Shadow XL-BOMD (pq_md_run) on a random ionic system at 0.1 atoms/A^3:
+    masses 16/23/35.5 amu, hardness U(20, 25) eV, 300 K start, the repulsive
+    V_short stand-in (400 exp(-r/0.25 A) eV), K = 5 dissipation, PME at the
+    parameters for delta = 5e-4 and rc = 9 A, rebuild every step. Prints one
+    JSON line: ms per MD step and the total-energy statistics."""
+    import torch
+
+    import paper_2503_21176_amd as P
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)  # noqa: E731
+    s = W.small_random(n, (n / 0.1) ** (1 / 3), seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    eta = rng.uniform(20.0, 25.0, n)
+    mass = rng.choice([16.0, 23.0, 35.5], n)
+    vel = rng.normal(0.0, 1.0, (n, 3)) * np.sqrt(0.02585 * 9.648533212331e-3 / mass)[:, None]
+    prm = P.choose_params(s.box, n, 9.0, 5e-4, 6, "pme")
+    ctx = P.Context(0)
+    pos = t(s.pos)
+    ctx.set_system(pos, prm)
+    r = ctx.qeq_solve(t(s.chi), t(eta), tol=1e-10, max_it=400, restart=100)
+    H = P.md_history(5)
+    hist = r.q.reshape(1, n).repeat(H, 1).contiguous()
+    v, m, chi, et = t(vel), t(mass), t(s.chi), t(eta)
+    ctx.md_run(pos, v, m, chi, et, hist, 5, dt_fs=dt, n_krylov=n_krylov, dissipation=5, rep_a=400.0, rep_rho=0.25)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = ctx.md_run(pos, v, m, chi, et, hist, steps, dt_fs=dt, n_krylov=n_krylov, dissipation=5, rep_a=400.0,
+                   rep_rho=0.25)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.close()
+    tot, ke = e[:, 3], e[:, 0]
+    slope = float(np.polyfit(np.arange(len(tot)) * dt * 1e-3, tot, 1)[0])
+    print(json.dumps({"md": "shadow XL-BOMD", "n_atoms": n, "steps": steps, "dt_fs": dt, "n_krylov": n_krylov,
+                      "grid": list(prm.grid), "ms_per_md_step": round(ms, 4), "md_steps_per_s": round(1e3 / ms, 1),
+                      "e_tot_std_eV": float(tot.std()), "e_tot_drift_eV_per_ps": slope, "ke_std_eV": float(ke.std()),
+                      "ke_mean_eV": float(ke.mean())}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,9 +157,14 @@ def main():
     ap.add_argument("--serve-only", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--crossover", action="store_true",
                     help="time direct Ewald against PME at equal accuracy over system sizes and exit")
+    ap.add_argument("--md", action="store_true",
+                    help="time shadow XL-BOMD steps (pq_md_run) on a 3000-atom system and exit")
     args = ap.parse_args()
     if args.crossover:
         crossover()
+        return
+    if args.md:
+        md_bench()
         return
     if args.serve_only:
         import paper_2503_21176_amd as P

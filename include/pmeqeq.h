@@ -266,6 +266,44 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
  * 1024..65536). */
 pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
 
+/* ---- shadow MD driver ----------------------------------------------------- */
+/* Shadow Born-Oppenheimer (XL-BOMD) molecular dynamics on the context's
+ * system (Section "Shadow Born-Oppenheimer MD for a Charge Equilibration
+ * Model"): the atoms move on the shadow potential with the force at fixed n
+ * (velocity Verlet); the extended charges follow n'' = -omega^2 K (q[n] - n),
+ * whose right-hand side each step approximates with n_krylov GMRES steps on
+ * J x = -(q[n] - n), integrated as
+ *   n(t+dt) = 2 n(t) - n(t-dt) + kappa x(t) + alpha sum_k c_k n(t - k dt)
+ * (kappa = dt^2 omega^2). dissipation = 5 takes the weak-dissipation scheme
+ * of extended-Lagrangian BOMD with K = 5 (kappa 1.82, alpha 0.018,
+ * c = -6, 14, -8, -3, 4, -1); dissipation = 0 uses alpha = 0 and the given
+ * kappa. The system is rebuilt (pq_set_system, the context's parameters) at
+ * every step. V_short, the paper's trained short-range model, is not part of
+ * this library: a repulsive pair term rep_a exp(-r/rep_rho) over every pair
+ * and image closer than the cutoff stands in for it (rep_a = 0: none; brute
+ * force over all pairs, FP64, meant for test systems of a few thousand atoms).
+ * Units: A, fs, amu, eV. */
+typedef struct pq_md_cfg {
+    double dt_fs;          /* time step in fs, > 0                                  */
+    int32_t n_krylov;      /* Krylov steps for n'' per MD step, 1..512               */
+    int32_t dissipation;   /* 0 or 5 (see above)                                    */
+    double kappa;          /* dt^2 omega^2 when dissipation = 0                      */
+    double rep_a, rep_rho; /* V_short stand-in: A (eV) >= 0, rho (A) > 0 when A > 0  */
+} pq_md_cfg;
+
+/* Runs `steps` steps from the state in pos, vel (device n x 3 FP64, updated
+ * in place; pos as accepted by pq_set_system, which the context must already
+ * have received for these positions) and n_hist (device, pq_md_history()
+ * vectors of n, newest first: n(t), n(t - dt), ...; updated in place).
+ * mass (amu), chi, eta (= u): device n FP64. energies: host (steps + 1) x 4
+ * FP64 or NULL, row t = {kinetic, shadow energy E(R, q[n], n), V_short,
+ * total} at step t (row 0: the initial state). Host-synchronising. */
+pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const double* mass, const double* chi,
+                    const double* eta, double q_tot, double* n_hist, int32_t steps, const pq_md_cfg* cfg,
+                    double* energies);
+/* Number of n vectors pq_md_run keeps for a dissipation setting (2 or 6). */
+int32_t pq_md_history(int32_t dissipation);
+
 /* ---- continuous-batching QEQ server -------------------------------------- */
 /* A server owns `slots` contexts on one device, each with its own HIP stream
  * and worker thread, and a scheduler thread. Submitted requests wait in FIFO

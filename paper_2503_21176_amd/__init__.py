@@ -12,6 +12,7 @@ import ctypes
 import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -30,7 +31,7 @@ EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create"
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
-           "pq_choose_params", "pq_auto_pme_min_atoms"]
+           "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -109,6 +110,8 @@ def load() -> ctypes.CDLL:
         "pq_set_tuning": (i32, [vp, ctypes.POINTER(TuneResult)]),
         "pq_choose_params": (i32, [ctypes.POINTER(dbl), i64, dbl, dbl, i32, i32, ctypes.POINTER(Params)]),
         "pq_auto_pme_min_atoms": (i64, []),
+        "pq_md_run": (i32, [vp, vp, vp, vp, vp, vp, dbl, vp, i32, ctypes.POINTER(MdCfg), vp]),
+        "pq_md_history": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -150,6 +153,16 @@ def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, met
         raise ValueError(method)
     p.flags = FLAG_FP64 if fp64 else 0
     return p
+
+
+class MdCfg(ctypes.Structure):
+    _fields_ = [("dt_fs", ctypes.c_double), ("n_krylov", ctypes.c_int32), ("dissipation", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("rep_a", ctypes.c_double), ("rep_rho", ctypes.c_double)]
+
+
+def md_history(dissipation: int) -> int:
+    """Number of n vectors the shadow-MD driver keeps (newest first)."""
+    return int(load().pq_md_history(int(dissipation)))
 
 
 def choose_params(box, n, cutoff, delta=5e-4, order=6, method="auto", fp64=False) -> Params:
@@ -304,6 +317,27 @@ class Context:
         _check(self.lib.pq_shadow_step(self.h, _ptr(chi), _ptr(eta), float(q_tot), _ptr(n_vec), int(n_krylov),
                                        _ptr(q), _ptr(f), _ptr(x), _ptr(e)))
         return q, f, x, e
+
+    def md_run(self, pos, vel, mass, chi, eta, n_hist, steps, dt_fs=0.5, n_krylov=8, dissipation=5, kappa=1.82,
+               rep_a=0.0, rep_rho=0.3, q_tot=0.0):
+        """Shadow XL-BOMD steps (pq_md_run). pos, vel (n x 3), n_hist
+        (md_history(dissipation) x n, newest first) are FP64 device tensors
+        updated in place; the context must hold the system at pos. Returns
+        the (steps + 1) x 4 energies {kinetic, shadow, V_short, total} (eV)."""
+        N = self.n
+        H = md_history(dissipation)
+        for t, shape, name in ((pos, (N, 3), "pos"), (vel, (N, 3), "vel"), (n_hist, (H, N), "n_hist")):
+            if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous()
+                    and tuple(t.shape) == shape and t.device == self.device):
+                raise ValueError(f"{name} must be a contiguous FP64 tensor of shape {shape} on {self.device}")
+        mass = self._vec(mass, N, "mass")
+        chi, eta = self._vec(chi, N, "chi"), self._vec(eta, N, "eta")
+        cfg = MdCfg(float(dt_fs), int(n_krylov), int(dissipation), float(kappa), float(rep_a), float(rep_rho))
+        e = np.zeros((int(steps) + 1, 4), dtype=np.float64)
+        self._sync_stream()
+        _check(self.lib.pq_md_run(self.h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(chi), _ptr(eta), float(q_tot),
+                                  _ptr(n_hist), int(steps), ctypes.byref(cfg), e.ctypes.data_as(ctypes.c_void_p)))
+        return e
 
     def qeq_vjp(self, chi, eta, q_star, gbar=None, tol=1e-8, max_it=1000):
         chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")

@@ -16,7 +16,7 @@ SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libpmeqeq.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["nbr.hip", "pair.hip", "pme.hip", "fft.hip", "ewald.hip", "vec.hip",
+SOURCES = ["nbr.hip", "pair.hip", "pme.hip", "fft.hip", "ewald.hip", "vec.hip", "md.hip",
            "abi.cpp", "krylov.cpp", "server.cpp"]
 
 ARCH = os.environ.get("PQ_OFFLOAD_ARCH", "gfx950")

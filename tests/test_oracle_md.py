@@ -1,0 +1,71 @@
+"""Pins of the FP64 shadow-MD oracle (oracle/md.py): the V_short stand-in
+against closed forms and finite differences, the dissipation coefficients,
+uniform motion, and the second order of the velocity-Verlet energy error."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import md as M
+
+COUL = dict(method="ewald", alpha=0.35, rc=6.0, kmax=5)
+
+
+def test_short_range_two_atoms_closed_form():
+    box = np.array([50.0, 50.0, 50.0])
+    pos = np.array([[10.0, 10.0, 10.0], [11.3, 10.4, 9.8]])
+    A, rho, rc = 300.0, 0.3, 6.0
+    F, E = M.short_range(pos, box, rc, A, rho)
+    d = pos[1] - pos[0]
+    r = np.linalg.norm(d)
+    assert abs(E - A * np.exp(-r / rho)) < 1e-13 * E
+    f1 = A / rho * np.exp(-r / rho) * d / r      # pushes atom 1 away from atom 0
+    assert np.allclose(F[1], f1, rtol=1e-12) and np.allclose(F[0], -f1, rtol=1e-12)
+
+
+def test_short_range_force_is_minus_gradient():
+    s = W.small_random(20, (20 / 0.1) ** (1 / 3), seed=3)   # L = 5.85 A < 2 rc: own images count
+    A, rho, rc = 200.0, 0.4, 4.0
+    F, _ = M.short_range(s.pos, s.box, rc, A, rho)
+    h = 1e-5
+    for i, d in [(0, 0), (3, 1), (7, 2), (11, 0)]:
+        p1, p2 = s.pos.copy(), s.pos.copy()
+        p1[i, d] += h
+        p2[i, d] -= h
+        fd = -(M.short_range(p1, s.box, rc, A, rho)[1] - M.short_range(p2, s.box, rc, A, rho)[1]) / (2 * h)
+        assert abs(fd - F[i, d]) < 1e-6 * (1 + abs(F[i, d]))
+
+
+def test_dissipation_coefficients_keep_constant_and_linear_histories():
+    kappa, alpha, c = M.XL5
+    k = np.arange(len(c))
+    assert sum(c) == 0.0 and float(np.dot(k, c)) == 0.0
+
+
+def test_uniform_motion_without_forces():
+    # no charges and no repulsion: every force vanishes and R advances by dt v
+    s = W.small_random(16, (16 / 0.1) ** (1 / 3), seed=4)
+    n = s.n
+    rng = np.random.default_rng(0)
+    vel = rng.normal(0, 3e-3, (n, 3))
+    hist = np.zeros((2, n))
+    pos, vel2, _, e = M.md_run(s.pos, vel, np.full(n, 20.0), s.box, COUL, np.zeros(n), np.full(n, 20.0), hist, 4,
+                               dt=0.5, dissipation=0, kappa=1.9)
+    assert np.allclose(pos, s.pos + 4 * 0.5 * vel, rtol=0, atol=1e-13)
+    assert np.array_equal(vel2, vel)
+    assert np.allclose(e[:, 3], e[0, 3], rtol=1e-14)
+
+
+def test_verlet_energy_error_is_second_order():
+    # repulsion only (no charges): E_tot fluctuates as dt^2
+    s = W.small_random(24, (24 / 0.1) ** (1 / 3), seed=6)
+    n = s.n
+    rng = np.random.default_rng(1)
+    vel = rng.normal(0, 2e-2, (n, 3))
+    mass = np.full(n, 20.0)
+    dev = []
+    for dt, steps in ((1.0, 40), (0.5, 80)):
+        *_, e = M.md_run(s.pos, vel, mass, s.box, COUL, np.zeros(n), np.full(n, 20.0), np.zeros((2, n)), steps,
+                         dt=dt, dissipation=0, kappa=1.9, rep_a=100.0, rep_rho=0.4)
+        dev.append(np.max(np.abs(e[:, 3] - e[0, 3])))
+    ratio = dev[0] / dev[1]
+    assert 3.0 < ratio < 5.0, ratio
