@@ -142,6 +142,64 @@ def md_bench(n=3000, steps=200, dt=0.5, n_krylov=6, seed=41):
                       "ke_mean_eV": float(ke.mean())}), flush=True)
 
 
+def md_sweep(n=300, steps=1000, dt=0.5, seed=51):
+    """Energy conservation against cost: regular Born-Oppenheimer MD with QEQ
+    solves to tolerance tol (Jacobi GMRES, warm start) against shadow MD with
+    m Krylov steps for n'' (K = 5 dissipation), from the same relaxed state
+    and 300 K velocities, NVE, rebuild every step. System: N random atoms at
+    0.1 atoms/A^3, masses 16 / 23 / 35.5 amu, chi ~ N(0, 1) eV, hardness
+    U(20, 25) eV, the repulsive V_short stand-in, PME at the parameters for
+    delta = 5e-4, rc = 7 A. One JSON line per run."""
+    import torch
+
+    import paper_2503_21176_amd as P
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)  # noqa: E731
+    s = W.small_random(n, (n / 0.1) ** (1 / 3), seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    eta = rng.uniform(20.0, 25.0, n)
+    mass = rng.choice([16.0, 23.0, 35.5], n)
+    prm = P.choose_params(s.box, n, 7.0, 5e-4, 6, "pme")
+    chi, et, m = t(s.chi), t(eta), t(mass)
+    rep = dict(rep_a=400.0, rep_rho=0.25)
+    ctx = P.Context(0)
+    pos = t(s.pos)
+    ctx.set_system(pos, prm)
+    r = ctx.qeq_solve(chi, et, tol=1e-12, max_it=600, restart=n + 1)
+    H = P.md_history(5)
+    hist = r.q.reshape(1, n).repeat(H, 1).contiguous()
+    # relax the random packing: short shadow runs with the velocities zeroed in between
+    v = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+    for _ in range(8):
+        v.zero_()
+        ctx.md_run(pos, v, m, chi, et, hist, 40, dt_fs=dt, n_krylov=8, dissipation=5, **rep)
+    pos0 = pos.clone()
+    ctx.set_system(pos0, prm)
+    q0 = ctx.qeq_solve(chi, et, tol=1e-12, max_it=600, restart=n + 1).q
+    vel0 = t(rng.normal(0.0, 1.0, (n, 3)) * np.sqrt(0.02585 * 9.648533212331e-3 / mass)[:, None])
+    runs = [("regular", tol) for tol in (1e-2, 1e-3, 1e-4, 1e-6, 1e-8)] + [("shadow", k) for k in (1, 2, 4, 8)]
+    for kind, val in runs:
+        p, vv = pos0.clone(), vel0.clone()
+        ctx.set_system(p, prm)
+        h = q0.reshape(1, n).repeat(H, 1).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if kind == "regular":
+            e = ctx.md_run(p, vv, m, chi, et, h, steps, dt_fs=dt, dissipation=5, regular=True, tol=val, max_it=400,
+                           restart=50, **rep)
+        else:
+            e = ctx.md_run(p, vv, m, chi, et, h, steps, dt_fs=dt, n_krylov=val, dissipation=5, **rep)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        tot = e[:, 3]
+        drift = float(np.polyfit(np.arange(len(tot)) * dt * 1e-3, tot, 1)[0])
+        print(json.dumps({"md": kind, ("tol" if kind == "regular" else "n_krylov"): val, "n_atoms": n,
+                          "steps": steps, "dt_fs": dt, "coulomb_evals_per_step": round(float(e[1:, 4].mean()), 2),
+                          "e_tot_std_eV": float(tot.std()), "e_tot_drift_eV_per_ps": drift,
+                          "ke_mean_eV": float(e[:, 0].mean()), "ms_per_md_step": round(ms, 4)}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,12 +217,17 @@ def main():
                     help="time direct Ewald against PME at equal accuracy over system sizes and exit")
     ap.add_argument("--md", action="store_true",
                     help="time shadow XL-BOMD steps (pq_md_run) on a 3000-atom system and exit")
+    ap.add_argument("--md-sweep", action="store_true",
+                    help="regular BO-MD over solver tolerances against shadow MD over Krylov steps and exit")
     args = ap.parse_args()
     if args.crossover:
         crossover()
         return
     if args.md:
         md_bench()
+        return
+    if args.md_sweep:
+        md_sweep()
         return
     if args.serve_only:
         import paper_2503_21176_amd as P

@@ -282,22 +282,36 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
  * this library: a repulsive pair term rep_a exp(-r/rep_rho) over every pair
  * and image closer than the cutoff stands in for it (rep_a = 0: none; brute
  * force over all pairs, FP64, meant for test systems of a few thousand atoms).
+ * mode PQ_MD_REGULAR runs regular Born-Oppenheimer MD instead (Section
+ * "Regular Born-Oppenheimer MD for a Charge Equilibration Model"): every step
+ * solves the QEQ system with pq_qeq_solve to relative residual tol (max_it
+ * products, GMRES(restart)), started from the previous step's charges, and
+ * moves the atoms with the force at those charges; n_hist[0] holds the start
+ * charges on entry and the last charges on return.
  * Units: A, fs, amu, eV. */
+enum { PQ_MD_SHADOW = 0, PQ_MD_REGULAR = 1 };
 typedef struct pq_md_cfg {
     double dt_fs;          /* time step in fs, > 0                                  */
     int32_t n_krylov;      /* Krylov steps for n'' per MD step, 1..512               */
     int32_t dissipation;   /* 0 or 5 (see above)                                    */
     double kappa;          /* dt^2 omega^2 when dissipation = 0                      */
     double rep_a, rep_rho; /* V_short stand-in: A (eV) >= 0, rho (A) > 0 when A > 0  */
+    int32_t mode;          /* PQ_MD_SHADOW or PQ_MD_REGULAR                          */
+    int32_t max_it;        /* regular mode: products per solve, >= 1                 */
+    int32_t restart;       /* regular mode: GMRES restart length, >= 1               */
+    int32_t reserved;
+    double tol;            /* regular mode: relative residual of each solve, > 0     */
 } pq_md_cfg;
 
 /* Runs `steps` steps from the state in pos, vel (device n x 3 FP64, updated
  * in place; pos as accepted by pq_set_system, which the context must already
  * have received for these positions) and n_hist (device, pq_md_history()
  * vectors of n, newest first: n(t), n(t - dt), ...; updated in place).
- * mass (amu), chi, eta (= u): device n FP64. energies: host (steps + 1) x 4
- * FP64 or NULL, row t = {kinetic, shadow energy E(R, q[n], n), V_short,
- * total} at step t (row 0: the initial state). Host-synchronising. */
+ * mass (amu), chi, eta (= u): device n FP64. energies: host (steps + 1) x 5
+ * FP64 or NULL, row t = {kinetic, potential (shadow energy E(R, q[n], n), or
+ * the QEQ energy E(R, q) in regular mode), V_short, total, Coulomb
+ * evaluations of that step's force evaluation} at step t (row 0: the initial
+ * state). Host-synchronising. */
 pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const double* mass, const double* chi,
                     const double* eta, double q_tot, double* n_hist, int32_t steps, const pq_md_cfg* cfg,
                     double* energies);

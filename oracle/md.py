@@ -84,14 +84,45 @@ def shadow_state(pos, box, coul, chi, eta, q_tot, n_vec, n_krylov, rep_a=0.0, re
     return F, x, E, Es, q
 
 
+def regular_state(pos, box, coul, chi, eta, q_tot, rep_a=0.0, rep_rho=0.3):
+    """Regular Born-Oppenheimer force and QEQ energy (Section "Regular
+    Born-Oppenheimer MD for a Charge Equilibration Model") at the exact QEQ
+    charges (dense LU of the bordered system): (F, E, V_short, q)."""
+    A = Q.coulomb_matrix(pos, box, coul)
+    q, _ = Q.qeq_dense(A, chi, eta, q_tot)
+    F = Q.force(pos, q, box, coul)
+    E = Q.qeq_energy(A, chi, eta, q)
+    Es = 0.0
+    if rep_a > 0.0:
+        Fs, Es = short_range(pos, box, coul["rc"], rep_a, rep_rho)
+        F = F + Fs
+    return F, float(E), Es, q
+
+
 def kinetic(vel, mass) -> float:
     return float(0.5 * np.sum(np.asarray(mass)[:, None] * vel * vel) / ACC)
 
 
 def md_run(pos, vel, mass, box, coul, chi, eta, n_hist, steps, dt=0.5, n_krylov=8, dissipation=5, kappa=1.82,
-           rep_a=0.0, rep_rho=0.3, q_tot=0.0):
+           rep_a=0.0, rep_rho=0.3, q_tot=0.0, regular=False):
     """Returns (pos, vel, n_hist, energies) after `steps` steps; n_hist is
-    newest first; energies[t] = (kinetic, shadow, V_short, total)."""
+    newest first; energies[t] = (kinetic, potential, V_short, total).
+    regular: Born-Oppenheimer MD on the exact QEQ charges instead (n_hist is
+    returned unchanged)."""
+    if regular:
+        pos = np.array(pos, np.float64)
+        vel = np.array(vel, np.float64)
+        mass = np.asarray(mass, np.float64)
+        F, E, Es, _ = regular_state(pos, box, coul, chi, eta, q_tot, rep_a, rep_rho)
+        rows = [(kinetic(vel, mass), E, Es, kinetic(vel, mass) + E + Es)]
+        for _ in range(steps):
+            vel = vel + 0.5 * dt * ACC * F / mass[:, None]
+            pos = pos + dt * vel
+            F, E, Es, _ = regular_state(pos, box, coul, chi, eta, q_tot, rep_a, rep_rho)
+            vel = vel + 0.5 * dt * ACC * F / mass[:, None]
+            ke = kinetic(vel, mass)
+            rows.append((ke, E, Es, ke + E + Es))
+        return pos, vel, np.array(n_hist, np.float64), np.array(rows)
     pos = np.array(pos, np.float64)
     vel = np.array(vel, np.float64)
     mass = np.asarray(mass, np.float64)

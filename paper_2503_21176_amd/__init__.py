@@ -157,7 +157,12 @@ def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, met
 
 class MdCfg(ctypes.Structure):
     _fields_ = [("dt_fs", ctypes.c_double), ("n_krylov", ctypes.c_int32), ("dissipation", ctypes.c_int32),
-                ("kappa", ctypes.c_double), ("rep_a", ctypes.c_double), ("rep_rho", ctypes.c_double)]
+                ("kappa", ctypes.c_double), ("rep_a", ctypes.c_double), ("rep_rho", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("max_it", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+MD_SHADOW, MD_REGULAR = 0, 1
 
 
 def md_history(dissipation: int) -> int:
@@ -319,11 +324,13 @@ class Context:
         return q, f, x, e
 
     def md_run(self, pos, vel, mass, chi, eta, n_hist, steps, dt_fs=0.5, n_krylov=8, dissipation=5, kappa=1.82,
-               rep_a=0.0, rep_rho=0.3, q_tot=0.0):
-        """Shadow XL-BOMD steps (pq_md_run). pos, vel (n x 3), n_hist
-        (md_history(dissipation) x n, newest first) are FP64 device tensors
-        updated in place; the context must hold the system at pos. Returns
-        the (steps + 1) x 4 energies {kinetic, shadow, V_short, total} (eV)."""
+               rep_a=0.0, rep_rho=0.3, q_tot=0.0, regular=False, tol=1e-6, max_it=200, restart=50):
+        """Shadow XL-BOMD steps, or regular BO-MD steps with QEQ solves to
+        ``tol`` (pq_md_run). pos, vel (n x 3), n_hist (md_history(dissipation)
+        x n, newest first; regular mode: row 0 the start charges) are FP64
+        device tensors updated in place; the context must hold the system at
+        pos. Returns the (steps + 1) x 5 rows {kinetic, potential, V_short,
+        total (eV), Coulomb evaluations of the step}."""
         N = self.n
         H = md_history(dissipation)
         for t, shape, name in ((pos, (N, 3), "pos"), (vel, (N, 3), "vel"), (n_hist, (H, N), "n_hist")):
@@ -332,8 +339,9 @@ class Context:
                 raise ValueError(f"{name} must be a contiguous FP64 tensor of shape {shape} on {self.device}")
         mass = self._vec(mass, N, "mass")
         chi, eta = self._vec(chi, N, "chi"), self._vec(eta, N, "eta")
-        cfg = MdCfg(float(dt_fs), int(n_krylov), int(dissipation), float(kappa), float(rep_a), float(rep_rho))
-        e = np.zeros((int(steps) + 1, 4), dtype=np.float64)
+        cfg = MdCfg(float(dt_fs), int(n_krylov), int(dissipation), float(kappa), float(rep_a), float(rep_rho),
+                    MD_REGULAR if regular else MD_SHADOW, int(max_it), int(restart), 0, float(tol))
+        e = np.zeros((int(steps) + 1, 5), dtype=np.float64)
         self._sync_stream()
         _check(self.lib.pq_md_run(self.h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(chi), _ptr(eta), float(q_tot),
                                   _ptr(n_hist), int(steps), ctypes.byref(cfg), e.ctypes.data_as(ctypes.c_void_p)))

@@ -15,6 +15,11 @@
 // 214109, 2009), K = 5: kappa = 1.82, alpha = 0.018,
 // c = (-6, 14, -8, -3, 4, -1); or, without dissipation, alpha = 0 and a
 // caller-chosen kappa.
+// Regular Born-Oppenheimer mode (Section "Regular Born-Oppenheimer MD for a
+// Charge Equilibration Model"): each force evaluation instead solves the QEQ
+// system to a relative residual tol by the Jacobi-preconditioned GMRES of
+// pq_qeq_solve, started from the previous step's charges, and takes the force
+// and energy at those charges (exact only at convergence).
 // V_short: the paper's short-range model is a trained network that is not
 // part of this library; a repulsive pair term A exp(-r/rho) summed over every
 // pair (and periodic image) closer than the cutoff stands in for it, in FP64,
@@ -35,6 +40,7 @@ namespace pq {
 
 constexpr double ACC_PER_EV_A_AMU = 9.648533212331e-3;   // (eV/A)/amu in A/fs^2
 constexpr int MD_TILE = 256;
+constexpr int MD_COLS = 5;   // kinetic, potential, V_short, total, Coulomb evaluations
 
 __global__ void k_md_kick(int64_t n3, double* __restrict__ v, const double* __restrict__ f,
                           const double* __restrict__ m, double c) {
@@ -144,15 +150,16 @@ __global__ __launch_bounds__(MD_TILE) void k_md_short(int n, const double* __res
 }
 
 __global__ void k_md_record(const double* __restrict__ kin_part, int nk, const double* __restrict__ sr_part, int ns,
-                            const double* __restrict__ e_shadow, double* __restrict__ row) {
+                            const double* __restrict__ e_pot, double evals, double* __restrict__ row) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double ke = 0.0, es = 0.0;
     for (int k = 0; k < nk; ++k) ke += kin_part[k];
     for (int k = 0; k < ns; ++k) es += sr_part[k];
     row[0] = ke;
-    row[1] = e_shadow[0];
+    row[1] = e_pot[0];
     row[2] = es;
-    row[3] = (ke + e_shadow[0]) + es;
+    row[3] = (ke + e_pot[0]) + es;
+    row[4] = evals;
 }
 
 void set_error(const std::string& m);
@@ -173,6 +180,11 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
     PQ_REQUIRE(std::isfinite(cfg.kappa) && cfg.rep_a >= 0.0 && (cfg.rep_a == 0.0 || cfg.rep_rho > 0.0),
                PQ_ERR_INVALID, "bad kappa or repulsion parameters");
     PQ_REQUIRE(steps >= 0, PQ_ERR_INVALID, "steps must be >= 0");
+    PQ_REQUIRE(cfg.mode == PQ_MD_SHADOW || cfg.mode == PQ_MD_REGULAR, PQ_ERR_INVALID, "unknown MD mode");
+    const bool regular = cfg.mode == PQ_MD_REGULAR;
+    if (regular)
+        PQ_REQUIRE(std::isfinite(cfg.tol) && cfg.tol > 0.0 && cfg.max_it >= 1 && cfg.restart >= 1, PQ_ERR_INVALID,
+                   "regular mode needs tol > 0, max_it >= 1, restart >= 1");
     const int64_t n = c.n;
     const int H = md_history(cfg.dissipation);
     XlCoef cf{};
@@ -198,12 +210,29 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
     esh.ensure(2);
     kin.ensure(kb);
     srp.ensure(std::max(1, sb));
-    rows.ensure((size_t)4 * (steps + 1));
+    rows.ensure((size_t)MD_COLS * (steps + 1));
+    DBuf<double> qprev;
+    if (regular) {
+        // charges of the previous step (start vector of each solve): n_hist[0] on entry
+        qprev.ensure(n);
+        PQ_HIP(hipMemcpyAsync(qprev.p, n_hist, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    }
+    double evals = 0.0;   // Coulomb evaluations of the current force evaluation
     int head = 0;   // n_hist is newest first on entry
     auto forces = [&](int row) {
         check(pq_set_system(reinterpret_cast<pq_ctx*>(&c), n, pos, &prm));
-        check(pq_shadow_step(reinterpret_cast<pq_ctx*>(&c), chi, eta, q_tot, n_hist + (size_t)head * n,
-                             cfg.n_krylov, qn.p, f.p, x.p, esh.p));
+        if (regular) {
+            pq_solve_info info{};
+            const pq_status st = pq_qeq_solve(reinterpret_cast<pq_ctx*>(&c), chi, eta, q_tot, cfg.tol, cfg.max_it,
+                                              cfg.restart, qprev.p, qn.p, f.p, esh.p, &info);
+            if (st != PQ_WARN_NOT_CONVERGED) check(st);
+            PQ_HIP(hipMemcpyAsync(qprev.p, qn.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+            evals = info.iterations + 1.0;   // products + the force evaluation
+        } else {
+            check(pq_shadow_step(reinterpret_cast<pq_ctx*>(&c), chi, eta, q_tot, n_hist + (size_t)head * n,
+                                 cfg.n_krylov, qn.p, f.p, x.p, esh.p));
+            evals = 3.0 + cfg.n_krylov;      // potential of n, two force evaluations, Krylov products
+        }
         if (cfg.rep_a > 0.0)
             PQ_LAUNCH(k_md_short, sb, MD_TILE, 0, s, (int)n, c.w64.p, prm.box[0], prm.box[1], prm.box[2],
                       prm.cutoff, cfg.rep_a, cfg.rep_rho, f.p, srp.p);
@@ -212,7 +241,7 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
     auto record = [&](int row) {
         PQ_LAUNCH(k_md_kinetic, kb, MD_TILE, 0, s, n, (const double*)vel, mass, kin.p);
         PQ_LAUNCH(k_md_record, 1, 64, 0, s, (const double*)kin.p, kb, (const double*)srp.p,
-                  cfg.rep_a > 0.0 ? sb : 0, (const double*)esh.p, rows.p + 4 * (size_t)row);
+                  cfg.rep_a > 0.0 ? sb : 0, (const double*)esh.p, evals, rows.p + (size_t)MD_COLS * row);
     };
     try {
         forces(0);
@@ -221,8 +250,10 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
         for (int t = 0; t < steps; ++t) {
             PQ_LAUNCH(k_md_kick, nb3, 256, 0, s, 3 * n, vel, (const double*)f.p, mass, hdt);
             PQ_LAUNCH(k_md_drift, nb3, 256, 0, s, 3 * n, pos, (const double*)vel, cfg.dt_fs);
-            PQ_LAUNCH(k_md_nupdate, nb1, 256, 0, s, n, n_hist, H, head, (const double*)x.p, kappa, alpha, cf);
-            head = (head + H - 1) % H;
+            if (!regular) {
+                PQ_LAUNCH(k_md_nupdate, nb1, 256, 0, s, n, n_hist, H, head, (const double*)x.p, kappa, alpha, cf);
+                head = (head + H - 1) % H;
+            }
             forces(t + 1);
             PQ_LAUNCH(k_md_kick, nb3, 256, 0, s, 3 * n, vel, (const double*)f.p, mass, hdt);
             record(t + 1);
@@ -234,8 +265,9 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
                       hist2.p);
             PQ_HIP(hipMemcpyAsync(n_hist, hist2.p, sizeof(double) * H * n, hipMemcpyDeviceToDevice, s));
         }
+        if (regular) PQ_HIP(hipMemcpyAsync(n_hist, qprev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
         if (energies)
-            PQ_HIP(hipMemcpyAsync(energies, rows.p, sizeof(double) * 4 * (steps + 1), hipMemcpyDeviceToHost, s));
+            PQ_HIP(hipMemcpyAsync(energies, rows.p, sizeof(double) * MD_COLS * (steps + 1), hipMemcpyDeviceToHost, s));
         PQ_HIP(hipStreamSynchronize(s));
     } catch (...) {
         c.graphs = graphs_was;

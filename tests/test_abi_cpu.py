@@ -75,3 +75,10 @@ def test_request_footprint_is_host_only_and_sane():
     assert fp(20000, restart=200) > b
     with pytest.raises(ValueError):
         P.request_footprint(0, P.make_params(10.0, 4.0, 0.5, grid=10, order=4))
+
+
+def test_md_cfg_layout_matches_header():
+    import paper_2503_21176_amd as P
+    # dt, (n_krylov, dissipation), kappa, rep_a, rep_rho, (mode, max_it), (restart, reserved), tol
+    assert ctypes.sizeof(P.MdCfg) == 64
+    assert P.MdCfg.kappa.offset == 16 and P.MdCfg.mode.offset == 40 and P.MdCfg.tol.offset == 56

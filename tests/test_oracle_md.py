@@ -69,3 +69,15 @@ def test_verlet_energy_error_is_second_order():
         dev.append(np.max(np.abs(e[:, 3] - e[0, 3])))
     ratio = dev[0] / dev[1]
     assert 3.0 < ratio < 5.0, ratio
+
+
+def test_shadow_step_at_the_ground_state_is_regular_bo():
+    # n = q*: q[n] = q*, the shadow force is F[q*] and the shadow energy the QEQ energy
+    s = W.small_random(24, (24 / 0.1) ** (1 / 3), seed=8)
+    eta = np.random.default_rng(2).uniform(20.0, 25.0, s.n)
+    F, E, _, q = M.regular_state(s.pos, s.box, COUL, s.chi, eta, 0.0)
+    Fs, x, Es, _, qs = M.shadow_state(s.pos, s.box, COUL, s.chi, eta, 0.0, q, 4)
+    assert np.allclose(qs, q, rtol=0, atol=1e-12)
+    assert np.allclose(Fs, F, rtol=1e-10, atol=1e-12)
+    assert abs(Es - E) < 1e-10 * abs(E)
+    assert np.abs(x).max() < 1e-9
