@@ -188,17 +188,21 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     E.end(PQ_PHASE_STAGE);
     // the real-space pair kernel (ALU bound) runs on the context's second
     // stream, concurrently with the memory-bound reciprocal-space chain
-    ensure_side(c);
-    hipStream_t ps = c.serial ? s : c.side;
-    ev_record(c.ev_fork, s);
-    stream_wait(ps, c.ev_fork);
+    // (serial contexts: on the same stream, no fork and join)
+    hipStream_t ps = s;
+    if (!c.serial) {
+        ensure_side(c);
+        ps = c.side;
+        ev_record(c.ev_fork, s);
+        stream_wait(ps, c.ev_fork);
+    }
     E.begin(PQ_PHASE_PAIR, ps);
     pair_sum(c, fo, ps);
     E.end(PQ_PHASE_PAIR, ps);
     // the total charge (background term) is only needed by the final combine:
     // summed after the pair kernel, off the reciprocal-space chain
     sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
-    ev_record(c.ev_join, ps);
+    if (ps != s) ev_record(c.ev_join, ps);
     if (c.prm.method == PQ_METHOD_PME) {
         pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s);
     } else {
@@ -210,7 +214,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
         ewald_eval(c, q, fo, s);
         E.end(PQ_PHASE_GATHER);
     }
-    stream_wait(s, c.ev_join);
+    if (ps != s) stream_wait(s, c.ev_join);
     E.begin(PQ_PHASE_COMBINE);
     combine(c, q, phi, force, energy, s);
     E.end(PQ_PHASE_COMBINE);

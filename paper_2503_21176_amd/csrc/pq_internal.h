@@ -288,7 +288,7 @@ struct Ctx {
 
     // --- phase timing ---
     bool timing = false;
-    bool serial = false;     // run the pair kernel on the main stream (phase timing mode 2)
+    bool serial = false;     // pair kernel on the main stream (phase timing mode 2, server slots)
     std::vector<hipEvent_t> ev_pool;          // free events
     std::vector<std::vector<hipEvent_t>> ev_pending;   // PQ_NPHASE*2 events per timed evaluation
 

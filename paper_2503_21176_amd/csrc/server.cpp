@@ -270,6 +270,9 @@ pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg) {
         // for contexts driven from one thread (several slots replaying their
         // graphs concurrently crashed the process; the cause is not known)
         reinterpret_cast<Ctx*>(sl->ctx)->graphs = false;
+        // requests overlap across slots, so a slot evaluates on its one
+        // stream: no second stream and no fork/join events per evaluation
+        reinterpret_cast<Ctx*>(sl->ctx)->serial = true;
         S->slots.push_back(std::move(sl));
     }
     for (auto& sl : S->slots) sl->th = std::thread(slot_main, S.get(), sl.get());
