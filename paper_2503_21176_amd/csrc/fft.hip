@@ -493,6 +493,124 @@ __global__ __launch_bounds__(CT*(R1 > R2 ? R1 : R2)) void k_fft_col2(const V2<T>
     }
 }
 
+// ---- x passes, two register radices --------------------------------------
+// The same decomposition along rows: a workgroup takes RP pairs of real rows,
+// each pair the complex sequence z = row0 + i row1 of length n = R1 R2.
+// Forward: thread (n2, pair) loads z[R2 n1 + n2] (R2 consecutive threads read
+// consecutive points of a row), R1-point DFT, twiddles, LDS; thread (k1, pair)
+// the R2-point DFT; the spectrum goes through LDS once more, where the two
+// half spectra are split off: H0[m] = (Z[m] + conj Z[n-m]) / 2,
+// H1[m] = (Z[m] - conj Z[n-m]) / 2i. Inverse: thread (n2, pair) builds
+// z[m] = H0[m] + i H1[m] (Hermitian halves for m > n/2) from the spectra,
+// R1-point DFT, twiddles, LDS; R2-point DFT; real and imaginary parts are the
+// two rows, stored from registers.
+constexpr int RP = 16;   // row pairs per workgroup
+
+template <int R1, int R2, class T>
+__global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_r2c(const V2<T>* __restrict__ wn, int nrows,
+                                                                       const T* __restrict__ grid,
+                                                                       V2<T>* __restrict__ spec) {
+    using C = V2<T>;
+    constexpr int N = R1 * R2, X = N / 2 + 1;
+    __shared__ C sm[N * RP];
+    const int p0 = blockIdx.x * RP;
+    {
+        const int n2 = threadIdx.x % R2, pr = threadIdx.x / R2;
+        const int r0 = 2 * (p0 + pr), r1 = r0 + 1;
+        if (pr < RP) {
+            C v[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                const int k = R2 * n1 + n2;
+                const T re = (r0 < nrows) ? grid[(size_t)r0 * N + k] : T(0);
+                const T im = (r1 < nrows) ? grid[(size_t)r1 * N + k] : T(0);
+                v[n1] = cmk<C>(re, im);
+            }
+            dft<R1, -1>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1)
+                sm[pr * N + k1 * R2 + n2] = (k1 == 0 || n2 == 0) ? v[k1] : cmul(v[k1], wn[(n2 * k1) % N]);
+        }
+    }
+    __syncthreads();
+    C u[R2];
+    const int k1 = threadIdx.x % R1, pb = threadIdx.x / R1;
+    if (pb < RP) {
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) u[n2] = sm[pb * N + k1 * R2 + n2];
+        dft<R2, -1>(u);
+    }
+    __syncthreads();
+    if (pb < RP) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) sm[pb * N + k1 + R1 * k2] = u[k2];
+    }
+    __syncthreads();
+    const T h = T(0.5);
+    for (int idx = threadIdx.x; idx < RP * X; idx += blockDim.x) {
+        const int pr = idx / X, m = idx - pr * X;
+        const int r0 = 2 * (p0 + pr), r1 = r0 + 1;
+        if (r0 >= nrows) continue;
+        const C z = sm[pr * N + m];
+        const C zr = sm[pr * N + (m == 0 ? 0 : N - m)];
+        spec[(size_t)r0 * X + m] = cmk<C>(h * (z.x + zr.x), h * (z.y - zr.y));
+        if (r1 < nrows) spec[(size_t)r1 * X + m] = cmk<C>(h * (z.y + zr.y), -h * (z.x - zr.x));
+    }
+}
+
+template <int R1, int R2, class T>
+__global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_c2r(const V2<T>* __restrict__ wn, int nrows,
+                                                                       const V2<T>* __restrict__ spec,
+                                                                       T* __restrict__ grid) {
+    using C = V2<T>;
+    constexpr int N = R1 * R2, X = N / 2 + 1;
+    __shared__ C sm[N * RP];
+    const int p0 = blockIdx.x * RP;
+    {
+        const int n2 = threadIdx.x % R2, pr = threadIdx.x / R2;
+        const int r0 = 2 * (p0 + pr), r1 = r0 + 1;
+        if (pr < RP) {
+            C v[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                const int m = R2 * n1 + n2;
+                C A = cmk<C>(T(0), T(0)), B = cmk<C>(T(0), T(0));
+                if (m < X) {
+                    if (r0 < nrows) A = spec[(size_t)r0 * X + m];
+                    if (r1 < nrows) B = spec[(size_t)r1 * X + m];
+                } else {
+                    if (r0 < nrows) A = spec[(size_t)r0 * X + (N - m)];
+                    if (r1 < nrows) B = spec[(size_t)r1 * X + (N - m)];
+                    A.y = -A.y;
+                    B.y = -B.y;
+                }
+                v[n1] = cmk<C>(A.x - B.y, A.y + B.x);
+            }
+            dft<R1, 1>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                C w = wn[(n2 * k1) % N];
+                w.y = -w.y;
+                sm[pr * N + k1 * R2 + n2] = (k1 == 0 || n2 == 0) ? v[k1] : cmul(v[k1], w);
+            }
+        }
+    }
+    __syncthreads();
+    const int k1 = threadIdx.x % R1, pb = threadIdx.x / R1;
+    if (pb < RP) {
+        C u[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) u[n2] = sm[pb * N + k1 * R2 + n2];
+        dft<R2, 1>(u);
+        const int r0 = 2 * (p0 + pb), r1 = r0 + 1;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            if (r0 < nrows) grid[(size_t)r0 * N + k1 + R1 * k2] = u[k2].x;
+            if (r1 < nrows) grid[(size_t)r1 * N + k1 + R1 * k2] = u[k2].y;
+        }
+    }
+}
+
 // Sum of n partials in a fixed order: thread t adds t, t + 1024, ... with four
 // independent accumulators (loads in flight together), then a block tree.
 __global__ __launch_bounds__(1024) void k_sum_part(const double* __restrict__ part, int n, double* __restrict__ out) {
@@ -708,6 +826,26 @@ static bool col2_launch(int r1, int r2, dim3 grid, hipStream_t s, const V2<T>* w
     return false;
 }
 
+// The two-radix x passes for (r1, r2); false if that pair has no instance.
+template <bool FWD, class T>
+static bool x2_launch(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn, int nrows, T* grid, V2<T>* spec) {
+#define PQ_X2(A, B)                                                                                          \
+    if (r1 == A && r2 == B) {                                                                                \
+        if (FWD)                                                                                             \
+            PQ_LAUNCH((k_fft_x2_r2c<A, B, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,          \
+                      (const T*)grid, spec);                                                                 \
+        else                                                                                                 \
+            PQ_LAUNCH((k_fft_x2_c2r<A, B, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,          \
+                      (const V2<T>*)spec, grid);                                                             \
+        return true;                                                                                         \
+    }
+    PQ_X2(3, 2) PQ_X2(4, 2) PQ_X2(3, 3) PQ_X2(5, 2) PQ_X2(4, 3) PQ_X2(5, 3) PQ_X2(4, 4) PQ_X2(9, 2)
+    PQ_X2(5, 4) PQ_X2(8, 3) PQ_X2(5, 5) PQ_X2(9, 3) PQ_X2(8, 4) PQ_X2(9, 4) PQ_X2(8, 5) PQ_X2(9, 5)
+    PQ_X2(16, 3) PQ_X2(8, 8) PQ_X2(9, 8) PQ_X2(16, 5) PQ_X2(9, 9) PQ_X2(16, 8) PQ_X2(16, 9) PQ_X2(16, 16)
+#undef PQ_X2
+    return false;
+}
+
 template <class T>
 static void fft_convolve_t(Ctx& c, hipStream_t s) {
     using C = V2<T>;
@@ -724,8 +862,12 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     ConvArgs cv{c.inf.T[0], c.inf.T[1], c.inf.T[2], c.inf.S[0], c.inf.S[1], c.inf.S[2], c.inf.scale, K0};
     const int np = row_pairs(K0, esz, c.fft_budget);
     const int npairs = (nrows + 1) / 2;
+    const C* wn0 = static_cast<const C*>(c.fft[0].wn);
+    const int x1 = c.fft[0].r1, x2 = c.fft[0].r2;
     // x forward
-    PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, grid, spec);
+    if (!x2_launch<true, T>(x1, x2, npairs, s, wn0, nrows, grid, spec))
+        PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, grid,
+                  spec);
     const C* wn1 = static_cast<const C*>(c.fft[1].wn);
     const C* wn2 = static_cast<const C*>(c.fft[2].wn);
     const int y1 = c.fft[1].r1, y2 = c.fft[1].r2, z1 = c.fft[2].r1, z2 = c.fft[2].r2;
@@ -750,7 +892,9 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
         PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X,
                   ty, (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
     // x inverse
-    PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, spec, grid);
+    if (!x2_launch<false, T>(x1, x2, npairs, s, wn0, nrows, grid, spec))
+        PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, spec,
+                  grid);
 }
 
 // grid (real, Q) -> grid (real, psi = conv(Q)); E_rec (without KE) into c.scal[1]
