@@ -252,18 +252,21 @@ typedef struct pq_tune_result {
     int32_t fft_lds_bytes;    /* LDS bytes per FFT ping-pong buffer (0: default 18432); */
                               /* smaller tiles let FFT workgroups run beside the pair  */
                               /* kernel; the results do not depend on it               */
-    int32_t reserved;
+    int32_t pair_fork;        /* PME: where the pair kernel's stream forks: 0 before   */
+                              /* the reciprocal chain, 1 after the first spreading     */
+                              /* pass, 2 after spreading; the results do not depend    */
+                              /* on it                                                 */
 } pq_tune_result;
 
 /* Times the pair-kernel shapes 0, 1, 2, 3, 4, 6, 8 jointly with FFT buffer
- * sizes of 18432, 9216 and 4608 bytes on `reps` (1..1000) potential + force
- * evaluations each, after one warm-up, of the current system with charges q
- * (device, n), and keeps the fastest for this context (also across later
- * pq_set_system calls). Phase timing must be off. Host-synchronising; out may
- * be NULL. */
+ * sizes of 18432, 9216 and 4608 bytes and (PME) the fork points 0, 1, 2 on
+ * `reps` (1..1000) potential + force evaluations each, after one warm-up, of
+ * the current system with charges q (device, n), and keeps the fastest for
+ * this context (also across later pq_set_system calls). Phase timing must be
+ * off. Host-synchronising; out may be NULL. */
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out);
 /* Applies a stored choice (pair_wg_per_cu in 0..64; fft_lds_bytes 0 or
- * 1024..65536). */
+ * 1024..65536; pair_fork 0..2). */
 pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
 
 /* ---- shadow MD driver ----------------------------------------------------- */

@@ -54,7 +54,7 @@ class SolveInfo(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("pair_wg_per_cu", ctypes.c_int32), ("candidates", ctypes.c_int32), ("ms", ctypes.c_double),
-                ("ms_default", ctypes.c_double), ("fft_lds_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("ms_default", ctypes.c_double), ("fft_lds_bytes", ctypes.c_int32), ("pair_fork", ctypes.c_int32)]
 
 
 class ServerCfg(ctypes.Structure):
@@ -270,10 +270,10 @@ class Context:
         t = TuneResult()
         _check(self.lib.pq_autotune(self.h, _ptr(q), int(reps), ctypes.byref(t)))
         return dict(pair_wg_per_cu=t.pair_wg_per_cu, candidates=t.candidates, ms=t.ms, ms_default=t.ms_default,
-                    fft_lds_bytes=t.fft_lds_bytes)
+                    fft_lds_bytes=t.fft_lds_bytes, pair_fork=t.pair_fork)
 
-    def set_tuning(self, pair_wg_per_cu: int, fft_lds_bytes: int = 0):
-        t = TuneResult(int(pair_wg_per_cu), 0, 0.0, 0.0, int(fft_lds_bytes), 0)
+    def set_tuning(self, pair_wg_per_cu: int, fft_lds_bytes: int = 0, pair_fork: int = 0):
+        t = TuneResult(int(pair_wg_per_cu), 0, 0.0, 0.0, int(fft_lds_bytes), int(pair_fork))
         _check(self.lib.pq_set_tuning(self.h, ctypes.byref(t)))
 
     def set_timing(self, mode=1):

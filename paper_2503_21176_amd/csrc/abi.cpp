@@ -188,24 +188,32 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
     E.end(PQ_PHASE_STAGE);
     // the real-space pair kernel (ALU bound) runs on the context's second
     // stream, concurrently with the memory-bound reciprocal-space chain
-    // (serial contexts: on the same stream, no fork and join)
+    // (serial contexts: on the same stream, no fork and join). With PME it
+    // forks before the chain, or (c.fork_at) after a spreading pass, so that
+    // spreading runs with the device to itself.
     hipStream_t ps = s;
-    if (!c.serial) {
-        ensure_side(c);
-        ps = c.side;
-        ev_record(c.ev_fork, s);
-        stream_wait(ps, c.ev_fork);
-    }
-    E.begin(PQ_PHASE_PAIR, ps);
-    pair_sum(c, fo, ps);
-    E.end(PQ_PHASE_PAIR, ps);
-    // the total charge (background term) is only needed by the final combine:
-    // summed after the pair kernel, off the reciprocal-space chain
-    sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
-    if (ps != s) ev_record(c.ev_join, ps);
+    auto fork_pair = [&]() {
+        if (!c.serial) {
+            ensure_side(c);
+            ps = c.side;
+            ev_record(c.ev_fork, s);
+            stream_wait(ps, c.ev_fork);
+        }
+        E.begin(PQ_PHASE_PAIR, ps);
+        pair_sum(c, fo, ps);
+        E.end(PQ_PHASE_PAIR, ps);
+        // the total charge (background term) is only needed by the final
+        // combine: summed after the pair kernel, off the reciprocal-space chain
+        sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
+        if (ps != s) ev_record(c.ev_join, ps);
+    };
     if (c.prm.method == PQ_METHOD_PME) {
-        pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s);
+        const bool late = c.fork_at > 0 && !c.serial;
+        if (!late) fork_pair();
+        pme_eval(c, q, fo, E.ev.empty() ? nullptr : E.ev.data(), s, late ? std::function<void()>(fork_pair)
+                                                                          : std::function<void()>());
     } else {
+        fork_pair();
         E.begin(PQ_PHASE_SPREAD);
         E.end(PQ_PHASE_SPREAD);
         E.begin(PQ_PHASE_FFT);
@@ -360,13 +368,16 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     PQ_HIP(hipEventCreate(&e1));
     const int cand[] = {0, 1, 2, 3, 4, 6, 8};
     const int budgets[] = {18432, 9216, 4608};
-    int best = 0, best_b = 18432, ntried = 0;
+    const int nfork = c.prm.method == PQ_METHOD_PME ? 3 : 1;
+    int best = 0, best_b = 18432, best_f = 0, ntried = 0;
     double best_ms = 1e300, ms0 = 0.0;
     try {
+        for (int fk = 0; fk < nfork; ++fk)
         for (int bgt : budgets)
         for (int k : cand) {
             c.pair_grid = k * ncu;
             c.fft_budget = bgt;
+            c.fork_at = fk;
             ++ntried;
             coulomb_eval(c, q, phi.p, f.p, e.p, s);
             PQ_HIP(hipEventRecord(e0, s));
@@ -376,11 +387,12 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
             float el = 0.f;
             PQ_HIP(hipEventElapsedTime(&el, e0, e1));
             const double ms = (double)el / reps;
-            if (k == 0 && bgt == 18432) ms0 = ms;
+            if (k == 0 && bgt == 18432 && fk == 0) ms0 = ms;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = k;
                 best_b = bgt;
+                best_f = fk;
             }
         }
     } catch (...) {
@@ -392,6 +404,7 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     (void)hipEventDestroy(e1);
     c.pair_grid = best * ncu;
     c.fft_budget = best_b;
+    c.fork_at = best_f;
     c.tune_ms = best_ms;
     if (out) {
         out->pair_wg_per_cu = best;
@@ -399,7 +412,7 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
         out->ms = best_ms;
         out->ms_default = ms0;
         out->fft_lds_bytes = best_b;
-        out->reserved = 0;
+        out->pair_fork = best_f;
     }
     return PQ_OK;
     PQ_API_END
@@ -411,8 +424,10 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
     PQ_REQUIRE(t->pair_wg_per_cu >= 0 && t->pair_wg_per_cu <= 64, PQ_ERR_INVALID, "pair_wg_per_cu must be in 0..64");
     PQ_REQUIRE(t->fft_lds_bytes == 0 || (t->fft_lds_bytes >= 1024 && t->fft_lds_bytes <= 65536), PQ_ERR_INVALID,
                "fft_lds_bytes must be 0 or in 1024..65536");
+    PQ_REQUIRE(t->pair_fork >= 0 && t->pair_fork <= 2, PQ_ERR_INVALID, "pair_fork must be in 0..2");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
     c.fft_budget = t->fft_lds_bytes ? t->fft_lds_bytes : 18432;
+    c.fork_at = t->pair_fork;
     PQ_HIP(hipSetDevice(c.device));
     int ncu = 0;
     PQ_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c.device));

@@ -86,7 +86,7 @@ hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, c
     std::vector<uintptr_t> key = {kind, (uintptr_t)opkey, (uintptr_t)nv, (uintptr_t)W.m, (uintptr_t)W.ld,
                                   (uintptr_t)c.kv.p, (uintptr_t)c.kw.p, (uintptr_t)c.kh.p, (uintptr_t)c.scal.p,
                                   (uintptr_t)c.part.p, (uintptr_t)c.kj.p, (uintptr_t)c.gen, (uintptr_t)c.pair_grid,
-                                  (uintptr_t)c.fft_budget};
+                                  (uintptr_t)c.fft_budget, (uintptr_t)c.fork_at};
     if (c.kgraph && key == c.kgraph_key) return c.kgraph;
     if (c.kgraph) {
         (void)hipGraphExecDestroy(c.kgraph);

@@ -468,14 +468,17 @@ void pme_setup(Ctx& c) {
 }
 
 template <int P, class T>
-static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
+static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
+                       const std::function<void()>& at_fork) {
     using v4 = V4<T>;
     PmeGeo G = geo(c);
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD], s));
     PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 64 * SW, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac), as<T>(c.pme_w),
               as<T>(c.qbrick), as<T>(c.stage));
+    if (at_fork && c.fork_at == 1) at_fork();
     PQ_LAUNCH((k_spread_reduce<P, T>), cdiv(c.K[1] * c.K[2], REDUCE_ROWS), 64 * REDUCE_ROWS, 0, s, G,
               as<T>(c.stage), as<T>(c.grid));
+    if (at_fork && c.fork_at == 2) at_fork();
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_SPREAD + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT], s));
     fft_convolve(c, s);
@@ -491,23 +494,25 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
 }
 
 template <class T>
-static void pme_eval_t(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
+static void pme_eval_t(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
+                       const std::function<void()>& at_fork) {
     switch (c.P) {
-        case 3: pme_eval_p<3, T>(c, q, force, ev, s); break;
-        case 4: pme_eval_p<4, T>(c, q, force, ev, s); break;
-        case 5: pme_eval_p<5, T>(c, q, force, ev, s); break;
-        case 6: pme_eval_p<6, T>(c, q, force, ev, s); break;
-        case 7: pme_eval_p<7, T>(c, q, force, ev, s); break;
-        case 8: pme_eval_p<8, T>(c, q, force, ev, s); break;
+        case 3: pme_eval_p<3, T>(c, q, force, ev, s, at_fork); break;
+        case 4: pme_eval_p<4, T>(c, q, force, ev, s, at_fork); break;
+        case 5: pme_eval_p<5, T>(c, q, force, ev, s, at_fork); break;
+        case 6: pme_eval_p<6, T>(c, q, force, ev, s, at_fork); break;
+        case 7: pme_eval_p<7, T>(c, q, force, ev, s, at_fork); break;
+        case 8: pme_eval_p<8, T>(c, q, force, ev, s, at_fork); break;
         default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
     }
 }
 
-void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s) {
+void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
+              const std::function<void()>& at_fork) {
     if (c.fp64)
-        pme_eval_t<double>(c, q, force, ev, s);
+        pme_eval_t<double>(c, q, force, ev, s, at_fork);
     else
-        pme_eval_t<float>(c, q, force, ev, s);
+        pme_eval_t<float>(c, q, force, ev, s, at_fork);
 }
 
 }  // namespace pq

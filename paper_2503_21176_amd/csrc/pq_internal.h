@@ -11,6 +11,7 @@
 #include <utility>
 #include <stdexcept>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "pmeqeq.h"
@@ -280,6 +281,8 @@ struct Ctx {
     bool want_energy = true; // the current evaluation reports energies (E_rec reduction)
     int pair_grid = 0;       // pair kernel workgroups (0: one wavefront per i-cluster)
     int fft_budget = 18432;  // bytes per FFT ping-pong buffer (sets the tile sizes)
+    int fork_at = 0;         // PME: where the pair kernel's stream forks (0 start, 1 after the
+                             // spreading pass 1, 2 after spreading)
     double tune_ms = 0.0;    // evaluation time of the chosen shape
 
     // --- second stream: the pair kernel overlaps the PME chain ---
@@ -333,7 +336,10 @@ void pair_sum(Ctx& c, bool force, hipStream_t s);   // into c.phi_r, c.f_r
 // pme.hip
 void pme_setup(Ctx& c);
 // ev: 2*PQ_NPHASE timing events or NULL (spread, FFT and gather phases are recorded)
-void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s);   // into c.phi_k, c.f_k
+// into c.phi_k, c.f_k; calls at_fork (if not empty) after the spreading
+// kernel c.fork_at names (1: pass 1, 2: pass 2)
+void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
+              const std::function<void()>& at_fork = {});
 // fft.hip
 void fft_setup(Ctx& c);
 void fft_convolve(Ctx& c, hipStream_t s);   // grid -> psi in place; energy partials into c.part

@@ -231,22 +231,22 @@ def test_invalid_arguments_raise(P):
 
 def test_pair_launch_shapes_bitwise_and_autotune(P):
     # the pair kernel's launch shape (one wavefront per cluster, or k
-    # workgroups per CU striding over clusters) and the FFT tile sizes change
-    # nothing in the results
+    # workgroups per CU striding over clusters), the FFT tile sizes and the
+    # point where the pair kernel's stream forks change nothing in the results
     s = W.random_ionic(n=3000, seed=9, grid=None, order=6)
     ctx = P.Context(0)
     ctx.set_system(gpu(s.pos), P.make_params(s.box, 10.0, W.ALPHA_RC10, grid=32, order=6))
     q = gpu(s.q)
     outs = []
-    for k, fb in ((0, 0), (1, 0), (2, 9216), (8, 4608), (64, 2048)):
-        ctx.set_tuning(k, fb)
+    for k, fb, fk in ((0, 0, 0), (1, 0, 1), (2, 9216, 2), (8, 4608, 0), (64, 2048, 1), (0, 0, 2)):
+        ctx.set_tuning(k, fb, fk)
         phi, F, E = ctx.coulomb(q)
         outs.append((phi.cpu().numpy(), F.cpu().numpy(), E.cpu().numpy()))
     for o in outs[1:]:
         assert all(np.array_equal(a, b) for a, b in zip(o, outs[0]))
     t = ctx.autotune(q, reps=2)
     say(f"[autotune] {t}")
-    assert t["pair_wg_per_cu"] in (0, 1, 2, 3, 4, 6, 8) and t["candidates"] == 21
+    assert t["pair_wg_per_cu"] in (0, 1, 2, 3, 4, 6, 8) and t["candidates"] == 63 and t["pair_fork"] in (0, 1, 2)
     assert t["fft_lds_bytes"] in (18432, 9216, 4608)
     assert 0.0 < t["ms"] <= t["ms_default"]
     phi, F, E = ctx.coulomb(q)
