@@ -78,6 +78,75 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ in, int* 
     if (t == 0) out[n] = carry;
 }
 
+// Wavefront-wide inclusive prefix sum.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over several workgroups for long arrays: SCAN_BLOCK values
+// per workgroup; k_scan_part sums each block, k_scan_apply adds the sums of the
+// blocks before its own (read directly, they are few) to a scan of its block.
+constexpr int SCAN_BLOCK = 4096;   // 1024 threads x 4 consecutive values
+template <int OP>
+__device__ __forceinline__ int scan_val(const int* __restrict__ in, int i, int n) {
+    if (i >= n) return 0;
+    return (OP == 1) ? (in[i] + CL - 1) / CL : in[i];
+}
+__device__ __forceinline__ int block_sum_int(int v, int* lds /* 16 */) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < 16; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+template <int OP>
+__global__ __launch_bounds__(1024) void k_scan_part(const int* __restrict__ in, int n, int* __restrict__ part) {
+    __shared__ int lds[16];
+    const int b0 = blockIdx.x * SCAN_BLOCK + 4 * threadIdx.x;
+    int v = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v += scan_val<OP>(in, b0 + r, n);
+    v = block_sum_int(v, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+template <int OP>
+__global__ __launch_bounds__(1024) void k_scan_apply(const int* __restrict__ in, int* __restrict__ out, int n,
+                                                     const int* __restrict__ part) {
+    __shared__ int lds[16];
+    __shared__ int wtot[16];
+    const int t = threadIdx.x, lane = lane_id(), w = t >> 6;
+    int off = 0;
+    for (int k = t; k < (int)blockIdx.x; k += 1024) off += part[k];
+    off = block_sum_int(off, lds);
+    const int b0 = blockIdx.x * SCAN_BLOCK + 4 * t;
+    int v[4], sum = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        v[r] = scan_val<OP>(in, b0 + r, n);
+        sum += v[r];
+    }
+    const int incl = wave_incl_scan(sum);
+    if (lane == 63) wtot[w] = incl;
+    __syncthreads();
+    int before = off;
+    for (int k = 0; k < w; ++k) before += wtot[k];
+    int run = before + incl - sum;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (b0 + r < n) out[b0 + r] = run;
+        run += v[r];
+    }
+    if (blockIdx.x == gridDim.x - 1 && t == 1023) out[n] = run;
+}
+
 __global__ void k_bin(int n, const int* __restrict__ col_of, const int* __restrict__ col_start,
                       int* __restrict__ col_fill, int* __restrict__ tmp) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -86,21 +155,38 @@ __global__ void k_bin(int n, const int* __restrict__ col_of, const int* __restri
     tmp[col_start[c] + atomicAdd(&col_fill[c], 1)] = i;
 }
 
-// Rank of each atom inside its column by (z, index): a deterministic sort.
-__global__ void k_rank(int n, const int* __restrict__ col_of, const int* __restrict__ col_start,
-                       const int* __restrict__ col_cl, const int* __restrict__ tmp,
-                       const double* __restrict__ w64, int* __restrict__ orig) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int c = col_of[i];
-    double zi = w64[3 * (size_t)i + 2];
-    int r = 0;
-    for (int k = col_start[c]; k < col_start[c + 1]; ++k) {
-        int j = tmp[k];
-        double zj = w64[3 * (size_t)j + 2];
-        r += (zj < zi) || (zj == zi && j < i);
+// Rank of each atom inside its column by (z, index), a deterministic sort:
+// one workgroup per column stages the column's (z, index) keys in LDS and
+// every atom counts the keys below its own there.
+// Columns longer than RANK_CAP atoms count from global memory instead.
+constexpr int RANK_CAP = 2048;
+__global__ __launch_bounds__(256) void k_rank_col(int ncol, const int* __restrict__ col_start,
+                                                  const int* __restrict__ col_cl, const int* __restrict__ tmp,
+                                                  const double* __restrict__ w64, int* __restrict__ orig) {
+    __shared__ double sz[RANK_CAP];
+    __shared__ int si[RANK_CAP];
+    const int c = blockIdx.x;
+    if (c >= ncol) return;
+    const int k0 = col_start[c], m = col_start[c + 1] - k0;
+    const bool lds = m <= RANK_CAP;
+    if (lds)
+        for (int t = threadIdx.x; t < m; t += blockDim.x) {
+            const int j = tmp[k0 + t];
+            si[t] = j;
+            sz[t] = w64[3 * (size_t)j + 2];
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+        const int i = lds ? si[t] : tmp[k0 + t];
+        const double zi = lds ? sz[t] : w64[3 * (size_t)i + 2];
+        int r = 0;
+        for (int u = 0; u < m; ++u) {
+            const int j = lds ? si[u] : tmp[k0 + u];
+            const double zj = lds ? sz[u] : w64[3 * (size_t)j + 2];
+            r += (zj < zi) || (zj == zi && j < i);
+        }
+        orig[(size_t)col_cl[c] * CL + r] = i;
     }
-    orig[(size_t)col_cl[c] * CL + r] = i;
 }
 
 __global__ void k_cluster_col(int ncol, const int* __restrict__ col_cl, int* __restrict__ cl_col) {
@@ -109,11 +195,12 @@ __global__ void k_cluster_col(int ncol, const int* __restrict__ col_cl, int* __r
     for (int k = col_cl[c]; k < col_cl[c + 1]; ++k) cl_col[k] = c;
 }
 
-// Bounding box, reference point and offsets (bulk precision T) of each cluster.
+// Bounding box, reference point and offsets (bulk precision T) of each cluster;
+// cpos: the wrapped FP64 positions in slot order (w = 1, padding w = 0).
 template <class T>
 __global__ void k_cluster(int ncl, const int* __restrict__ orig, const double* __restrict__ w64,
                           double* __restrict__ ref, double* __restrict__ lo, double* __restrict__ hi,
-                          V4<T>* __restrict__ xyzq) {
+                          V4<T>* __restrict__ xyzq, double4* __restrict__ cpos) {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncl) return;
     double l[3] = {1e300, 1e300, 1e300}, h[3] = {-1e300, -1e300, -1e300};
@@ -137,16 +224,19 @@ __global__ void k_cluster(int ncl, const int* __restrict__ orig, const double* _
         size_t s = (size_t)c * CL + a;
         int i = orig[s];
         V4<T> v;
+        double4 p = make_double4(0.0, 0.0, 0.0, 0.0);
         if (i >= 0) {
-            v.x = (T)(w64[3 * (size_t)i + 0] - r[0]);
-            v.y = (T)(w64[3 * (size_t)i + 1] - r[1]);
-            v.z = (T)(w64[3 * (size_t)i + 2] - r[2]);
+            p = make_double4(w64[3 * (size_t)i + 0], w64[3 * (size_t)i + 1], w64[3 * (size_t)i + 2], 1.0);
+            v.x = (T)(p.x - r[0]);
+            v.y = (T)(p.y - r[1]);
+            v.z = (T)(p.z - r[2]);
         } else {
             // padding: far from everything, zero charge
             v.x = v.y = v.z = (T)1.0e4;
         }
         v.w = (T)0;
         xyzq[s] = v;
+        cpos[s] = p;
     }
 }
 
@@ -154,9 +244,15 @@ __device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, do
     return fmax(0.0, fmax(lo_j - hi_i, lo_i - hi_j));
 }
 
-// Cluster-pair list: one wavefront per i-cluster; lanes scan the clusters of
-// each candidate column and every z image. FILL = false counts, FILL = true
-// writes at lstart[ic] in the same deterministic order.
+// Cluster-pair list: one wavefront per i-cluster. The candidate columns (the
+// periodic (2Rx+1) x (2Ry+1) neighbourhood, dy-major) are taken 64 at a time,
+// one per lane: a column whose x-y strip lies beyond the list radius drops
+// out, the others put their clusters into one flat sequence that the
+// wavefront walks 64 clusters per step, testing bounding boxes at every z
+// image. LIST_UNROLL steps load their cluster bounds before any is tested, so
+// that their latencies overlap. FILL = false counts, FILL = true writes at
+// lstart[ic] in the same deterministic order (flat position, then z image).
+constexpr int LIST_UNROLL = 4;
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
                                               const int* __restrict__ col_cl, const double* __restrict__ lo,
@@ -171,41 +267,75 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
     const int cxi = coli % g.ncx, cyi = coli / g.ncx;
     const double loi0 = lo[3 * ic], loi1 = lo[3 * ic + 1], loi2 = lo[3 * ic + 2];
     const double hii0 = hi[3 * ic], hii1 = hi[3 * ic + 1], hii2 = hi[3 * ic + 2];
+    const int nxc = 2 * g.Rx + 1, ncand = nxc * (2 * g.Ry + 1);
     int cnt = 0;
     const int base = FILL ? lstart[ic] : 0;
-    for (int dy = -g.Ry; dy <= g.Ry; ++dy) {
-        int cy = cyi + dy;
-        int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
-        int cyw = cy - ny * g.ncy;
-        double sy = (double)ny * g.L[1];
-        double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
-        if (gy > 0.0 && gy * gy >= rl2) continue;
-        for (int dx = -g.Rx; dx <= g.Rx; ++dx) {
-            int cx = cxi + dx;
-            int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
-            int cxw = cx - nx * g.ncx;
-            double sx = (double)nx * g.L[0];
-            double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
-            if (gx > 0.0 && gx * gx >= rl2) continue;
-            const int col = cxw + g.ncx * cyw;
-            const int j0 = col_cl[col], j1 = col_cl[col + 1];
-            for (int jb = j0; jb < j1; jb += 64) {
-                const int jc = jb + lane;
-                const bool valid = jc < j1;
-                double dxy2 = 0.0, loj2 = 0.0, hij2 = 0.0;
-                if (valid) {
-                    double gxx = gap1(lo[3 * jc] + sx, hi[3 * jc] + sx, loi0, hii0);
-                    double gyy = gap1(lo[3 * jc + 1] + sy, hi[3 * jc + 1] + sy, loi1, hii1);
-                    dxy2 = gxx * gxx + gyy * gyy;
-                    loj2 = lo[3 * jc + 2];
-                    hij2 = hi[3 * jc + 2];
+    for (int cb = 0; cb < ncand; cb += 64) {
+        // this lane's candidate column: its clusters [j0, j0 + nc) and image (nx, ny)
+        const int k = cb + lane;
+        int j0 = 0, nc = 0, img = 0;
+        if (k < ncand) {
+            const int dy = k / nxc - g.Ry, dx = k % nxc - g.Rx;
+            const int cy = cyi + dy;
+            const int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
+            const int cyw = cy - ny * g.ncy;
+            const double sy = (double)ny * g.L[1];
+            const double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
+            const int cx = cxi + dx;
+            const int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
+            const int cxw = cx - nx * g.ncx;
+            const double sx = (double)nx * g.L[0];
+            const double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
+            if (!(gy > 0.0 && gy * gy >= rl2) && !(gx > 0.0 && gx * gx >= rl2)) {
+                const int col = cxw + g.ncx * cyw;
+                j0 = col_cl[col];
+                nc = col_cl[col + 1] - j0;
+                img = pack_img(nx, ny, 0);
+            }
+        }
+        const int incl = wave_incl_scan(nc);
+        const int total = __shfl(incl, 63, 64);
+        const int jofs = j0 - (incl - nc);   // cluster = flat position + jofs of the owning lane
+        for (int fb = 0; fb < total; fb += 64 * LIST_UNROLL) {
+            int jc[LIST_UNROLL], im[LIST_UNROLL];
+            double l0[LIST_UNROLL], l1[LIST_UNROLL], l2[LIST_UNROLL];
+            double h0[LIST_UNROLL], h1[LIST_UNROLL], h2[LIST_UNROLL];
+#pragma unroll
+            for (int u = 0; u < LIST_UNROLL; ++u) {
+                const int f = fb + 64 * u + lane;
+                // owner: the first lane whose inclusive count exceeds f
+                int o = 0;
+#pragma unroll
+                for (int st = 32; st >= 1; st >>= 1)
+                    if (__shfl(incl, o + st - 1, 64) <= f) o += st;
+                jc[u] = f + __shfl(jofs, o, 64);
+                im[u] = __shfl(img, o, 64);
+                l0[u] = l1[u] = l2[u] = h0[u] = h1[u] = h2[u] = 0.0;
+                if (f < total) {
+                    l0[u] = lo[3 * jc[u]];
+                    l1[u] = lo[3 * jc[u] + 1];
+                    l2[u] = lo[3 * jc[u] + 2];
+                    h0[u] = hi[3 * jc[u]];
+                    h1[u] = hi[3 * jc[u] + 1];
+                    h2[u] = hi[3 * jc[u] + 2];
                 }
+            }
+#pragma unroll
+            for (int u = 0; u < LIST_UNROLL; ++u) {
+                if (fb + 64 * u >= total) break;
+                const bool valid = fb + 64 * u + lane < total;
+                int nx, ny, nz0;
+                unpack_img(im[u], nx, ny, nz0);
+                const double sx = (double)nx * g.L[0], sy = (double)ny * g.L[1];
+                const double gxx = gap1(l0[u] + sx, h0[u] + sx, loi0, hii0);
+                const double gyy = gap1(l1[u] + sy, h1[u] + sy, loi1, hii1);
+                const double dxy2 = gxx * gxx + gyy * gyy;
                 for (int nz = -g.Rz; nz <= g.Rz; ++nz) {
-                    double sz = (double)nz * g.L[2];
-                    double gz = gap1(loj2 + sz, hij2 + sz, loi2, hii2);
-                    bool pass = valid && (dxy2 + gz * gz < rl2);
-                    unsigned long long m = __ballot(pass);
-                    if (FILL && pass) lj[base + cnt + lanes_below(m)] = make_int2(jc, pack_img(nx, ny, nz));
+                    const double sz = (double)nz * g.L[2];
+                    const double gz = gap1(l2[u] + sz, h2[u] + sz, loi2, hii2);
+                    const bool pass = valid && (dxy2 + gz * gz < rl2);
+                    const unsigned long long m = __ballot(pass);
+                    if (FILL && pass) lj[base + cnt + lanes_below(m)] = make_int2(jc[u], pack_img(nx, ny, nz));
                     cnt += __popcll(m);
                 }
             }
@@ -259,24 +389,23 @@ __device__ __forceinline__ long long inv_mod(long long s, long long n) {
 
 template <bool FILL, class T>
 __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lstart,
-                                               const int2* __restrict__ lj, const int* __restrict__ orig,
-                                               const double* __restrict__ w64, const double* __restrict__ ref,
-                                               int* __restrict__ jcount, const int* __restrict__ jstart,
-                                               V4<T>* __restrict__ jl) {
+                                               const int2* __restrict__ lj, const double4* __restrict__ cpos,
+                                               const double* __restrict__ ref, int* __restrict__ jcount,
+                                               const int* __restrict__ jstart, V4<T>* __restrict__ jl) {
     const int lane = lane_id();
     const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (ic >= ncl) return;
     const double rc2 = g.rc * g.rc;
     // the i-cluster's atoms (the same in every lane)
-    int ii[CL];
+    bool ireal[CL];
     double wi[CL][3];
 #pragma unroll
     for (int a = 0; a < CL; ++a) {
-        ii[a] = orig[(size_t)ic * CL + a];
-        const int k = ii[a] >= 0 ? ii[a] : 0;
-        wi[a][0] = w64[3 * (size_t)k + 0];
-        wi[a][1] = w64[3 * (size_t)k + 1];
-        wi[a][2] = w64[3 * (size_t)k + 2];
+        const double4 p = cpos[(size_t)ic * CL + a];
+        ireal[a] = p.w != 0.0;
+        wi[a][0] = p.x;
+        wi[a][1] = p.y;
+        wi[a][2] = p.z;
     }
     const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
     const int e0 = lstart[ic], e1 = lstart[ic + 1];
@@ -293,34 +422,42 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
         }
     }
     auto dest = [&](long long k) -> size_t { return base + (size_t)(((k >> 3) * sinv) % nrow) * CL + (k & 7); };
+    // two-stage load pipeline: the list entry of step s + 2 and the j position
+    // of step s + 1 are in flight while step s is tested
+    auto entry = [&](int eb) -> int2 { const int e = eb + eo; return e < e1 ? lj[e] : make_int2(-1, 0); };
+    auto jpos = [&](int2 je) -> double4 {
+        return je.x >= 0 ? cpos[(size_t)je.x * CL + b] : make_double4(0.0, 0.0, 0.0, 0.0);
+    };
+    int2 je1 = entry(e0);
+    double4 p1 = jpos(je1);
+    int2 je2 = entry(e0 + 8);
     int cnt = 0;
     for (int eb = e0; eb < e1; eb += 8) {
-        const int e = eb + eo;
-        int col = 0, slot = 0;
-        double p0 = 0.0, p1 = 0.0, p2 = 0.0;
-        if (e < e1) {
-            const int2 je = lj[e];
-            slot = je.x * CL + b;
-            const int j = orig[slot];
-            if (j >= 0) {
-                int n0, n1, n2;
-                unpack_img(je.y, n0, n1, n2);
-                const double* wj = w64 + 3 * (size_t)j;
+        const int2 je = je1;
+        const double4 pj = p1;
+        je1 = je2;
+        p1 = jpos(je1);
+        je2 = entry(eb + 16);
+        int col = 0;
+        double p0 = 0.0, pp1 = 0.0, p2 = 0.0;
+        if (pj.w != 0.0) {
+            int n0, n1, n2;
+            unpack_img(je.y, n0, n1, n2);
+            const double wj[3] = {pj.x, pj.y, pj.z};
 #pragma unroll
-                for (int a = 0; a < CL; ++a) {
-                    const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
-                    if (ii[a] >= 0 && d2 > 0.0 && d2 < rc2) col |= 1 << a;
-                }
-                p0 = wj[0] + (double)n0 * g.L[0];
-                p1 = wj[1] + (double)n1 * g.L[1];
-                p2 = wj[2] + (double)n2 * g.L[2];
+            for (int a = 0; a < CL; ++a) {
+                const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
+                if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
             }
+            p0 = pj.x + (double)n0 * g.L[0];
+            pp1 = pj.y + (double)n1 * g.L[1];
+            p2 = pj.z + (double)n2 * g.L[2];
         }
         const bool pass = col != 0;
         const unsigned long long m = __builtin_amdgcn_ballot_w64(pass);
         if (FILL && pass) {
-            jl[dest(cnt + lanes_below(m))] =
-                mk4<T>((T)(p0 - r0), (T)(p1 - r1), (T)(p2 - r2), pack_int(slot | (col << JL_SLOT_BITS), T(0)));
+            jl[dest(cnt + lanes_below(m))] = mk4<T>((T)(p0 - r0), (T)(pp1 - r1), (T)(p2 - r2),
+                                                    pack_int((je.x * CL + b) | (col << JL_SLOT_BITS), T(0)));
         }
         cnt += __popcll(m);
     }
@@ -377,11 +514,23 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
     }
 }
 
-void scan_ints(const int* in, int* out, int n, bool ceil8, hipStream_t s) {
-    if (ceil8)
-        PQ_LAUNCH(k_scan<1>, 1, 1024, 0, s, in, out, n);
-    else
-        PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, in, out, n);
+void scan_ints(Ctx& c, const int* in, int* out, int n, bool ceil8, hipStream_t s) {
+    if (n <= SCAN_BLOCK) {
+        if (ceil8)
+            PQ_LAUNCH(k_scan<1>, 1, 1024, 0, s, in, out, n);
+        else
+            PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, in, out, n);
+        return;
+    }
+    const int nb = cdiv(n, SCAN_BLOCK);
+    c.scan_part.ensure(nb);
+    if (ceil8) {
+        PQ_LAUNCH(k_scan_part<1>, nb, 1024, 0, s, in, n, c.scan_part.p);
+        PQ_LAUNCH(k_scan_apply<1>, nb, 1024, 0, s, in, out, n, c.scan_part.p);
+    } else {
+        PQ_LAUNCH(k_scan_part<0>, nb, 1024, 0, s, in, n, c.scan_part.p);
+        PQ_LAUNCH(k_scan_apply<0>, nb, 1024, 0, s, in, out, n, c.scan_part.p);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -425,8 +574,8 @@ void nbr_build(Ctx& c, const double* pos) {
     PQ_HIP(hipMemsetAsync(c.col_fill.p, 0, sizeof(int) * c.ncol, s));
     PQ_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int) * 4, s));
     PQ_LAUNCH(k_wrap_count, cdiv(n, 256), 256, 0, s, n, pos, g, c.w64.p, c.col_of.p, c.col_cnt.p, c.flag.p);
-    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.col_cnt.p, c.col_start.p, c.ncol);
-    PQ_LAUNCH(k_scan<1>, 1, 1024, 0, s, c.col_cnt.p, c.col_cl.p, c.ncol);
+    scan_ints(c, c.col_cnt.p, c.col_start.p, c.ncol, false, s);
+    scan_ints(c, c.col_cnt.p, c.col_cl.p, c.ncol, true, s);
     int hv[2];
     PQ_HIP(hipMemcpyAsync(&hv[0], c.col_cl.p + c.ncol, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipMemcpyAsync(&hv[1], c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -440,6 +589,7 @@ void nbr_build(Ctx& c, const double* pos) {
     c.orig.ensure(nslot);
     c.xyzq.ensure(nslot * 4 * rsz(c));
     c.cl_ref.ensure((size_t)ncl * 3);
+    c.cl_pos.ensure(nslot);
     c.cl_lo.ensure((size_t)ncl * 3);
     c.cl_hi.ensure((size_t)ncl * 3);
     c.cl_col.ensure(ncl);
@@ -448,18 +598,17 @@ void nbr_build(Ctx& c, const double* pos) {
 
     PQ_LAUNCH(k_bin, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_fill.p, c.tmp_atoms.p);
     PQ_LAUNCH(k_fill_int, cdiv(nslot, 256), 256, 0, s, c.orig.p, (int)nslot, -1);
-    PQ_LAUNCH(k_rank, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_cl.p, c.tmp_atoms.p,
-              c.w64.p, c.orig.p);
+    PQ_LAUNCH(k_rank_col, c.ncol, 256, 0, s, c.ncol, c.col_start.p, c.col_cl.p, c.tmp_atoms.p, c.w64.p, c.orig.p);
     PQ_LAUNCH(k_cluster_col, cdiv(c.ncol, 256), 256, 0, s, c.ncol, c.col_cl.p, c.cl_col.p);
     if (c.fp64)
         PQ_LAUNCH(k_cluster<double>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
-                  c.cl_hi.p, as<double4>(c.xyzq));
+                  c.cl_hi.p, as<double4>(c.xyzq), c.cl_pos.p);
     else
         PQ_LAUNCH(k_cluster<float>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
-                  c.cl_hi.p, as<float4>(c.xyzq));
+                  c.cl_hi.p, as<float4>(c.xyzq), c.cl_pos.p);
     PQ_LAUNCH((k_list<false>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p,
               c.lcount.p, (const int*)nullptr, (int2*)nullptr);
-    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.lcount.p, c.lstart.p, ncl);
+    scan_ints(c, c.lcount.p, c.lstart.p, ncl, false, s);
     int tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.lstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipStreamSynchronize(s));
@@ -472,12 +621,12 @@ void nbr_build(Ctx& c, const double* pos) {
     c.jcount.ensure(ncl + 1);
     c.jstart.ensure(ncl + 1);
     if (c.fp64)
-        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
                   c.cl_ref.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
     else
-        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
                   c.cl_ref.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
-    PQ_LAUNCH(k_scan<0>, 1, 1024, 0, s, c.jcount.p, c.jstart.p, ncl);
+    scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
     int rows = 0;
     PQ_HIP(hipMemcpyAsync(&rows, c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipStreamSynchronize(s));
@@ -491,10 +640,10 @@ void nbr_build(Ctx& c, const double* pos) {
     else
         PQ_LAUNCH(k_far_entries<float>, 1, 256, 0, s, as<float4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     if (c.fp64)
-        PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+        PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
                   c.cl_ref.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
     else
-        PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+        PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
                   c.cl_ref.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
 }
 

@@ -425,7 +425,7 @@ static void pme_setup_t(Ctx& c) {
     PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
     PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
     PQ_LAUNCH(k_pme_setup<T>, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, as<v4>(c.f_k), c.brick_cnt.p);
-    scan_ints(c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
+    scan_ints(c, c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
     PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.brick_fill.p,
               c.tmp_atoms.p);
     PQ_LAUNCH(k_pme_order<T>, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.tmp_atoms.p,

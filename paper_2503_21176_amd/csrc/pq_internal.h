@@ -230,6 +230,7 @@ struct Ctx {
     DBuf<int> orig;          // slot -> original atom (-1 padding), ncl*8
     DBuf<unsigned char> xyzq; // slot-ordered V4<T>: offset from the cluster reference + charge
     DBuf<double> cl_ref;     // ncl*3 reference points
+    DBuf<double4> cl_pos;    // slot-ordered FP64 wrapped positions, w = 1 (0: padding)
     DBuf<double> cl_lo;      // ncl*3 bounding boxes
     DBuf<double> cl_hi;
     DBuf<int> cl_col;        // column of each cluster
@@ -242,6 +243,7 @@ struct Ctx {
     int64_t njrows = 0;
     DBuf<int> flag;          // device error flags
     DBuf<unsigned long long> counter;
+    DBuf<int> scan_part;     // block sums of the multi-workgroup scan
 
     // --- PME ---
     int K[3] = {0, 0, 0}, P = 0, B = 8;
@@ -327,7 +329,7 @@ inline size_t rsz(const Ctx& c) { return c.fp64 ? 8 : 4; }
 // launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------
 // nbr.hip
-void scan_ints(const int* in, int* out, int n, bool ceil8, hipStream_t s);  // exclusive; out[n] = total
+void scan_ints(Ctx& c, const int* in, int* out, int n, bool ceil8, hipStream_t s);  // exclusive; out[n] = total
 void nbr_build(Ctx& c, const double* pos);
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs);
 // pair.hip: outputs in original atom order, without KE; force includes q_i
