@@ -18,6 +18,8 @@
 // precision and are staged in LDS with the data.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <vector>
 
@@ -728,6 +730,12 @@ static void col2_radices(int n, int& r1, int& r2) {
 }
 
 void fft_setup(Ctx& c) {
+    // twiddle and influence tables depend only on the grid, the spline order,
+    // alpha, the box and the precision: kept when none of them changed
+    const double key[9] = {(double)c.K[0], (double)c.K[1], (double)c.K[2], (double)c.P, c.prm.alpha,
+                           c.prm.box[0],   c.prm.box[1],   c.prm.box[2],   c.fp64 ? 1.0 : 0.0};
+    if (c.fft_key_valid && std::equal(key, key + 9, c.fft_key)) return;
+    c.fft_key_valid = false;
     std::vector<double> tw;   // interleaved (cos, sin), rounded to the bulk precision on upload
     int off[3];
     for (int d = 0; d < 3; ++d) {
@@ -799,6 +807,8 @@ void fft_setup(Ctx& c) {
     }
     const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
     c.inf.scale = 1.0 / (PI * V);
+    std::copy(key, key + 9, c.fft_key);
+    c.fft_key_valid = true;
 }
 
 // LDS budget of one FFT workgroup: two ping-pong buffers of `budget` bytes

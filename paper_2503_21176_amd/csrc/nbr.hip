@@ -155,11 +155,70 @@ __global__ void k_bin(int n, const int* __restrict__ col_of, const int* __restri
     tmp[col_start[c] + atomicAdd(&col_fill[c], 1)] = i;
 }
 
+// Column binning without global atomics: workgroup w takes atoms
+// [w per, (w + 1) per), counts them per column in LDS and stores its counts
+// column-major, hist[c nwg + w]; an exclusive scan of hist then gives each
+// workgroup its first slot in every column, where k_bin_hist places its atoms
+// (LDS cursors). The order inside a column is settled by k_rank_col.
+constexpr int BIN_LDS_COLS = 16384;   // columns that fit the LDS counters
+__global__ __launch_bounds__(256) void k_wrap_hist(int n, int per, const double* __restrict__ pos, Geom g,
+                                                   double* __restrict__ w64, int* __restrict__ col_of,
+                                                   int* __restrict__ hist, int* __restrict__ flag) {
+    extern __shared__ int cntl[];
+    const int ncol = g.ncx * g.ncy;
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) cntl[c] = 0;
+    __syncthreads();
+    const int a0 = blockIdx.x * per, a1 = min(n, a0 + per);
+    for (int i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
+        double w[3];
+        bool ok = true;
+        for (int d = 0; d < 3; ++d) {
+            const double x = pos[3 * (size_t)i + d];
+            ok = ok && isfinite(x);
+            w[d] = canon_wrap(x, g.L[d], g.invL[d]);
+            w64[3 * (size_t)i + d] = w[d];
+        }
+        if (!ok) {
+            atomicOr(flag, 1);
+            w[0] = w[1] = w[2] = 0.0;
+        }
+        int cx = (int)floor(w[0] * ((double)g.ncx * g.invL[0]));
+        int cy = (int)floor(w[1] * ((double)g.ncy * g.invL[1]));
+        cx = min(max(cx, 0), g.ncx - 1);
+        cy = min(max(cy, 0), g.ncy - 1);
+        const int c = cx + g.ncx * cy;
+        col_of[i] = c;
+        atomicAdd(&cntl[c], 1);
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) hist[(size_t)c * gridDim.x + blockIdx.x] = cntl[c];
+}
+
+// Column starts and counts from the scanned per-workgroup histogram.
+__global__ void k_col_from_hist(int ncol, int nwg, const int* __restrict__ hscan, int* __restrict__ col_start,
+                                int* __restrict__ col_cnt) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c > ncol) return;
+    const int a = hscan[(size_t)c * nwg];
+    col_start[c] = a;
+    if (c < ncol) col_cnt[c] = hscan[(size_t)(c + 1) * nwg] - a;
+}
+
+__global__ __launch_bounds__(256) void k_bin_hist(int n, int per, int ncol, const int* __restrict__ col_of,
+                                                  const int* __restrict__ hscan, int* __restrict__ tmp) {
+    extern __shared__ int cur[];
+    for (int c = threadIdx.x; c < ncol; c += blockDim.x) cur[c] = hscan[(size_t)c * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int a0 = blockIdx.x * per, a1 = min(n, a0 + per);
+    for (int i = a0 + threadIdx.x; i < a1; i += blockDim.x) tmp[atomicAdd(&cur[col_of[i]], 1)] = i;
+}
+
 // Rank of each atom inside its column by (z, index), a deterministic sort:
-// one workgroup per column stages the column's (z, index) keys in LDS and
-// every atom counts the keys below its own there.
-// Columns longer than RANK_CAP atoms count from global memory instead.
-constexpr int RANK_CAP = 2048;
+// one workgroup per column stages the column's (z, index) keys in LDS (padded
+// to a multiple of 8 with keys that rank below nobody) and every atom counts
+// the keys below its own there, 8 keys per step. Columns longer than RANK_CAP
+// atoms count from global memory instead.
+constexpr int RANK_CAP = 2048;   // a multiple of 8
 __global__ __launch_bounds__(256) void k_rank_col(int ncol, const int* __restrict__ col_start,
                                                   const int* __restrict__ col_cl, const int* __restrict__ tmp,
                                                   const double* __restrict__ w64, int* __restrict__ orig) {
@@ -168,24 +227,46 @@ __global__ __launch_bounds__(256) void k_rank_col(int ncol, const int* __restric
     const int c = blockIdx.x;
     if (c >= ncol) return;
     const int k0 = col_start[c], m = col_start[c + 1] - k0;
-    const bool lds = m <= RANK_CAP;
-    if (lds)
+    int* __restrict__ dst = orig + (size_t)col_cl[c] * CL;
+    if (m > RANK_CAP) {
         for (int t = threadIdx.x; t < m; t += blockDim.x) {
-            const int j = tmp[k0 + t];
-            si[t] = j;
-            sz[t] = w64[3 * (size_t)j + 2];
+            const int i = tmp[k0 + t];
+            const double zi = w64[3 * (size_t)i + 2];
+            int r = 0;
+            for (int u = 0; u < m; ++u) {
+                const int j = tmp[k0 + u];
+                const double zj = w64[3 * (size_t)j + 2];
+                r += (zj < zi) || (zj == zi && j < i);
+            }
+            dst[r] = i;
         }
+        return;
+    }
+    const int m8 = (m + 7) & ~7;
+    for (int t = threadIdx.x; t < m8; t += blockDim.x) {
+        int j = 0x7fffffff;
+        double z = __builtin_inf();
+        if (t < m) {
+            j = tmp[k0 + t];
+            z = w64[3 * (size_t)j + 2];
+        }
+        si[t] = j;
+        sz[t] = z;
+    }
     __syncthreads();
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
-        const int i = lds ? si[t] : tmp[k0 + t];
-        const double zi = lds ? sz[t] : w64[3 * (size_t)i + 2];
+        const int i = si[t];
+        const double zi = sz[t];
         int r = 0;
-        for (int u = 0; u < m; ++u) {
-            const int j = lds ? si[u] : tmp[k0 + u];
-            const double zj = lds ? sz[u] : w64[3 * (size_t)j + 2];
-            r += (zj < zi) || (zj == zi && j < i);
+        for (int u = 0; u < m8; u += 8) {
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const double zj = sz[u + v];
+                const int j = si[u + v];
+                r += (zj < zi) || (zj == zi && j < i);
+            }
         }
-        orig[(size_t)col_cl[c] * CL + r] = i;
+        dst[r] = i;
     }
 }
 
@@ -250,14 +331,14 @@ __device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, do
 // out, the others put their clusters into one flat sequence that the
 // wavefront walks 64 clusters per step, testing bounding boxes at every z
 // image. LIST_UNROLL steps load their cluster bounds before any is tested, so
-// that their latencies overlap. FILL = false counts, FILL = true writes at
-// lstart[ic] in the same deterministic order (flat position, then z image).
+// that their latencies overlap. The entries of i-cluster ic go to
+// lj[ic * cap + k] in a deterministic order (flat position, then z image);
+// those with k >= cap are counted but not written (cap = 0: count only).
 constexpr int LIST_UNROLL = 4;
-template <bool FILL>
 __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
                                               const int* __restrict__ col_cl, const double* __restrict__ lo,
-                                              const double* __restrict__ hi, int* __restrict__ lcount,
-                                              const int* __restrict__ lstart, int2* __restrict__ lj) {
+                                              const double* __restrict__ hi, int* __restrict__ lcount, int cap,
+                                              int2* __restrict__ lj) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
@@ -269,7 +350,7 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
     const double hii0 = hi[3 * ic], hii1 = hi[3 * ic + 1], hii2 = hi[3 * ic + 2];
     const int nxc = 2 * g.Rx + 1, ncand = nxc * (2 * g.Ry + 1);
     int cnt = 0;
-    const int base = FILL ? lstart[ic] : 0;
+    int2* __restrict__ out = lj + (size_t)ic * cap;
     for (int cb = 0; cb < ncand; cb += 64) {
         // this lane's candidate column: its clusters [j0, j0 + nc) and image (nx, ny)
         const int k = cb + lane;
@@ -335,13 +416,28 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
                     const double gz = gap1(l2[u] + sz, h2[u] + sz, loi2, hii2);
                     const bool pass = valid && (dxy2 + gz * gz < rl2);
                     const unsigned long long m = __ballot(pass);
-                    if (FILL && pass) lj[base + cnt + lanes_below(m)] = make_int2(jc[u], pack_img(nx, ny, nz));
+                    const int k = cnt + lanes_below(m);
+                    if (pass && k < cap) out[k] = make_int2(jc[u], pack_img(nx, ny, nz));
                     cnt += __popcll(m);
                 }
             }
         }
     }
-    if (!FILL && lane == 0) lcount[ic] = cnt;
+    if (lane == 0) lcount[ic] = cnt;
+}
+
+// Largest of n integers (n >= 0; 0 for n == 0), one workgroup.
+__global__ __launch_bounds__(1024) void k_max_int(const int* __restrict__ a, int n, int* __restrict__ out) {
+    __shared__ int lds[16];
+    int v = 0;
+    for (int i = threadIdx.x; i < n; i += 1024) v = max(v, a[i]);
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) v = max(v, lds[w]);
+        out[0] = v;
+    }
 }
 
 // Atom-level j list of each i-cluster, derived from its cluster-pair list: the
@@ -363,7 +459,9 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
 // (position p holds row (p S) mod R, S ~ 0.618 R, gcd(S, R) = 1), which
 // spreads every stretch of the list over the whole walk: with it ~92 % of the
 // compute lanes are busy against ~79 % in list order.
-// FILL = false counts entries and rows, FILL = true writes.
+// FILL = false decides every candidate, stores its colmask (one byte per
+// cluster-pair entry and j atom, at jmask[8 e + b]) and counts rows; FILL =
+// true reads those bytes back and writes the entries.
 __device__ __forceinline__ long long gcd_ll(long long a, long long b) {
     while (b != 0) {
         const long long t = a % b;
@@ -388,10 +486,11 @@ __device__ __forceinline__ long long inv_mod(long long s, long long n) {
 }
 
 template <bool FILL, class T>
-__global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lstart,
+__global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                const int2* __restrict__ lj, const double4* __restrict__ cpos,
-                                               const double* __restrict__ ref, int* __restrict__ jcount,
-                                               const int* __restrict__ jstart, V4<T>* __restrict__ jl) {
+                                               const double* __restrict__ ref, unsigned char* __restrict__ jmask,
+                                               int* __restrict__ jcount, const int* __restrict__ jstart,
+                                               V4<T>* __restrict__ jl) {
     const int lane = lane_id();
     const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (ic >= ncl) return;
@@ -399,16 +498,18 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
     // the i-cluster's atoms (the same in every lane)
     bool ireal[CL];
     double wi[CL][3];
+    if (!FILL) {
 #pragma unroll
-    for (int a = 0; a < CL; ++a) {
-        const double4 p = cpos[(size_t)ic * CL + a];
-        ireal[a] = p.w != 0.0;
-        wi[a][0] = p.x;
-        wi[a][1] = p.y;
-        wi[a][2] = p.z;
+        for (int a = 0; a < CL; ++a) {
+            const double4 p = cpos[(size_t)ic * CL + a];
+            ireal[a] = p.w != 0.0;
+            wi[a][0] = p.x;
+            wi[a][1] = p.y;
+            wi[a][2] = p.z;
+        }
     }
     const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
-    const int e0 = lstart[ic], e1 = lstart[ic + 1];
+    const size_t e0 = (size_t)ic * lcap, e1 = e0 + lcount[ic];
     const int eo = lane >> 3, b = lane & 7;
     const size_t base = FILL ? (size_t)jstart[ic] * CL : 0;
     // row r of list order is stored at row (r * sinv) mod nrow
@@ -422,37 +523,49 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
         }
     }
     auto dest = [&](long long k) -> size_t { return base + (size_t)(((k >> 3) * sinv) % nrow) * CL + (k & 7); };
-    // two-stage load pipeline: the list entry of step s + 2 and the j position
-    // of step s + 1 are in flight while step s is tested
-    auto entry = [&](int eb) -> int2 { const int e = eb + eo; return e < e1 ? lj[e] : make_int2(-1, 0); };
-    auto jpos = [&](int2 je) -> double4 {
-        return je.x >= 0 ? cpos[(size_t)je.x * CL + b] : make_double4(0.0, 0.0, 0.0, 0.0);
+    // two-stage load pipeline: the list entry (and stored mask) of step s + 2
+    // and the j position of step s + 1 are in flight while step s is handled;
+    // the fill pass loads positions only where the mask is not empty
+    auto entry = [&](size_t eb, int& msk) -> int2 {
+        const size_t e = eb + eo;
+        msk = 0;
+        if (e >= e1) return make_int2(-1, 0);
+        if (FILL) msk = jmask[8 * e + b];
+        return lj[e];
     };
-    int2 je1 = entry(e0);
-    double4 p1 = jpos(je1);
-    int2 je2 = entry(e0 + 8);
+    auto jpos = [&](int2 je, int msk) -> double4 {
+        return (je.x >= 0 && (!FILL || msk != 0)) ? cpos[(size_t)je.x * CL + b] : make_double4(0.0, 0.0, 0.0, 0.0);
+    };
+    int m1, m2;
+    int2 je1 = entry(e0, m1);
+    double4 p1 = jpos(je1, m1);
+    int2 je2 = entry(e0 + 8, m2);
     int cnt = 0;
-    for (int eb = e0; eb < e1; eb += 8) {
+    for (size_t eb = e0; eb < e1; eb += 8) {
         const int2 je = je1;
         const double4 pj = p1;
+        int col = m1;
         je1 = je2;
-        p1 = jpos(je1);
-        je2 = entry(eb + 16);
-        int col = 0;
+        m1 = m2;
+        p1 = jpos(je1, m1);
+        je2 = entry(eb + 16, m2);
         double p0 = 0.0, pp1 = 0.0, p2 = 0.0;
         if (pj.w != 0.0) {
             int n0, n1, n2;
             unpack_img(je.y, n0, n1, n2);
-            const double wj[3] = {pj.x, pj.y, pj.z};
+            if (!FILL) {
+                const double wj[3] = {pj.x, pj.y, pj.z};
 #pragma unroll
-            for (int a = 0; a < CL; ++a) {
-                const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
-                if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                for (int a = 0; a < CL; ++a) {
+                    const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
+                    if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                }
             }
             p0 = pj.x + (double)n0 * g.L[0];
             pp1 = pj.y + (double)n1 * g.L[1];
             p2 = pj.z + (double)n2 * g.L[2];
         }
+        if (!FILL && eb + eo < e1) jmask[8 * (eb + eo) + b] = (unsigned char)col;
         const bool pass = col != 0;
         const unsigned long long m = __builtin_amdgcn_ballot_w64(pass);
         if (FILL && pass) {
@@ -478,7 +591,7 @@ __global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
 // Export of the atom pairs closer than the list radius, by the canonical FP64
 // predicate; each unordered pair once. Rows are reserved with a global
 // counter; rows beyond `cap` are not written but still counted.
-__global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lstart,
+__global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                 const int2* __restrict__ lj, const int* __restrict__ orig,
                                                 const double* __restrict__ w64, int64_t cap,
                                                 int32_t* __restrict__ out, unsigned long long* __restrict__ counter) {
@@ -488,7 +601,8 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
     const int a = lane >> 3, b = lane & 7;
     const int i = orig[(size_t)ic * CL + a];
     const double rl2 = g.rlist * g.rlist;
-    for (int e = lstart[ic]; e < lstart[ic + 1]; ++e) {
+    const size_t e0 = (size_t)ic * lcap, e1 = e0 + lcount[ic];
+    for (size_t e = e0; e < e1; ++e) {
         const int2 je = lj[e];
         const int j = orig[(size_t)je.x * CL + b];
         int n0, n1, n2;
@@ -570,13 +684,30 @@ void nbr_build(Ctx& c, const double* pos) {
     c.flag.ensure(4);
     c.counter.ensure(1);
 
-    PQ_HIP(hipMemsetAsync(c.col_cnt.p, 0, sizeof(int) * c.ncol, s));
-    PQ_HIP(hipMemsetAsync(c.col_fill.p, 0, sizeof(int) * c.ncol, s));
     PQ_HIP(hipMemsetAsync(c.flag.p, 0, sizeof(int) * 4, s));
-    PQ_LAUNCH(k_wrap_count, cdiv(n, 256), 256, 0, s, n, pos, g, c.w64.p, c.col_of.p, c.col_cnt.p, c.flag.p);
-    scan_ints(c, c.col_cnt.p, c.col_start.p, c.ncol, false, s);
+    // binning by per-workgroup LDS histograms (global counters when the
+    // columns do not fit in LDS)
+    const bool hist = c.ncol <= BIN_LDS_COLS;
+    const int nwg = std::max(1, std::min(256, (int)cdiv(n, 1024)));
+    const int per = (int)cdiv(n, nwg);
+    if (hist) {
+        const size_t nh = (size_t)c.ncol * nwg;
+        c.bin_hist.ensure(nh + 1);
+        c.bin_scan.ensure(nh + 1);
+        PQ_LAUNCH(k_wrap_hist, nwg, 256, sizeof(int) * c.ncol, s, n, per, pos, g, c.w64.p, c.col_of.p,
+                  c.bin_hist.p, c.flag.p);
+        scan_ints(c, c.bin_hist.p, c.bin_scan.p, (int)nh, false, s);
+        PQ_LAUNCH(k_col_from_hist, cdiv(c.ncol + 1, 256), 256, 0, s, c.ncol, nwg, c.bin_scan.p, c.col_start.p,
+                  c.col_cnt.p);
+    } else {
+        PQ_HIP(hipMemsetAsync(c.col_cnt.p, 0, sizeof(int) * c.ncol, s));
+        PQ_HIP(hipMemsetAsync(c.col_fill.p, 0, sizeof(int) * c.ncol, s));
+        PQ_LAUNCH(k_wrap_count, cdiv(n, 256), 256, 0, s, n, pos, g, c.w64.p, c.col_of.p, c.col_cnt.p, c.flag.p);
+        scan_ints(c, c.col_cnt.p, c.col_start.p, c.ncol, false, s);
+    }
     scan_ints(c, c.col_cnt.p, c.col_cl.p, c.ncol, true, s);
-    int hv[2];
+    // small read-backs go through the context's pinned host words
+    int* hv = reinterpret_cast<int*>(c.pinned + 48);
     PQ_HIP(hipMemcpyAsync(&hv[0], c.col_cl.p + c.ncol, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipMemcpyAsync(&hv[1], c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipStreamSynchronize(s));
@@ -594,9 +725,12 @@ void nbr_build(Ctx& c, const double* pos) {
     c.cl_hi.ensure((size_t)ncl * 3);
     c.cl_col.ensure(ncl);
     c.lcount.ensure(ncl + 1);
-    c.lstart.ensure(ncl + 1);
 
-    PQ_LAUNCH(k_bin, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_fill.p, c.tmp_atoms.p);
+    if (hist)
+        PQ_LAUNCH(k_bin_hist, nwg, 256, sizeof(int) * c.ncol, s, n, per, c.ncol, c.col_of.p, c.bin_scan.p,
+                  c.tmp_atoms.p);
+    else
+        PQ_LAUNCH(k_bin, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_fill.p, c.tmp_atoms.p);
     PQ_LAUNCH(k_fill_int, cdiv(nslot, 256), 256, 0, s, c.orig.p, (int)nslot, -1);
     PQ_LAUNCH(k_rank_col, c.ncol, 256, 0, s, c.ncol, c.col_start.p, c.col_cl.p, c.tmp_atoms.p, c.w64.p, c.orig.p);
     PQ_LAUNCH(k_cluster_col, cdiv(c.ncol, 256), 256, 0, s, c.ncol, c.col_cl.p, c.cl_col.p);
@@ -606,30 +740,35 @@ void nbr_build(Ctx& c, const double* pos) {
     else
         PQ_LAUNCH(k_cluster<float>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
                   c.cl_hi.p, as<float4>(c.xyzq), c.cl_pos.p);
-    PQ_LAUNCH((k_list<false>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p,
-              c.lcount.p, (const int*)nullptr, (int2*)nullptr);
-    scan_ints(c, c.lcount.p, c.lstart.p, ncl, false, s);
-    int tot = 0;
-    PQ_HIP(hipMemcpyAsync(&tot, c.lstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
-    PQ_HIP(hipStreamSynchronize(s));
-    PQ_REQUIRE(tot >= 0, PQ_ERR_BOX, "cluster-pair list overflow");
-    c.nlist = tot;
-    c.lj.ensure(std::max(1, tot));
-    PQ_LAUNCH((k_list<true>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p,
-              c.lcount.p, c.lstart.p, c.lj.p);
+    // cluster-pair list, one segment of lcap entries per i-cluster; lcap is
+    // kept across builds and raised when a cluster has more entries (the pass
+    // then runs again)
+    for (int pass = 0;; ++pass) {
+        c.lj.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap));
+        PQ_LAUNCH(k_list, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p, c.lcount.p,
+                  c.lcap, c.lj.p);
+        PQ_LAUNCH(k_max_int, 1, 1024, 0, s, c.lcount.p, ncl, c.flag.p + 2);
+        PQ_HIP(hipMemcpyAsync(&hv[2], c.flag.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+        PQ_HIP(hipStreamSynchronize(s));
+        const int mx = hv[2];
+        if (mx <= c.lcap) break;
+        PQ_REQUIRE(pass == 0, PQ_ERR_BOX, "cluster-pair list overflow");
+        c.lcap = mx + mx / 8 + 8;
+    }
+    c.jmask.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap * CL));
     // atom-level j lists for the pair kernel
     c.jcount.ensure(ncl + 1);
     c.jstart.ensure(ncl + 1);
     if (c.fp64)
-        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
+        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
     else
-        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
+        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
     scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
-    int rows = 0;
-    PQ_HIP(hipMemcpyAsync(&rows, c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipStreamSynchronize(s));
+    const int rows = hv[3];
     PQ_REQUIRE(rows >= 0, PQ_ERR_BOX, "atom list overflow");
     c.njrows = rows;
     // JL_TAIL far-away entries after the last row keep the pair kernel's
@@ -640,17 +779,17 @@ void nbr_build(Ctx& c, const double* pos) {
     else
         PQ_LAUNCH(k_far_entries<float>, 1, 256, 0, s, as<float4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     if (c.fp64)
-        PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
+        PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
     else
-        PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lstart.p, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
+        PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {
     hipStream_t s = c.stream;
     PQ_HIP(hipMemsetAsync(c.counter.p, 0, sizeof(unsigned long long), s));
-    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lstart.p, c.lj.p, c.orig.p, c.w64.p,
+    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, c.w64.p,
               pairs ? cap : (int64_t)0, pairs, c.counter.p);
     unsigned long long tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.counter.p, sizeof(tot), hipMemcpyDeviceToHost, s));

@@ -219,7 +219,6 @@ struct Ctx {
 
     // --- neighbour list (set_system) ---
     int ncol = 0, ncl = 0;
-    int64_t nlist = 0;
     DBuf<double> w64;        // wrapped FP64 positions, original order, n*3
     DBuf<int> col_of;        // column of each atom
     DBuf<int> col_cnt;       // atoms per column
@@ -227,6 +226,7 @@ struct Ctx {
     DBuf<int> col_fill;      // fill counters
     DBuf<int> col_cl;        // ncol+1, cluster offsets per column
     DBuf<int> tmp_atoms;     // atoms grouped by column, unordered
+    DBuf<int> bin_hist, bin_scan; // per-workgroup column counts (column-major) and their scan
     DBuf<int> orig;          // slot -> original atom (-1 padding), ncl*8
     DBuf<unsigned char> xyzq; // slot-ordered V4<T>: offset from the cluster reference + charge
     DBuf<double> cl_ref;     // ncl*3 reference points
@@ -234,9 +234,10 @@ struct Ctx {
     DBuf<double> cl_lo;      // ncl*3 bounding boxes
     DBuf<double> cl_hi;
     DBuf<int> cl_col;        // column of each cluster
-    DBuf<int> lcount;        // ncl+1
-    DBuf<int> lstart;        // ncl+1
-    DBuf<int2> lj;           // cluster-pair list: (j cluster, packed image vector)
+    DBuf<int> lcount;        // ncl+1: cluster-pair entries per i-cluster
+    int lcap = 0;            // entries reserved per i-cluster (kept across builds)
+    DBuf<int2> lj;           // cluster-pair list, ncl*lcap: (j cluster, packed image vector)
+    DBuf<unsigned char> jmask; // ncl*lcap*8: colmask of each (entry, j atom)
     DBuf<int> jcount;        // ncl+1: rows of 8 j atoms per i-cluster
     DBuf<int> jstart;        // ncl+1: row offsets
     DBuf<unsigned char> jl;  // atom-level j lists: V4<T> (image position - ref_i, slot)
@@ -260,6 +261,8 @@ struct Ctx {
     DBuf<double> inftab;     // T and S tables (FP64)
     Fft1D fft[3];
     InfTab inf{};
+    double fft_key[9] = {};  // (K, p, alpha, box, precision) the tables above were made for
+    bool fft_key_valid = false;
 
     // --- direct Ewald ---
     int nk = 0;

@@ -69,9 +69,11 @@ double request_footprint(int64_t n, const pq_params& p, int restart) {
     const double rl = p.cutoff + p.skin;
     auto grown = [&](double e) { return e * e * e + 6 * e * e * rl + 3 * PI * e * rl * rl + 4.0 / 3.0 * PI * rl * rl * rl; };
     const double ncl = std::ceil((double)n / 8.0) + 1.0;
-    const double pairs = ncl * grown(2.0 * a) * rho / 8.0 * 8.0;        // cluster pairs, int2 each
+    // cluster pairs: int2 and 8 mask bytes each, in per-cluster segments sized
+    // for the fullest cluster
+    const double pairs = ncl * grown(2.0 * a) * rho / 8.0 * 16.0 * 1.3;
     const double jatoms = ncl * (grown(a) * rho + 8.0) * 4.0 * rs;       // atom list, V4 each
-    const double atoms = (double)n * (24 + 16 + 16 + 16 + 20 + 8 + 32 + 24) + (double)n * (4 + 4 + 16 + 24) * rs;
+    const double atoms = (double)n * (24 + 16 + 16 + 16 + 20 + 8 + 32 + 24 + 32) + (double)n * (4 + 4 + 16 + 24) * rs;
     double grid = 0;
     if (p.method == PQ_METHOD_PME) {
         const double K3 = (double)p.grid[0] * p.grid[1] * p.grid[2];
