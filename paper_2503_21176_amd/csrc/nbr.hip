@@ -325,24 +325,66 @@ __device__ __forceinline__ double gap1(double lo_j, double hi_j, double lo_i, do
     return fmax(0.0, fmax(lo_j - hi_i, lo_i - hi_j));
 }
 
-// Cluster-pair list: one wavefront per i-cluster. The candidate columns (the
-// periodic (2Rx+1) x (2Ry+1) neighbourhood, dy-major) are taken 64 at a time,
-// one per lane: a column whose x-y strip lies beyond the list radius drops
-// out, the others put their clusters into one flat sequence that the
-// wavefront walks 64 clusters per step, testing bounding boxes at every z
-// image. LIST_UNROLL steps load their cluster bounds before any is tested, so
-// that their latencies overlap. The entries of i-cluster ic go to
-// lj[ic * cap + k] in a deterministic order (flat position, then z image);
-// those with k >= cap are counted but not written (cap = 0: count only).
+// z window of the clusters of each column. Within a column both the lowest
+// and the highest z of a cluster grow with the cluster index (clusters are
+// runs of 8 atoms in z order), so for bin edges z_t = t bw, t = 0..nbin:
+//   zta[c][t] = first cluster j of column c with hi_z(j) > z_t (t = 0: the first),
+//   ztb[c][t] = first cluster j with lo_z(j) >= z_t (t = nbin: one past the last).
+// Clusters that reach into a window (zlo, zhi) then lie in
+// [zta[c][t0], ztb[c][t1]) for any t0 with z_t0 < zlo and t1 with z_t1 > zhi.
+__global__ void k_ztab(int ncol, int nbin, double bw, const int* __restrict__ col_cl, const double* __restrict__ lo,
+                       const double* __restrict__ hi, int* __restrict__ zta, int* __restrict__ ztb) {
+    const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (idx >= (size_t)ncol * (nbin + 1)) return;
+    const int c = (int)(idx / (nbin + 1)), t = (int)(idx % (nbin + 1));
+    const int j0 = col_cl[c], j1 = col_cl[c + 1];
+    const double z = (double)t * bw;
+    int a = j0;
+    if (t > 0) {
+        int l = j0, h = j1;
+        while (l < h) {
+            const int m = (l + h) >> 1;
+            if (hi[3 * (size_t)m + 2] > z) h = m; else l = m + 1;
+        }
+        a = l;
+    }
+    int b = j1;
+    if (t < nbin) {
+        int l = j0, h = j1;
+        while (l < h) {
+            const int m = (l + h) >> 1;
+            if (lo[3 * (size_t)m + 2] >= z) h = m; else l = m + 1;
+        }
+        b = l;
+    }
+    zta[idx] = a;
+    ztb[idx] = b;
+}
+
+// Cluster-pair list: one wavefront per i-cluster. For each z image whose
+// window (the i-cluster's z range widened by the list radius) can hold
+// clusters, the candidate columns (the periodic (2Rx+1) x (2Ry+1)
+// neighbourhood, dy-major) are taken 64 at a time, one per lane: a column
+// whose x-y strip lies beyond the list radius drops out, the others look up
+// their clusters in the window (k_ztab) and put them into one flat sequence
+// that the wavefront walks 64 clusters per step with the bounding-box test.
+// Every cluster the test accepts lies in its column's window, so the list is
+// the same as from testing whole columns. LIST_UNROLL steps load their
+// cluster bounds before any is tested, so that their latencies overlap. The
+// entries of i-cluster ic go to lj[ic * cap + k] in a deterministic order
+// (z image, flat position); those with k >= cap are counted but not written
+// (cap = 0: count only).
 constexpr int LIST_UNROLL = 4;
 __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __restrict__ cl_col,
-                                              const int* __restrict__ col_cl, const double* __restrict__ lo,
+                                              const int* __restrict__ zta, const int* __restrict__ ztb, int nbin,
+                                              double bw, const double* __restrict__ lo,
                                               const double* __restrict__ hi, int* __restrict__ lcount, int cap,
                                               int2* __restrict__ lj) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
     const double rl2 = g.rlist * g.rlist * (1.0 + 1e-9) + 1e-12;
+    const double zr = sqrt(rl2) * (1.0 + 1e-9) + 1e-9;   // above every z gap the box test accepts
     const double eps = 1e-6;
     const int coli = cl_col[ic];
     const int cxi = coli % g.ncx, cyi = coli / g.ncx;
@@ -351,73 +393,77 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
     const int nxc = 2 * g.Rx + 1, ncand = nxc * (2 * g.Ry + 1);
     int cnt = 0;
     int2* __restrict__ out = lj + (size_t)ic * cap;
-    for (int cb = 0; cb < ncand; cb += 64) {
-        // this lane's candidate column: its clusters [j0, j0 + nc) and image (nx, ny)
-        const int k = cb + lane;
-        int j0 = 0, nc = 0, img = 0;
-        if (k < ncand) {
-            const int dy = k / nxc - g.Ry, dx = k % nxc - g.Rx;
-            const int cy = cyi + dy;
-            const int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
-            const int cyw = cy - ny * g.ncy;
-            const double sy = (double)ny * g.L[1];
-            const double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
-            const int cx = cxi + dx;
-            const int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
-            const int cxw = cx - nx * g.ncx;
-            const double sx = (double)nx * g.L[0];
-            const double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
-            if (!(gy > 0.0 && gy * gy >= rl2) && !(gx > 0.0 && gx * gx >= rl2)) {
-                const int col = cxw + g.ncx * cyw;
-                j0 = col_cl[col];
-                nc = col_cl[col + 1] - j0;
-                img = pack_img(nx, ny, 0);
-            }
-        }
-        const int incl = wave_incl_scan(nc);
-        const int total = __shfl(incl, 63, 64);
-        const int jofs = j0 - (incl - nc);   // cluster = flat position + jofs of the owning lane
-        for (int fb = 0; fb < total; fb += 64 * LIST_UNROLL) {
-            int jc[LIST_UNROLL], im[LIST_UNROLL];
-            double l0[LIST_UNROLL], l1[LIST_UNROLL], l2[LIST_UNROLL];
-            double h0[LIST_UNROLL], h1[LIST_UNROLL], h2[LIST_UNROLL];
-#pragma unroll
-            for (int u = 0; u < LIST_UNROLL; ++u) {
-                const int f = fb + 64 * u + lane;
-                // owner: the first lane whose inclusive count exceeds f
-                int o = 0;
-#pragma unroll
-                for (int st = 32; st >= 1; st >>= 1)
-                    if (__shfl(incl, o + st - 1, 64) <= f) o += st;
-                jc[u] = f + __shfl(jofs, o, 64);
-                im[u] = __shfl(img, o, 64);
-                l0[u] = l1[u] = l2[u] = h0[u] = h1[u] = h2[u] = 0.0;
-                if (f < total) {
-                    l0[u] = lo[3 * jc[u]];
-                    l1[u] = lo[3 * jc[u] + 1];
-                    l2[u] = lo[3 * jc[u] + 2];
-                    h0[u] = hi[3 * jc[u]];
-                    h1[u] = hi[3 * jc[u] + 1];
-                    h2[u] = hi[3 * jc[u] + 2];
+    for (int nz = -g.Rz; nz <= g.Rz; ++nz) {
+        const double sz = (double)nz * g.L[2];
+        const double zlo = loi2 - zr - sz, zhi = hii2 + zr - sz;
+        // wrapped z lies within a rounding error of [0, L]
+        if (zhi <= -bw || zlo >= g.L[2] + bw) continue;
+        const int t0 = (int)fmin(fmax(floor(zlo / bw) - 1.0, 0.0), (double)nbin);
+        const int t1 = (int)fmin(fmax(floor(zhi / bw) + 2.0, 0.0), (double)nbin);
+        for (int cb = 0; cb < ncand; cb += 64) {
+            // this lane's candidate column: clusters [ja, ja + nc) and image (nx, ny, nz)
+            const int k = cb + lane;
+            int ja = 0, nc = 0, img = 0;
+            if (k < ncand) {
+                const int dy = k / nxc - g.Ry, dx = k % nxc - g.Rx;
+                const int cy = cyi + dy;
+                const int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
+                const int cyw = cy - ny * g.ncy;
+                const double sy = (double)ny * g.L[1];
+                const double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
+                const int cx = cxi + dx;
+                const int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
+                const int cxw = cx - nx * g.ncx;
+                const double sx = (double)nx * g.L[0];
+                const double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
+                if (!(gy > 0.0 && gy * gy >= rl2) && !(gx > 0.0 && gx * gx >= rl2)) {
+                    const size_t row = (size_t)(cxw + g.ncx * cyw) * (nbin + 1);
+                    ja = zta[row + t0];
+                    nc = max(0, ztb[row + t1] - ja);
+                    img = pack_img(nx, ny, nz);
                 }
             }
+            const int incl = wave_incl_scan(nc);
+            const int total = __shfl(incl, 63, 64);
+            const int jofs = ja - (incl - nc);   // cluster = flat position + jofs of the owning lane
+            for (int fb = 0; fb < total; fb += 64 * LIST_UNROLL) {
+                int jc[LIST_UNROLL], im[LIST_UNROLL];
+                double l0[LIST_UNROLL], l1[LIST_UNROLL], l2[LIST_UNROLL];
+                double h0[LIST_UNROLL], h1[LIST_UNROLL], h2[LIST_UNROLL];
 #pragma unroll
-            for (int u = 0; u < LIST_UNROLL; ++u) {
-                if (fb + 64 * u >= total) break;
-                const bool valid = fb + 64 * u + lane < total;
-                int nx, ny, nz0;
-                unpack_img(im[u], nx, ny, nz0);
-                const double sx = (double)nx * g.L[0], sy = (double)ny * g.L[1];
-                const double gxx = gap1(l0[u] + sx, h0[u] + sx, loi0, hii0);
-                const double gyy = gap1(l1[u] + sy, h1[u] + sy, loi1, hii1);
-                const double dxy2 = gxx * gxx + gyy * gyy;
-                for (int nz = -g.Rz; nz <= g.Rz; ++nz) {
-                    const double sz = (double)nz * g.L[2];
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const int f = fb + 64 * u + lane;
+                    // owner: the first lane whose inclusive count exceeds f
+                    int o = 0;
+#pragma unroll
+                    for (int st = 32; st >= 1; st >>= 1)
+                        if (__shfl(incl, o + st - 1, 64) <= f) o += st;
+                    jc[u] = f + __shfl(jofs, o, 64);
+                    im[u] = __shfl(img, o, 64);
+                    l0[u] = l1[u] = l2[u] = h0[u] = h1[u] = h2[u] = 0.0;
+                    if (f < total) {
+                        l0[u] = lo[3 * jc[u]];
+                        l1[u] = lo[3 * jc[u] + 1];
+                        l2[u] = lo[3 * jc[u] + 2];
+                        h0[u] = hi[3 * jc[u]];
+                        h1[u] = hi[3 * jc[u] + 1];
+                        h2[u] = hi[3 * jc[u] + 2];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    if (fb + 64 * u >= total) break;
+                    const bool valid = fb + 64 * u + lane < total;
+                    int nx, ny, nzz;
+                    unpack_img(im[u], nx, ny, nzz);
+                    const double sx = (double)nx * g.L[0], sy = (double)ny * g.L[1];
+                    const double gxx = gap1(l0[u] + sx, h0[u] + sx, loi0, hii0);
+                    const double gyy = gap1(l1[u] + sy, h1[u] + sy, loi1, hii1);
                     const double gz = gap1(l2[u] + sz, h2[u] + sz, loi2, hii2);
-                    const bool pass = valid && (dxy2 + gz * gz < rl2);
+                    const bool pass = valid && (gxx * gxx + gyy * gyy + gz * gz < rl2);
                     const unsigned long long m = __ballot(pass);
-                    const int k = cnt + lanes_below(m);
-                    if (pass && k < cap) out[k] = make_int2(jc[u], pack_img(nx, ny, nz));
+                    const int kk = cnt + lanes_below(m);
+                    if (pass && kk < cap) out[kk] = make_int2(jc[u], im[u]);
                     cnt += __popcll(m);
                 }
             }
@@ -743,10 +789,18 @@ void nbr_build(Ctx& c, const double* pos) {
     // cluster-pair list, one segment of lcap entries per i-cluster; lcap is
     // kept across builds and raised when a cluster has more entries (the pass
     // then runs again)
+    // per-column z windows: bins of rlist/8 (at most 4096 over the box)
+    const double bw = std::max(g.rlist / 8.0, p.box[2] / 4096.0);
+    const int nbin = (int)std::ceil(p.box[2] / bw) + 1;
+    const size_t nzt = (size_t)c.ncol * (nbin + 1);
+    c.zta.ensure(nzt);
+    c.ztb.ensure(nzt);
+    PQ_LAUNCH(k_ztab, cdiv(nzt, 256), 256, 0, s, c.ncol, nbin, bw, c.col_cl.p, c.cl_lo.p, c.cl_hi.p, c.zta.p,
+              c.ztb.p);
     for (int pass = 0;; ++pass) {
         c.lj.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap));
-        PQ_LAUNCH(k_list, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.col_cl.p, c.cl_lo.p, c.cl_hi.p, c.lcount.p,
-                  c.lcap, c.lj.p);
+        PQ_LAUNCH(k_list, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.zta.p, c.ztb.p, nbin, bw, c.cl_lo.p,
+                  c.cl_hi.p, c.lcount.p, c.lcap, c.lj.p);
         PQ_LAUNCH(k_max_int, 1, 1024, 0, s, c.lcount.p, ncl, c.flag.p + 2);
         PQ_HIP(hipMemcpyAsync(&hv[2], c.flag.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
         PQ_HIP(hipStreamSynchronize(s));

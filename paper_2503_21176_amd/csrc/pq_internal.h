@@ -234,6 +234,7 @@ struct Ctx {
     DBuf<double> cl_lo;      // ncl*3 bounding boxes
     DBuf<double> cl_hi;
     DBuf<int> cl_col;        // column of each cluster
+    DBuf<int> zta, ztb;      // per-column z-window tables, ncol*(nbin+1) each
     DBuf<int> lcount;        // ncl+1: cluster-pair entries per i-cluster
     int lcap = 0;            // entries reserved per i-cluster (kept across builds)
     DBuf<int2> lj;           // cluster-pair list, ncl*lcap: (j cluster, packed image vector)
