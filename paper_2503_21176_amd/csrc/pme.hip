@@ -97,18 +97,32 @@ __global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const int
 
 // Deterministic order inside each brick (by atom index), so every
 // accumulation order, and hence every result, is reproducible bit for bit.
+// One wavefront per brick: each lane holds one of the brick's atoms and counts
+// the smaller indices among all of the brick's atoms, 64 at a time from lane
+// registers.
 template <class T>
-__global__ void k_pme_order(int n, const int* __restrict__ brick_of, const int* __restrict__ brick_start,
-                            const int* __restrict__ unordered, const V4<T>* __restrict__ frac_tmp,
-                            int* __restrict__ pme_idx, V4<T>* __restrict__ pme_frac) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int br = brick_of[i];
-    const int s0 = brick_start[br], s1 = brick_start[br + 1];
-    int r = 0;
-    for (int k = s0; k < s1; ++k) r += unordered[k] < i;
-    pme_idx[s0 + r] = i;
-    pme_frac[s0 + r] = frac_tmp[i];
+__global__ __launch_bounds__(256) void k_pme_order(int nbrick, const int* __restrict__ brick_start,
+                                                   const int* __restrict__ unordered,
+                                                   const V4<T>* __restrict__ frac_tmp, int* __restrict__ pme_idx,
+                                                   V4<T>* __restrict__ pme_frac) {
+    const int lane = threadIdx.x & 63;
+    const int br = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (br >= nbrick) return;
+    const int s0 = brick_start[br], m = brick_start[br + 1] - s0;
+    for (int ab = 0; ab < m; ab += 64) {
+        const int t = ab + lane;
+        const int ki = t < m ? unordered[s0 + t] : 0x7fffffff;
+        int r = 0;
+        for (int kb = 0; kb < m; kb += 64) {
+            const int kv = (kb + lane < m) ? unordered[s0 + kb + lane] : 0x7fffffff;
+            const int lim = min(64, m - kb);
+            for (int u = 0; u < lim; ++u) r += __builtin_amdgcn_readlane(kv, u) < ki;
+        }
+        if (t < m) {
+            pme_idx[s0 + r] = ki;
+            pme_frac[s0 + r] = frac_tmp[ki];
+        }
+    }
 }
 
 // B-spline weights and derivatives of every atom (brick order), computed once
@@ -428,7 +442,7 @@ static void pme_setup_t(Ctx& c) {
     scan_ints(c, c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
     PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.brick_fill.p,
               c.tmp_atoms.p);
-    PQ_LAUNCH(k_pme_order<T>, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.tmp_atoms.p,
+    PQ_LAUNCH(k_pme_order<T>, cdiv(c.nbrick, 4), 256, 0, s, c.nbrick, c.brick_start.p, c.tmp_atoms.p,
               as<v4>(c.f_k), c.pme_idx.p, as<v4>(c.pme_frac));
     switch (c.P) {
         case 3: PQ_LAUNCH((k_pme_weights<3, T>), cdiv(n, 256), 256, 0, s, n, as<v4>(c.pme_frac), as<T>(c.pme_w)); break;
