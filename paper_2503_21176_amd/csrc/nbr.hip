@@ -216,10 +216,11 @@ __global__ __launch_bounds__(256) void k_bin_hist(int n, int per, int ncol, cons
 // Rank of each atom inside its column by (z, index), a deterministic sort:
 // one workgroup per column stages the column's (z, index) keys in LDS (padded
 // to a multiple of 8 with keys that rank below nobody) and every atom counts
-// the keys below its own there, 8 keys per step. Columns longer than RANK_CAP
-// atoms count from global memory instead.
+// the keys below its own there, 8 keys per step (512 threads: one pass for
+// columns of up to 512 atoms). Columns longer than RANK_CAP atoms count from
+// global memory instead.
 constexpr int RANK_CAP = 2048;   // a multiple of 8
-__global__ __launch_bounds__(256) void k_rank_col(int ncol, const int* __restrict__ col_start,
+__global__ __launch_bounds__(512) void k_rank_col(int ncol, const int* __restrict__ col_start,
                                                   const int* __restrict__ col_cl, const int* __restrict__ tmp,
                                                   const double* __restrict__ w64, int* __restrict__ orig) {
     __shared__ double sz[RANK_CAP];
@@ -635,35 +636,54 @@ __global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
 }
 
 // Export of the atom pairs closer than the list radius, by the canonical FP64
-// predicate; each unordered pair once. Rows are reserved with a global
-// counter; rows beyond `cap` are not written but still counted.
+// predicate; each unordered pair once. A wavefront counts its i-cluster's
+// pairs, reserves that many rows with one atomic on the global counter and,
+// when `out` is given, walks the list again to write them; rows beyond `cap`
+// are not written but still counted.
 __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                 const int2* __restrict__ lj, const int* __restrict__ orig,
-                                                const double* __restrict__ w64, int64_t cap,
+                                                const double4* __restrict__ cpos, int64_t cap,
                                                 int32_t* __restrict__ out, unsigned long long* __restrict__ counter) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
     const int a = lane >> 3, b = lane & 7;
     const int i = orig[(size_t)ic * CL + a];
+    const double4 pi4 = cpos[(size_t)ic * CL + a];
+    const double wi[3] = {pi4.x, pi4.y, pi4.z};
     const double rl2 = g.rlist * g.rlist;
     const size_t e0 = (size_t)ic * lcap, e1 = e0 + lcount[ic];
-    for (size_t e = e0; e < e1; ++e) {
+    auto pair_at = [&](size_t e, int& j, int& n0, int& n1, int& n2) -> bool {
         const int2 je = lj[e];
-        const int j = orig[(size_t)je.x * CL + b];
-        int n0, n1, n2;
+        const size_t slot = (size_t)je.x * CL + b;
+        j = orig[slot];
+        const double4 pj = cpos[slot];
         unpack_img(je.y, n0, n1, n2);
         bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
-        if (ok) ok = canon_d2(w64 + 3 * (size_t)i, w64 + 3 * (size_t)j, n0, n1, n2, g.L[0], g.L[1], g.L[2]) < rl2;
-        unsigned long long m = __ballot(ok);
-        if (m == 0ull) continue;
-        unsigned long long basepos = 0;
-        if (lane == 0) basepos = atomicAdd(counter, (unsigned long long)__popcll(m));
-        basepos = __shfl(basepos, 0, 64);
         if (ok) {
-            unsigned long long pos = basepos + lanes_below(m);
-            if ((int64_t)pos < cap && out) {
-                int32_t* r = out + 5 * pos;
+            const double wj[3] = {pj.x, pj.y, pj.z};
+            ok = canon_d2(wi, wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]) < rl2;
+        }
+        return ok;
+    };
+    unsigned long long cnt = 0;
+    for (size_t e = e0; e < e1; ++e) {
+        int j, n0, n1, n2;
+        cnt += __popcll(__ballot(pair_at(e, j, n0, n1, n2)));
+    }
+    if (cnt == 0) return;
+    unsigned long long pos = 0;
+    if (lane == 0) pos = atomicAdd(counter, cnt);
+    pos = __shfl(pos, 0, 64);
+    if (!out) return;
+    for (size_t e = e0; e < e1; ++e) {
+        int j, n0, n1, n2;
+        const bool ok = pair_at(e, j, n0, n1, n2);
+        const unsigned long long m = __ballot(ok);
+        if (ok) {
+            const unsigned long long k = pos + lanes_below(m);
+            if ((int64_t)k < cap) {
+                int32_t* r = out + 5 * k;
                 r[0] = i;
                 r[1] = j;
                 r[2] = n0;
@@ -671,6 +691,7 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
                 r[4] = n2;
             }
         }
+        pos += __popcll(m);
     }
 }
 
@@ -778,7 +799,7 @@ void nbr_build(Ctx& c, const double* pos) {
     else
         PQ_LAUNCH(k_bin, cdiv(n, 256), 256, 0, s, n, c.col_of.p, c.col_start.p, c.col_fill.p, c.tmp_atoms.p);
     PQ_LAUNCH(k_fill_int, cdiv(nslot, 256), 256, 0, s, c.orig.p, (int)nslot, -1);
-    PQ_LAUNCH(k_rank_col, c.ncol, 256, 0, s, c.ncol, c.col_start.p, c.col_cl.p, c.tmp_atoms.p, c.w64.p, c.orig.p);
+    PQ_LAUNCH(k_rank_col, c.ncol, 512, 0, s, c.ncol, c.col_start.p, c.col_cl.p, c.tmp_atoms.p, c.w64.p, c.orig.p);
     PQ_LAUNCH(k_cluster_col, cdiv(c.ncol, 256), 256, 0, s, c.ncol, c.col_cl.p, c.cl_col.p);
     if (c.fp64)
         PQ_LAUNCH(k_cluster<double>, cdiv(ncl, 256), 256, 0, s, ncl, c.orig.p, c.w64.p, c.cl_ref.p, c.cl_lo.p,
@@ -843,7 +864,7 @@ void nbr_build(Ctx& c, const double* pos) {
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {
     hipStream_t s = c.stream;
     PQ_HIP(hipMemsetAsync(c.counter.p, 0, sizeof(unsigned long long), s));
-    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, c.w64.p,
+    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, c.cl_pos.p,
               pairs ? cap : (int64_t)0, pairs, c.counter.p);
     unsigned long long tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.counter.p, sizeof(tot), hipMemcpyDeviceToHost, s));

@@ -13,6 +13,8 @@
 //    reads each atom's p^3 stencil from there.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 
 #include "dev.h"
@@ -62,11 +64,10 @@ struct PmeGeo {
     double L[3], invL[3];
 };
 
+// Base grid point, fractional offsets and brick of atom i.
 template <class T>
-__global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int* __restrict__ brick_of,
-                            V4<T>* __restrict__ frac_tmp, int* __restrict__ brick_cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ int pme_atom_setup(int i, const double* __restrict__ w64, const PmeGeo& G,
+                                              int* __restrict__ brick_of, V4<T>* __restrict__ frac_tmp) {
     const int K[3] = {G.K0, G.K1, G.K2};
     int base[3];
     T fr[3];
@@ -81,10 +82,18 @@ __global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int
         fr[d] = (T)f;
         if (fr[d] >= T(1)) fr[d] = T(1) - T(1e-7);
     }
-    int br = base[0] / PME_B + G.nb0 * (base[1] / PME_B + G.nb1 * (base[2] / PME_B));
+    const int br = base[0] / PME_B + G.nb0 * (base[1] / PME_B + G.nb1 * (base[2] / PME_B));
     brick_of[i] = br;
     frac_tmp[i] = mk4<T>(fr[0], fr[1], fr[2], pack_int(base[0] | (base[1] << 10) | (base[2] << 20), T(0)));
-    atomicAdd(&brick_cnt[br], 1);
+    return br;
+}
+
+template <class T>
+__global__ void k_pme_setup(int n, const double* __restrict__ w64, PmeGeo G, int* __restrict__ brick_of,
+                            V4<T>* __restrict__ frac_tmp, int* __restrict__ brick_cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    atomicAdd(&brick_cnt[pme_atom_setup<T>(i, w64, G, brick_of, frac_tmp)], 1);
 }
 
 __global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const int* __restrict__ brick_start,
@@ -93,6 +102,38 @@ __global__ void k_pme_scatter(int n, const int* __restrict__ brick_of, const int
     if (i >= n) return;
     int br = brick_of[i];
     unordered[brick_start[br] + atomicAdd(&brick_fill[br], 1)] = i;
+}
+
+// The same binning without global atomics (bricks that fit the LDS counters):
+// workgroup w takes atoms [w per, (w + 1) per), counts them per brick in LDS
+// and stores the counts brick-major, hist[b nwg + w]; the exclusive scan of
+// hist gives each workgroup its first slot in every brick, where
+// k_pme_scatter_hist places its atoms with LDS cursors. The order inside a
+// brick is settled by k_pme_order.
+constexpr int BRICK_LDS_MAX = 16384;
+template <class T>
+__global__ __launch_bounds__(256) void k_pme_setup_hist(int n, int per, int nbrick, const double* __restrict__ w64,
+                                                        PmeGeo G, int* __restrict__ brick_of,
+                                                        V4<T>* __restrict__ frac_tmp, int* __restrict__ hist) {
+    extern __shared__ int cntl[];
+    for (int b = threadIdx.x; b < nbrick; b += blockDim.x) cntl[b] = 0;
+    __syncthreads();
+    const int a0 = blockIdx.x * per, a1 = min(n, a0 + per);
+    for (int i = a0 + threadIdx.x; i < a1; i += blockDim.x) atomicAdd(&cntl[pme_atom_setup<T>(i, w64, G, brick_of, frac_tmp)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbrick; b += blockDim.x) hist[(size_t)b * gridDim.x + blockIdx.x] = cntl[b];
+}
+__global__ void k_brick_starts(int nbrick, int nwg, const int* __restrict__ hscan, int* __restrict__ brick_start) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= nbrick) brick_start[b] = hscan[(size_t)b * nwg];
+}
+__global__ __launch_bounds__(256) void k_pme_scatter_hist(int n, int per, int nbrick, const int* __restrict__ brick_of,
+                                                          const int* __restrict__ hscan, int* __restrict__ unordered) {
+    extern __shared__ int cur[];
+    for (int b = threadIdx.x; b < nbrick; b += blockDim.x) cur[b] = hscan[(size_t)b * gridDim.x + blockIdx.x];
+    __syncthreads();
+    const int a0 = blockIdx.x * per, a1 = min(n, a0 + per);
+    for (int i = a0 + threadIdx.x; i < a1; i += blockDim.x) unordered[atomicAdd(&cur[brick_of[i]], 1)] = i;
 }
 
 // Deterministic order inside each brick (by atom index), so every
@@ -436,12 +477,27 @@ static void pme_setup_t(Ctx& c) {
     c.pme_frac.ensure((size_t)n * sizeof(v4));
     c.pme_w.ensure((size_t)n * PME_WSTRIDE * sizeof(T));
     c.tmp_atoms.ensure(n);
-    PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
-    PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
-    PQ_LAUNCH(k_pme_setup<T>, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, as<v4>(c.f_k), c.brick_cnt.p);
-    scan_ints(c, c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
-    PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.brick_fill.p,
-              c.tmp_atoms.p);
+    if (c.nbrick <= BRICK_LDS_MAX) {
+        const int nwg = std::max(1, std::min(256, (int)cdiv(n, 1024)));
+        const int per = (int)cdiv(n, nwg);
+        const size_t nh = (size_t)c.nbrick * nwg;
+        c.bin_hist.ensure(nh + 1);
+        c.bin_scan.ensure(nh + 1);
+        PQ_LAUNCH(k_pme_setup_hist<T>, nwg, 256, sizeof(int) * c.nbrick, s, n, per, c.nbrick, c.w64.p, G,
+                  c.brick_of.p, as<v4>(c.f_k), c.bin_hist.p);
+        scan_ints(c, c.bin_hist.p, c.bin_scan.p, (int)nh, false, s);
+        PQ_LAUNCH(k_brick_starts, cdiv(c.nbrick + 1, 256), 256, 0, s, c.nbrick, nwg, c.bin_scan.p, c.brick_start.p);
+        PQ_LAUNCH(k_pme_scatter_hist, nwg, 256, sizeof(int) * c.nbrick, s, n, per, c.nbrick, c.brick_of.p,
+                  c.bin_scan.p, c.tmp_atoms.p);
+    } else {
+        PQ_HIP(hipMemsetAsync(c.brick_cnt.p, 0, sizeof(int) * c.nbrick, s));
+        PQ_HIP(hipMemsetAsync(c.brick_fill.p, 0, sizeof(int) * c.nbrick, s));
+        PQ_LAUNCH(k_pme_setup<T>, cdiv(n, 256), 256, 0, s, n, c.w64.p, G, c.brick_of.p, as<v4>(c.f_k),
+                  c.brick_cnt.p);
+        scan_ints(c, c.brick_cnt.p, c.brick_start.p, c.nbrick, false, s);
+        PQ_LAUNCH(k_pme_scatter, cdiv(n, 256), 256, 0, s, n, c.brick_of.p, c.brick_start.p, c.brick_fill.p,
+                  c.tmp_atoms.p);
+    }
     PQ_LAUNCH(k_pme_order<T>, cdiv(c.nbrick, 4), 256, 0, s, c.nbrick, c.brick_start.p, c.tmp_atoms.p,
               as<v4>(c.f_k), c.pme_idx.p, as<v4>(c.pme_frac));
     switch (c.P) {
