@@ -5,29 +5,31 @@ atom pairs closer than a cutoff under periodic boundaries; the set itself has a
 plain definition, which is what this computes:
 
   (i, j, n) is a pair iff  d = (w_j - w_i) + n*L  has  d.d < cut^2,
+  (triclinic cells: n*L becomes the lattice vector n H, summed as image_offsets
+  states)
   w = canonical wrap of the FP64 positions, d.d = dx*dx + dy*dy + dz*dz
   evaluated left to right in FP64 without fused multiply-add, and
   (i, j, n) != (i, i, 0).
 
 Every unordered pair is listed once: (i < j, n), or (i, i, n) with n
 lexicographically positive for an atom and its own image. All periodic images
-with |n_d| <= ceil(cut/L_d) are considered, so boxes smaller than twice the
+with |n_d| <= ceil(cut/w_d) are considered (w_d the distance between opposite
+faces of the cell), so boxes smaller than twice the
 cutoff are covered.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .ewald import image_shifts, wrap
+from .ewald import image_offsets, image_shifts, wrap
 
 
 def neighbor_pairs(pos, box, cut, chunk_elems=4_000_000) -> np.ndarray:
     """Sorted int64 array (npairs, 5) of rows (i, j, n0, n1, n2)."""
-    box = np.asarray(box, np.float64)
     w = wrap(np.asarray(pos, np.float64), box)
     n = len(w)
     shifts = image_shifts(box, cut)
-    sL = shifts * box
+    sL = image_offsets(shifts, box)
     cut2 = cut * cut
     pos_shift = (shifts[:, 0] > 0) | ((shifts[:, 0] == 0) & (shifts[:, 1] > 0)) | \
                 ((shifts[:, 0] == 0) & (shifts[:, 1] == 0) & (shifts[:, 2] > 0))

@@ -73,15 +73,14 @@ def coulomb_matrix_blocked(pos, box, coul: dict, chunk: int = 32) -> np.ndarray:
     terms of eq. ewald_real), the smooth-PME reciprocal potential of unit
     charges computed for a block of columns at once (same steps as
     spme_reciprocal), and the self and background terms on every entry."""
-    from .ewald import image_shifts, wrap
+    from .ewald import image_offsets, image_shifts, volume, wrap
     from .spme import _stencil, influence
     from scipy.special import erfc
-    box = np.asarray(box, np.float64)
     n = len(pos)
     a, rc = coul["alpha"], coul["rc"]
     w = wrap(np.asarray(pos, np.float64), box)
     shifts = image_shifts(box, rc)
-    sL = shifts * box
+    sL = image_offsets(shifts, box)
     zero = np.all(shifts == 0, axis=1)
     A = np.zeros((n, n))
     step = max(1, 2_000_000 // max(1, n * len(shifts)))
@@ -96,7 +95,7 @@ def coulomb_matrix_blocked(pos, box, coul: dict, chunk: int = 32) -> np.ndarray:
         from .ewald import kvectors
         _, k = kvectors(box, coul["kmax"])
         k2 = np.sum(k * k, 1)
-        V = float(np.prod(box))
+        V = volume(box)
         ck = 4.0 * np.pi / V * np.exp(-k2 / (4 * a * a)) / k2
         ph = w @ k.T
         C, S = np.cos(ph), np.sin(ph)
@@ -117,7 +116,7 @@ def coulomb_matrix_blocked(pos, box, coul: dict, chunk: int = 32) -> np.ndarray:
             FQ = np.fft.fftn(Q.reshape(len(J), *K), axes=(1, 2, 3))
             psi = np.real(np.fft.ifftn(G[None] * FQ, axes=(1, 2, 3))).reshape(len(J), nk) * nk
             A[:, J] += np.einsum("ip,jip->ij", wt, psi[:, flat])   # G carries KE
-    V = float(np.prod(box))
+    V = volume(box)
     A += -KE * np.pi / (V * a * a)
     A[np.diag_indices(n)] += -KE * 2.0 * a / np.sqrt(np.pi)
     return 0.5 * (A + A.T)

@@ -17,7 +17,10 @@ standard smooth PME of Essmann et al. (1995). With u_id = K_d * frac(r_id/L_d),
   E_rec = 1/2 sum_m G(m) |FQ(m)|^2,   FQ = forward DFT of Q
   psi(k) = sum_m G(m) FQ(m) exp(+2 pi i m.k/K)
   phi_rec,i = sum_k W_i(k) psi(k),  F_rec,i = -q_i sum_k grad W_i(k) psi(k)
-with |m|^2 = sum_d (m_d'/L_d)^2 and m_d' the signed frequency. For odd p and
+with |m|^2 = sum_d (m_d'/L_d)^2 and m_d' the signed frequency. A triclinic
+cell (lattice vectors the rows of H) takes u_id = K_d * frac(s_id) with the
+fractional coordinates s = r H^-1, |m|^2 = |H^-1 m'|^2, and forces through
+du_d/dr = K_d (column d of H^-1). For odd p and
 even K the Euler factor at m = K/2 has a zero denominator; it is replaced by
 the mean of its two neighbours (both sides of the library do the same).
 """
@@ -27,7 +30,7 @@ import math
 
 import numpy as np
 
-from .ewald import KE, wrap
+from .ewald import KE, cell_matrix, fractional, is_triclinic, volume, wrap
 
 
 def bspline(p: int, x):
@@ -58,16 +61,24 @@ def euler_factors(K: int, p: int) -> np.ndarray:
 
 
 def influence(box, alpha, grid, p) -> np.ndarray:
-    """G(m) on the full K1 x K2 x K3 frequency grid (numpy FFT index order)."""
-    box = np.asarray(box, np.float64)
+    """G(m) on the full K1 x K2 x K3 frequency grid (numpy FFT index order).
+    |m|^2 is the squared reciprocal vector: sum_d (m_d'/L_d)^2, or for a
+    triclinic cell |H^-1 m'|^2."""
     K = np.broadcast_to(np.asarray(grid), (3,)).astype(int)
-    V = float(np.prod(box))
+    V = volume(box)
     ms = []
     for d in range(3):
         m = np.arange(K[d])
-        ms.append(np.where(m <= K[d] // 2, m, m - K[d]) / box[d])
+        ms.append(np.where(m <= K[d] // 2, m, m - K[d]).astype(np.float64))
     mx, my, mz = np.meshgrid(*ms, indexing="ij")
-    m2 = mx * mx + my * my + mz * mz
+    if is_triclinic(box):
+        R = np.linalg.inv(cell_matrix(box))          # column d: reciprocal vector of axis d
+        kv = [R[r, 0] * mx + R[r, 1] * my + R[r, 2] * mz for r in range(3)]
+        m2 = kv[0] ** 2 + kv[1] ** 2 + kv[2] ** 2
+    else:
+        box = np.asarray(box, np.float64)
+        mx, my, mz = mx / box[0], my / box[1], mz / box[2]
+        m2 = mx * mx + my * my + mz * mz
     m2[0, 0, 0] = 1.0
     G = KE * np.exp(-math.pi ** 2 * m2 / alpha ** 2) / (math.pi * V * m2)
     G[0, 0, 0] = 0.0
@@ -76,22 +87,29 @@ def influence(box, alpha, grid, p) -> np.ndarray:
 
 
 def _stencil(pos, box, grid, p):
-    """Per atom and axis: grid indices (N,3,p), weights (N,3,p), derivatives (N,3,p)."""
-    box = np.asarray(box, np.float64)
+    """Per atom and axis: grid indices (N,3,p), weights (N,3,p), derivatives
+    (N,3,p) with respect to the scaled fractional coordinate u_d = K_d s_d."""
     K = np.broadcast_to(np.asarray(grid), (3,)).astype(int)
     w = wrap(np.asarray(pos, np.float64), box)
-    u = K[None, :] * (w / box[None, :])
+    u = K[None, :] * fractional(w, box)
     base = np.floor(u)
     fr = u - base
     t = np.arange(p)
     x = fr[:, :, None] + t[None, None, :]            # u - k for k = base - t
     idx = (base[:, :, None].astype(np.int64) - t[None, None, :]) % K[None, :, None]
-    return idx, bspline(p, x), bspline_deriv(p, x) * (K / box)[None, :, None]
+    return idx, bspline(p, x), bspline_deriv(p, x)
+
+
+def du_dr(box, grid) -> np.ndarray:
+    """J[d, k] = d u_d / d r_k = K_d (H^-1)[k, d]  (diagonal K_d / L_d when orthorhombic)."""
+    K = np.broadcast_to(np.asarray(grid), (3,)).astype(np.float64)
+    if not is_triclinic(box):
+        return np.diag(K / np.asarray(box, np.float64))
+    return K[:, None] * np.linalg.inv(cell_matrix(box)).T
 
 
 def spme_reciprocal(pos, q, box, alpha, grid, p, rows=None):
     """FP64 SPME reciprocal part: returns (phi_rec, F_rec, E_rec), phi in eV/e."""
-    box = np.asarray(box, np.float64)
     K = np.broadcast_to(np.asarray(grid), (3,)).astype(int)
     q = np.asarray(q, np.float64)
     idx, W, dW = _stencil(pos, box, K, p)
@@ -115,7 +133,8 @@ def spme_reciprocal(pos, q, box, alpha, grid, p, rows=None):
     gx = np.einsum("nabc,na,nb,nc->n", ps, dWr[:, 0], Wr[:, 1], Wr[:, 2])
     gy = np.einsum("nabc,na,nb,nc->n", ps, Wr[:, 0], dWr[:, 1], Wr[:, 2])
     gz = np.einsum("nabc,na,nb,nc->n", ps, Wr[:, 0], Wr[:, 1], dWr[:, 2])
-    F = -q[rows][:, None] * np.stack([gx, gy, gz], 1)
+    # chain rule from the scaled fractional coordinates u to r
+    F = -q[rows][:, None] * (np.stack([gx, gy, gz], 1) @ du_dr(box, K))
     return phi, F, E
 
 
