@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define PQ_ABI_VERSION 3
+#define PQ_ABI_VERSION 4
 
 typedef enum pq_status {
     PQ_OK = 0,
@@ -67,7 +67,7 @@ enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1, PQ_METHOD_AUTO = 2 /* pq_choose_p
  * charges, box, Ewald parameter, grid dimensions, spline order) and the
  * regular Ewald sum (eqs. ewald_real, ewald_rec, ewald_self). */
 typedef struct pq_params {
-    double box[3];    /* orthorhombic box edges L_d in A, each > 0                   */
+    double box[3];    /* box edges L_d in A, each > 0: the diagonal of the lattice  */
     double cutoff;    /* real-space cutoff rc in A, > 0; the erfc sum keeps |d| < rc  */
     double skin;      /* neighbour-list skin in A, >= 0 (list radius rc + skin)        */
     double alpha;     /* Ewald splitting parameter in 1/A, > 0                         */
@@ -76,6 +76,18 @@ typedef struct pq_params {
     int32_t kmax[3];  /* direct Ewald: k = 2 pi n / L over |n_d| <= kmax_d, 0..64     */
     int32_t method;   /* PQ_METHOD_PME (grid, order used) or PQ_METHOD_EWALD (kmax)   */
     int32_t flags;    /* 0 or PQ_FLAG_FP64; other bits are rejected (PQ_ERR_INVALID)  */
+    double tilt[3];   /* triclinic tilt factors (t_xy, t_xz, t_yz) in A; all 0 for an
+                       * orthorhombic box. The lattice vectors are the rows of
+                       *   a = (L0, 0, 0), b = (t_xy, L1, 0), c = (t_xz, t_yz, L2)
+                       * (the general cell rotated so that a lies on x and b in the
+                       * x-y plane), with |t_xy| <= L0/2, |t_xz| <= L0/2,
+                       * |t_yz| <= L1/2 (any lattice has such a reduced basis; else
+                       * PQ_ERR_BOX). Images are n0 a + n1 b + n2 c, wave vectors
+                       * 2 pi H^-1 n, PME works on the fractional coordinates
+                       * s = r H^-1 (the paper names triclinic cells for the Ewald
+                       * sum, Section "Regular Ewald Summation"). With zero tilts
+                       * every result is bit for bit that of the orthorhombic box.
+                       * pq_md_run requires zero tilts (PQ_ERR_BOX). */
 } pq_params;
 
 /* Accuracy-driven parameters. The paper tunes the number of k-vectors of the

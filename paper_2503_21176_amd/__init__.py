@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 PQ_OK = 0
 FLAG_FP64 = 1
 PQ_WARN_NOT_CONVERGED = 1
@@ -44,7 +44,8 @@ class PQError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double * 3), ("cutoff", ctypes.c_double), ("skin", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("grid", ctypes.c_int32 * 3), ("order", ctypes.c_int32),
-                ("kmax", ctypes.c_int32 * 3), ("method", ctypes.c_int32), ("flags", ctypes.c_int32)]
+                ("kmax", ctypes.c_int32 * 3), ("method", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tilt", ctypes.c_double * 3)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -134,11 +135,21 @@ def coulomb_constant() -> float:
 
 def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, method="pme",
                 fp64=False) -> Params:
-    """Parameters of one periodic system. ``fp64`` selects FP64 bulk arithmetic
-    (PQ_FLAG_FP64) instead of the default FP32 bulk with FP64 reductions."""
+    """Parameters of one periodic system. ``box``: an edge, three edges, or a
+    3x3 lower triangular matrix whose rows are the lattice vectors
+    a = (L0, 0, 0), b = (t_xy, L1, 0), c = (t_xz, t_yz, L2) (triclinic).
+    ``fp64`` selects FP64 bulk arithmetic (PQ_FLAG_FP64) instead of the
+    default FP32 bulk with FP64 reductions."""
     p = Params()
-    b = [float(x) for x in (box if hasattr(box, "__len__") else (box, box, box))]
-    p.box[:] = b
+    H = np.asarray(box, np.float64)
+    if H.shape == (3, 3):
+        if H[0, 1] != 0 or H[0, 2] != 0 or H[1, 2] != 0:
+            raise ValueError("a triclinic box must be lower triangular (rows a, b, c)")
+        p.box[:] = [float(H[0, 0]), float(H[1, 1]), float(H[2, 2])]
+        p.tilt[:] = [float(H[1, 0]), float(H[2, 0]), float(H[2, 1])]
+    else:
+        b = [float(x) for x in (box if hasattr(box, "__len__") else (box, box, box))]
+        p.box[:] = b
     p.cutoff, p.skin, p.alpha = float(cutoff), float(skin), float(alpha)
     if method == "pme":
         g = grid if hasattr(grid, "__len__") else (grid, grid, grid)

@@ -38,6 +38,19 @@ Ctx::~Ctx() {
     for (auto e : ev_pool) (void)hipEventDestroy(e);
 }
 
+Tric make_tric(const pq_params& p) {
+#pragma clang fp contract(off)
+    Tric t;
+    t.txy = p.tilt[0];
+    t.txz = p.tilt[1];
+    t.tyz = p.tilt[2];
+    const double i1 = 1.0 / p.box[1], i2 = 1.0 / p.box[2];
+    t.ryz = t.tyz * i2;
+    t.cxy = t.txy * i1;
+    t.cxz = (t.txz - t.tyz * t.cxy) * i2;
+    return t;
+}
+
 static bool smooth235(int k) {
     if (k <= 0) return false;
     for (int p : {2, 3, 5})
@@ -53,6 +66,11 @@ static void validate(int64_t n, const pq_params* p) {
     PQ_REQUIRE(std::isfinite(p->cutoff) && p->cutoff > 0.0, PQ_ERR_INVALID, "cutoff must be > 0");
     PQ_REQUIRE(std::isfinite(p->skin) && p->skin >= 0.0, PQ_ERR_INVALID, "skin must be >= 0");
     PQ_REQUIRE(std::isfinite(p->alpha) && p->alpha > 0.0, PQ_ERR_INVALID, "alpha must be > 0");
+    for (int d = 0; d < 3; ++d) PQ_REQUIRE(std::isfinite(p->tilt[d]), PQ_ERR_INVALID, "tilt factors must be finite");
+    PQ_REQUIRE(std::fabs(p->tilt[0]) <= 0.5 * p->box[0] * (1 + 1e-12) &&
+                   std::fabs(p->tilt[1]) <= 0.5 * p->box[0] * (1 + 1e-12) &&
+                   std::fabs(p->tilt[2]) <= 0.5 * p->box[1] * (1 + 1e-12),
+               PQ_ERR_BOX, "tilt factors must satisfy |t_xy|, |t_xz| <= L0/2 and |t_yz| <= L1/2");
     PQ_REQUIRE((p->flags & ~PQ_FLAG_FP64) == 0, PQ_ERR_INVALID, "unknown bits in flags");
     PQ_REQUIRE(p->method == PQ_METHOD_PME || p->method == PQ_METHOD_EWALD, PQ_ERR_INVALID, "unknown method");
     if (p->method == PQ_METHOD_PME) {

@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "pq_internal.h"
+
 namespace pq {
 
 // Canonical wrap into [0, L): w = x - L*floor(x*(1/L)), three separately
@@ -24,6 +26,57 @@ __device__ __forceinline__ double canon_d2(const double* __restrict__ wi, const 
     double dx = (wj[0] - wi[0]) + (double)n0 * L0;
     double dy = (wj[1] - wi[1]) + (double)n1 * L1;
     double dz = (wj[2] - wi[2]) + (double)n2 * L2;
+    double a = dx * dx;
+    double b = dy * dy;
+    double c = dz * dz;
+    return (a + b) + c;
+}
+
+// Canonical wrap into the triclinic cell: the c, b and a components are
+// removed in turn by the floor of the current fractional coordinate, every
+// product and difference rounded once (with zero tilts: canon_wrap per axis).
+__device__ __forceinline__ void canon_wrap_tric(double& x, double& y, double& z, const double* L, const double* inv,
+                                                const Tric& t) {
+#pragma clang fp contract(off)
+    const double f2 = floor(z * inv[2]);
+    z = z - f2 * L[2];
+    y = y - f2 * t.tyz;
+    x = x - f2 * t.txz;
+    const double f1 = floor((y - z * t.ryz) * inv[1]);
+    y = y - f1 * L[1];
+    x = x - f1 * t.txy;
+    const double f0 = floor(((x - y * t.cxy) - z * t.cxz) * inv[0]);
+    x = x - f0 * L[0];
+}
+
+// Fractional coordinates of a wrapped position.
+__device__ __forceinline__ void frac_tric(double x, double y, double z, const double* inv, const Tric& t, double& s0,
+                                          double& s1, double& s2) {
+#pragma clang fp contract(off)
+    s2 = z * inv[2];
+    s1 = (y - z * t.ryz) * inv[1];
+    s0 = ((x - y * t.cxy) - z * t.cxz) * inv[0];
+}
+
+// Lattice vector n0 a + n1 b + n2 c, each component summed left to right from
+// separately rounded products: x = (n0 L0 + n1 txy) + n2 txz, y = n1 L1 + n2 tyz,
+// z = n2 L2 (with zero tilts exactly n*L).
+__device__ __forceinline__ void lattice_vec(int n0, int n1, int n2, const double* L, const Tric& t, double& sx,
+                                            double& sy, double& sz) {
+#pragma clang fp contract(off)
+    sx = ((double)n0 * L[0] + (double)n1 * t.txy) + (double)n2 * t.txz;
+    sy = (double)n1 * L[1] + (double)n2 * t.tyz;
+    sz = (double)n2 * L[2];
+}
+
+// Canonical squared distance between w_i and w_j + s (s a lattice vector):
+// d = (w_j - w_i) + s per axis, d.d = (dx*dx + dy*dy) + dz*dz, no contraction.
+__device__ __forceinline__ double canon_d2s(const double* __restrict__ wi, const double* __restrict__ wj, double sx,
+                                            double sy, double sz) {
+#pragma clang fp contract(off)
+    double dx = (wj[0] - wi[0]) + sx;
+    double dy = (wj[1] - wi[1]) + sy;
+    double dz = (wj[2] - wi[2]) + sz;
     double a = dx * dx;
     double b = dy * dy;
     double c = dz * dz;

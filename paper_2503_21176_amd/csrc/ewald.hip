@@ -40,13 +40,32 @@ __device__ __forceinline__ void phase(const int4 nk, double s0, double s1, doubl
 // potentials and forces over chunks of k vectors; the chunk partials are then
 // added in chunk order (deterministic, independent of the launch).
 
+// Fractional coordinates s = r H^-1 of a wrapped position (orthorhombic:
+// s_d = r_d / L_d), and the rows of R = H^-1 that turn the fractional
+// gradient into the Cartesian force.
+struct EwFrac {
+    double inv[3];
+    int tric;
+    Tric t;
+    double r10, r20, r21;
+};
+__device__ __forceinline__ void ew_frac(const double* __restrict__ w, const EwFrac& f, double& s0, double& s1,
+                                        double& s2) {
+    if (f.tric) {
+        frac_tric(w[0], w[1], w[2], f.inv, f.t, s0, s1, s2);
+    } else {
+        s0 = w[0] * f.inv[0];
+        s1 = w[1] * f.inv[1];
+        s2 = w[2] * f.inv[2];
+    }
+}
+
 // Structure-factor partials: one thread per k vector, blockIdx.y = atom chunk
 // [y cs, (y+1) cs), atoms staged through LDS.
 template <class T>
 __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, int cs, const int4* __restrict__ kn,
-                                                 const double* __restrict__ w64, double inv0, double inv1,
-                                                 double inv2, const double* __restrict__ q,
-                                                 double2* __restrict__ spart) {
+                                                 const double* __restrict__ w64, EwFrac fr,
+                                                 const double* __restrict__ q, double2* __restrict__ spart) {
     __shared__ double s_s[EW_TILE * 3];
     __shared__ double s_q[EW_TILE];
     const int kidx = blockIdx.x * EW_TILE + threadIdx.x;
@@ -57,9 +76,8 @@ __global__ __launch_bounds__(EW_TILE) void k_sfac(int n, int nk, int cs, const i
     for (int j0 = jb; j0 < je; j0 += EW_TILE) {
         const int j = j0 + threadIdx.x;
         if (j < je) {
-            s_s[3 * threadIdx.x + 0] = w64[3 * (size_t)j + 0] * inv0;
-            s_s[3 * threadIdx.x + 1] = w64[3 * (size_t)j + 1] * inv1;
-            s_s[3 * threadIdx.x + 2] = w64[3 * (size_t)j + 2] * inv2;
+            ew_frac(w64 + 3 * (size_t)j, fr, s_s[3 * threadIdx.x + 0], s_s[3 * threadIdx.x + 1],
+                    s_s[3 * threadIdx.x + 2]);
             s_q[threadIdx.x] = q[j];
         }
         __syncthreads();
@@ -103,19 +121,14 @@ template <bool FORCE, class T>
 __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, int kcs, const int4* __restrict__ kn,
                                                     const double* __restrict__ kc,
                                                     const double2* __restrict__ sfac, const double* __restrict__ w64,
-                                                    double inv0, double inv1, double inv2,
-                                                    double4* __restrict__ gpart) {
+                                                    EwFrac fr, double4* __restrict__ gpart) {
     __shared__ int4 s_n[EW_TILE];
     __shared__ double s_c[EW_TILE];
     __shared__ double2 s_S[EW_TILE];
     const int i = blockIdx.x * EW_TILE + threadIdx.x;
     const bool valid = i < n;
     double s0 = 0, s1 = 0, s2 = 0;
-    if (valid) {
-        s0 = w64[3 * (size_t)i] * inv0;
-        s1 = w64[3 * (size_t)i + 1] * inv1;
-        s2 = w64[3 * (size_t)i + 2] * inv2;
-    }
+    if (valid) ew_frac(w64 + 3 * (size_t)i, fr, s0, s1, s2);
     const int kb = blockIdx.y * kcs, ke = min(nk, kb + kcs);
     double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
     for (int k0 = kb; k0 < ke; k0 += EW_TILE) {
@@ -150,9 +163,8 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather(int n, int nk, int kcs, con
 // Per atom: the k-chunk partials in chunk order, then phi and F.
 template <bool FORCE, class T>
 __global__ __launch_bounds__(EW_TILE) void k_kgather_sum(int n, int nkch, const double4* __restrict__ gpart,
-                                                        double inv0, double inv1, double inv2,
-                                                        const double* __restrict__ q, T* __restrict__ phi_out,
-                                                        V4<T>* __restrict__ f_out) {
+                                                        EwFrac fr, const double* __restrict__ q,
+                                                        T* __restrict__ phi_out, V4<T>* __restrict__ f_out) {
     const int i = blockIdx.x * EW_TILE + threadIdx.x;
     if (i >= n) return;
     double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
@@ -166,7 +178,11 @@ __global__ __launch_bounds__(EW_TILE) void k_kgather_sum(int n, int nkch, const 
     phi_out[i] = (T)(2.0 * phi);
     if (FORCE) {
         const double f = 2.0 * q[i] * 2.0 * PI;
-        f_out[i] = mk4<T>((T)(f * g0 * inv0), (T)(f * g1 * inv1), (T)(f * g2 * inv2), T(0));
+        if (fr.tric)
+            f_out[i] = mk4<T>((T)(f * (g0 * fr.inv[0])), (T)(f * (g1 * fr.inv[1] + g0 * fr.r10)),
+                              (T)(f * ((g2 * fr.inv[2] + g1 * fr.r21) + g0 * fr.r20)), T(0));
+        else
+            f_out[i] = mk4<T>((T)(f * g0 * fr.inv[0]), (T)(f * g1 * fr.inv[1]), (T)(f * g2 * fr.inv[2]), T(0));
     }
 }
 
@@ -184,13 +200,26 @@ void ewald_setup(Ctx& c) {
     const double a = c.prm.alpha;
     std::vector<int4> nv;
     std::vector<double> cv;
+    const bool tric = is_tric(c.prm);
+    const double L0 = c.prm.box[0], L1 = c.prm.box[1], L2 = c.prm.box[2];
+    const double txy = c.prm.tilt[0], txz = c.prm.tilt[1], tyz = c.prm.tilt[2];
+    const double r00 = 1.0 / L0, r11 = 1.0 / L1, r22 = 1.0 / L2, r10 = -txy / (L0 * L1),
+                 r21 = -tyz / (L1 * L2), r20 = (txy * tyz - L1 * txz) / (L0 * L1 * L2);
     for (int x = 0; x <= km[0]; ++x)
         for (int y = -km[1]; y <= km[1]; ++y)
             for (int z = -km[2]; z <= km[2]; ++z) {
                 if (!(x > 0 || (x == 0 && (y > 0 || (y == 0 && z > 0))))) continue;
-                const double kx = 2.0 * PI * x / c.prm.box[0], ky = 2.0 * PI * y / c.prm.box[1],
-                             kz = 2.0 * PI * z / c.prm.box[2];
-                const double k2 = kx * kx + ky * ky + kz * kz;
+                double k2;
+                if (tric) {
+                    // k = 2 pi R n with R = H^-1 lower triangular
+                    const double kx = 2.0 * PI * (r00 * x), ky = 2.0 * PI * (r10 * x + r11 * y),
+                                 kz = 2.0 * PI * ((r20 * x + r21 * y) + r22 * z);
+                    k2 = kx * kx + ky * ky + kz * kz;
+                } else {
+                    const double kx = 2.0 * PI * x / c.prm.box[0], ky = 2.0 * PI * y / c.prm.box[1],
+                                 kz = 2.0 * PI * z / c.prm.box[2];
+                    k2 = kx * kx + ky * ky + kz * kz;
+                }
                 nv.push_back(make_int4(x, y, z, 0));
                 cv.push_back(4.0 * PI / V * std::exp(-k2 / (4.0 * a * a)) / k2);
             }
@@ -222,7 +251,17 @@ __global__ void k_zero_bytes(unsigned char* __restrict__ p, size_t n) {
 template <class T>
 static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
     const int n = (int)c.n;
-    const double i0 = 1.0 / c.prm.box[0], i1 = 1.0 / c.prm.box[1], i2 = 1.0 / c.prm.box[2];
+    EwFrac fr;
+    for (int d = 0; d < 3; ++d) fr.inv[d] = 1.0 / c.prm.box[d];
+    fr.tric = is_tric(c.prm) ? 1 : 0;
+    fr.t = make_tric(c.prm);
+    {
+        const double L0 = c.prm.box[0], L1 = c.prm.box[1], L2 = c.prm.box[2];
+        const double txy = c.prm.tilt[0], txz = c.prm.tilt[1], tyz = c.prm.tilt[2];
+        fr.r10 = -txy / (L0 * L1);
+        fr.r21 = -tyz / (L1 * L2);
+        fr.r20 = (txy * tyz - L1 * txz) / (L0 * L1 * L2);
+    }
     T* phi = as<T>(c.phi_k);
     V4<T>* f = as<V4<T>>(c.f_k);
     if (c.nk == 0) {
@@ -241,22 +280,19 @@ static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
     PQ_REQUIRE(c.part.n >= (size_t)nb + 16 && c.spart.n >= (size_t)c.ew_nch * c.nk &&
                    c.gpart.n >= (size_t)c.ew_nkch * n,
                PQ_ERR_STATE, "direct-Ewald workspaces not sized");
-    PQ_LAUNCH(k_sfac<T>, dim3(nb, c.ew_nch), EW_TILE, 0, s, n, c.nk, c.ew_cs, c.kn.p, c.w64.p, i0, i1, i2, q,
-              c.spart.p);
+    PQ_LAUNCH(k_sfac<T>, dim3(nb, c.ew_nch), EW_TILE, 0, s, n, c.nk, c.ew_cs, c.kn.p, c.w64.p, fr, q, c.spart.p);
     PQ_LAUNCH(k_sfac_sum, nb, EW_TILE, 0, s, c.nk, c.ew_nch, c.kc.p, c.spart.p, c.sfac.p, c.part.p);
     PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.part.p, nb, c.scal.p + 1);
     if (n == 0) return;
     const dim3 g(cdiv(n, EW_TILE), c.ew_nkch);
     if (force) {
-        PQ_LAUNCH((k_kgather<true, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0, i1,
-                  i2, c.gpart.p);
-        PQ_LAUNCH((k_kgather_sum<true, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, i0, i1, i2, q,
-                  phi, f);
+        PQ_LAUNCH((k_kgather<true, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, fr,
+                  c.gpart.p);
+        PQ_LAUNCH((k_kgather_sum<true, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, fr, q, phi, f);
     } else {
-        PQ_LAUNCH((k_kgather<false, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, i0,
-                  i1, i2, c.gpart.p);
-        PQ_LAUNCH((k_kgather_sum<false, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, i0, i1, i2, q,
-                  phi, f);
+        PQ_LAUNCH((k_kgather<false, T>), g, EW_TILE, 0, s, n, c.nk, c.ew_kcs, c.kn.p, c.kc.p, c.sfac.p, c.w64.p, fr,
+                  c.gpart.p);
+        PQ_LAUNCH((k_kgather_sum<false, T>), cdiv(n, EW_TILE), EW_TILE, 0, s, n, c.ew_nkch, c.gpart.p, fr, q, phi, f);
     }
 }
 

@@ -324,7 +324,19 @@ struct ConvArgs {
     const double* S2;
     double scale;
     int K0;
+    int tric;
+    const double *B0, *B1, *B2, *M0, *M1, *M2;
+    double r00, r10, r11, r20, r21, r22, pa2;
 };
+
+// G(m) of a triclinic cell: scale B0 B1 B2 exp(-pi^2 |k|^2 / alpha^2) / |k|^2
+// with k = R m' (R = H^-1 lower triangular, m' the signed frequencies).
+__device__ __forceinline__ double conv_g_tric(const ConvArgs& cv, int mx, int my, int mz) {
+    const double m0 = cv.M0[mx], m1 = cv.M1[my], m2 = cv.M2[mz];
+    const double kx = cv.r00 * m0, ky = cv.r10 * m0 + cv.r11 * m1, kz = (cv.r20 * m0 + cv.r21 * m1) + cv.r22 * m2;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    return cv.scale * cv.B0[mx] * cv.B1[my] * cv.B2[mz] * exp(-cv.pa2 * k2) / k2;
+}
 
 template <int SIGN, bool CONV, class T>
 __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restrict__ tw, int X, int tx,
@@ -364,7 +376,7 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
                 const double tx0 = cv.scale * cv.T0[mx] * cv.T1[my], sx0 = cv.S0[mx] + cv.S1[my];
                 for (int mz = u; mz < n; mz += 16) {
                     if ((mx | my | mz) == 0) continue;
-                    const double g = tx0 * cv.T2[mz] / (sx0 + cv.S2[mz]);
+                    const double g = cv.tric ? conv_g_tric(cv, mx, my, mz) : tx0 * cv.T2[mz] / (sx0 + cv.S2[mz]);
                     const C v = r[mz * tx + s];
                     e += wgt * g * ((double)v.x * v.x + (double)v.y * v.y);
                 }
@@ -379,7 +391,8 @@ __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restr
             const int mx = mx0 + s;
             T gk = T(0);
             if (mx < X && (mx | my | mz) != 0)
-                gk = (T)(cv.scale * cv.T0[mx] * cv.T1[my] * cv.T2[mz] / (cv.S0[mx] + cv.S1[my] + cv.S2[mz]));
+                gk = (T)(cv.tric ? conv_g_tric(cv, mx, my, mz)
+                                 : cv.scale * cv.T0[mx] * cv.T1[my] * cv.T2[mz] / (cv.S0[mx] + cv.S1[my] + cv.S2[mz]));
             r[idx] = cmk<C>(r[idx].x * gk, r[idx].y * gk);
         }
         __syncthreads();
@@ -463,7 +476,8 @@ __global__ __launch_bounds__(CT*(R1 > R2 ? R1 : R2)) void k_fft_col2(const V2<T>
             for (int k2 = 0; k2 < R2; ++k2) {
                 const int mz = g + R1 * k2;
                 double gk = 0.0;
-                if (col && (mx | my | mz) != 0) gk = t01 * cv.T2[mz] / (s01 + cv.S2[mz]);
+                if (col && (mx | my | mz) != 0)
+                    gk = cv.tric ? conv_g_tric(cv, mx, my, mz) : t01 * cv.T2[mz] / (s01 + cv.S2[mz]);
                 if (epart) e += wgt * gk * ((double)u[k2].x * u[k2].x + (double)u[k2].y * u[k2].y);
                 u[k2] = cmk<C>(u[k2].x * (T)gk, u[k2].y * (T)gk);
             }
@@ -732,9 +746,10 @@ static void col2_radices(int n, int& r1, int& r2) {
 void fft_setup(Ctx& c) {
     // twiddle and influence tables depend only on the grid, the spline order,
     // alpha, the box and the precision: kept when none of them changed
-    const double key[9] = {(double)c.K[0], (double)c.K[1], (double)c.K[2], (double)c.P, c.prm.alpha,
-                           c.prm.box[0],   c.prm.box[1],   c.prm.box[2],   c.fp64 ? 1.0 : 0.0};
-    if (c.fft_key_valid && std::equal(key, key + 9, c.fft_key)) return;
+    const double key[12] = {(double)c.K[0], (double)c.K[1], (double)c.K[2], (double)c.P, c.prm.alpha,
+                            c.prm.box[0],   c.prm.box[1],   c.prm.box[2],   c.prm.tilt[0], c.prm.tilt[1],
+                            c.prm.tilt[2],  c.fp64 ? 1.0 : 0.0};
+    if (c.fft_key_valid && std::equal(key, key + 12, c.fft_key)) return;
     c.fft_key_valid = false;
     std::vector<double> tw;   // interleaved (cos, sin), rounded to the bulk precision on upload
     int off[3];
@@ -782,7 +797,7 @@ void fft_setup(Ctx& c) {
     // influence tables
     const double a = c.prm.alpha;
     std::vector<double> tab;
-    int toff[3], soff[3];
+    int toff[3], soff[3], boff[3], moff[3];
     for (int d = 0; d < 3; ++d) {
         const int K = c.K[d];
         const double L = c.prm.box[d];
@@ -798,16 +813,34 @@ void fft_setup(Ctx& c) {
             const double mp = (m <= K / 2) ? m : m - K;
             tab.push_back((mp / L) * (mp / L));
         }
+        boff[d] = (int)tab.size();
+        for (int m = 0; m < K; ++m) tab.push_back(B[m]);
+        moff[d] = (int)tab.size();
+        for (int m = 0; m < K; ++m) tab.push_back((m <= K / 2) ? (double)m : (double)(m - K));
     }
     c.inftab.ensure(tab.size());
     PQ_HIP(hipMemcpy(c.inftab.p, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice));
     for (int d = 0; d < 3; ++d) {
         c.inf.T[d] = c.inftab.p + toff[d];
         c.inf.S[d] = c.inftab.p + soff[d];
+        c.inf.B[d] = c.inftab.p + boff[d];
+        c.inf.M[d] = c.inftab.p + moff[d];
     }
     const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
     c.inf.scale = 1.0 / (PI * V);
-    std::copy(key, key + 9, c.fft_key);
+    {
+        const double L0 = c.prm.box[0], L1 = c.prm.box[1], L2 = c.prm.box[2];
+        const double txy = c.prm.tilt[0], txz = c.prm.tilt[1], tyz = c.prm.tilt[2];
+        c.inf.tric = is_tric(c.prm) ? 1 : 0;
+        c.inf.r00 = 1.0 / L0;
+        c.inf.r11 = 1.0 / L1;
+        c.inf.r22 = 1.0 / L2;
+        c.inf.r10 = -txy / (L0 * L1);
+        c.inf.r21 = -tyz / (L1 * L2);
+        c.inf.r20 = (txy * tyz - L1 * txz) / (L0 * L1 * L2);
+        c.inf.pa2 = PI * PI / (a * a);
+    }
+    std::copy(key, key + 12, c.fft_key);
     c.fft_key_valid = true;
 }
 
@@ -869,7 +902,10 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     const C* tw2 = static_cast<const C*>(c.fft[2].tw);
     T* grid = as<T>(c.grid);
     C* spec = as<C>(c.spec);
-    ConvArgs cv{c.inf.T[0], c.inf.T[1], c.inf.T[2], c.inf.S[0], c.inf.S[1], c.inf.S[2], c.inf.scale, K0};
+    const InfTab& it = c.inf;
+    ConvArgs cv{it.T[0], it.T[1], it.T[2], it.S[0], it.S[1], it.S[2], it.scale, K0,
+                it.tric, it.B[0], it.B[1], it.B[2], it.M[0], it.M[1], it.M[2],
+                it.r00, it.r10, it.r11, it.r20, it.r21, it.r22, it.pa2};
     const int np = row_pairs(K0, esz, c.fft_budget);
     const int npairs = (nrows + 1) / 2;
     const C* wn0 = static_cast<const C*>(c.fft[0].wn);

@@ -174,6 +174,7 @@ static int md_history(int dissipation) { return dissipation == 5 ? 6 : 2; }
 void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* chi, const double* eta,
             double q_tot, double* n_hist, int steps, const pq_md_cfg& cfg, double* energies) {
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_REQUIRE(!is_tric(c.prm), PQ_ERR_BOX, "the MD driver takes orthorhombic boxes (zero tilts)");
     PQ_REQUIRE(std::isfinite(cfg.dt_fs) && cfg.dt_fs > 0.0, PQ_ERR_INVALID, "dt_fs must be > 0");
     PQ_REQUIRE(cfg.n_krylov >= 1 && cfg.n_krylov <= 512, PQ_ERR_INVALID, "n_krylov must be in 1..512");
     PQ_REQUIRE(cfg.dissipation == 0 || cfg.dissipation == 5, PQ_ERR_INVALID, "dissipation must be 0 or 5");

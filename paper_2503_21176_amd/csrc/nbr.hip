@@ -23,28 +23,45 @@ __global__ void k_fill_int(int* __restrict__ a, int n, int v) {
     if (i < n) a[i] = v;
 }
 
-// Wrap positions into the box, pick each atom's column, count per column.
-__global__ void k_wrap_count(int n, const double* __restrict__ pos, Geom g, double* __restrict__ w64,
-                             int* __restrict__ col_of, int* __restrict__ col_cnt, int* __restrict__ flag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// Canonical wrap of atom i into the cell (stored in w64) and its column: x-y
+// columns of the box, or of the fractional coordinates (s0, s1) of a
+// triclinic cell. A non-finite position raises the flag and is placed at 0.
+__device__ __forceinline__ int wrap_column(int i, const double* __restrict__ pos, const Geom& g,
+                                           double* __restrict__ w64, int* __restrict__ flag) {
     double w[3];
     bool ok = true;
     for (int d = 0; d < 3; ++d) {
-        double x = pos[3 * (size_t)i + d];
-        ok = ok && isfinite(x);
-        w[d] = canon_wrap(x, g.L[d], g.invL[d]);
-        w64[3 * (size_t)i + d] = w[d];
+        w[d] = pos[3 * (size_t)i + d];
+        ok = ok && isfinite(w[d]);
     }
     if (!ok) {
         atomicOr(flag, 1);
         w[0] = w[1] = w[2] = 0.0;
     }
-    int cx = (int)floor(w[0] * ((double)g.ncx * g.invL[0]));
-    int cy = (int)floor(w[1] * ((double)g.ncy * g.invL[1]));
+    int cx, cy;
+    if (g.tric) {
+        canon_wrap_tric(w[0], w[1], w[2], g.L, g.invL, g.t);
+        double s0, s1, s2;
+        frac_tric(w[0], w[1], w[2], g.invL, g.t, s0, s1, s2);
+        cx = (int)floor(s0 * (double)g.ncx);
+        cy = (int)floor(s1 * (double)g.ncy);
+    } else {
+        for (int d = 0; d < 3; ++d) w[d] = canon_wrap(w[d], g.L[d], g.invL[d]);
+        cx = (int)floor(w[0] * ((double)g.ncx * g.invL[0]));
+        cy = (int)floor(w[1] * ((double)g.ncy * g.invL[1]));
+    }
+    for (int d = 0; d < 3; ++d) w64[3 * (size_t)i + d] = w[d];
     cx = min(max(cx, 0), g.ncx - 1);
     cy = min(max(cy, 0), g.ncy - 1);
-    int c = cx + g.ncx * cy;
+    return cx + g.ncx * cy;
+}
+
+// Wrap positions into the box, pick each atom's column, count per column.
+__global__ void k_wrap_count(int n, const double* __restrict__ pos, Geom g, double* __restrict__ w64,
+                             int* __restrict__ col_of, int* __restrict__ col_cnt, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = wrap_column(i, pos, g, w64, flag);
     col_of[i] = c;
     atomicAdd(&col_cnt[c], 1);
 }
@@ -170,23 +187,7 @@ __global__ __launch_bounds__(256) void k_wrap_hist(int n, int per, const double*
     __syncthreads();
     const int a0 = blockIdx.x * per, a1 = min(n, a0 + per);
     for (int i = a0 + threadIdx.x; i < a1; i += blockDim.x) {
-        double w[3];
-        bool ok = true;
-        for (int d = 0; d < 3; ++d) {
-            const double x = pos[3 * (size_t)i + d];
-            ok = ok && isfinite(x);
-            w[d] = canon_wrap(x, g.L[d], g.invL[d]);
-            w64[3 * (size_t)i + d] = w[d];
-        }
-        if (!ok) {
-            atomicOr(flag, 1);
-            w[0] = w[1] = w[2] = 0.0;
-        }
-        int cx = (int)floor(w[0] * ((double)g.ncx * g.invL[0]));
-        int cy = (int)floor(w[1] * ((double)g.ncy * g.invL[1]));
-        cx = min(max(cx, 0), g.ncx - 1);
-        cy = min(max(cy, 0), g.ncy - 1);
-        const int c = cx + g.ncx * cy;
+        const int c = wrap_column(i, pos, g, w64, flag);
         col_of[i] = c;
         atomicAdd(&cntl[c], 1);
     }
@@ -410,14 +411,20 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
                 const int cy = cyi + dy;
                 const int ny = (cy >= 0) ? cy / g.ncy : -((-cy + g.ncy - 1) / g.ncy);
                 const int cyw = cy - ny * g.ncy;
-                const double sy = (double)ny * g.L[1];
-                const double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
                 const int cx = cxi + dx;
                 const int nx = (cx >= 0) ? cx / g.ncx : -((-cx + g.ncx - 1) / g.ncx);
                 const int cxw = cx - nx * g.ncx;
-                const double sx = (double)nx * g.L[0];
-                const double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
-                if (!(gy > 0.0 && gy * gy >= rl2) && !(gx > 0.0 && gx * gx >= rl2)) {
+                // strip test of the column's x and y extent (orthorhombic; a
+                // triclinic column is a slanted prism and takes the box test only)
+                bool near = true;
+                if (!g.tric) {
+                    const double sy = (double)ny * g.L[1];
+                    const double gy = gap1(cyw * g.wy + sy, (cyw + 1) * g.wy + sy, loi1, hii1) - eps;
+                    const double sx = (double)nx * g.L[0];
+                    const double gx = gap1(cxw * g.wx + sx, (cxw + 1) * g.wx + sx, loi0, hii0) - eps;
+                    near = !(gy > 0.0 && gy * gy >= rl2) && !(gx > 0.0 && gx * gx >= rl2);
+                }
+                if (near) {
                     const size_t row = (size_t)(cxw + g.ncx * cyw) * (nbin + 1);
                     ja = zta[row + t0];
                     nc = max(0, ztb[row + t1] - ja);
@@ -457,7 +464,8 @@ __global__ __launch_bounds__(256) void k_list(int ncl, Geom g, const int* __rest
                     const bool valid = fb + 64 * u + lane < total;
                     int nx, ny, nzz;
                     unpack_img(im[u], nx, ny, nzz);
-                    const double sx = (double)nx * g.L[0], sy = (double)ny * g.L[1];
+                    double sx, sy, szz;
+                    lattice_vec(nx, ny, nzz, g.L, g.t, sx, sy, szz);
                     const double gxx = gap1(l0[u] + sx, h0[u] + sx, loi0, hii0);
                     const double gyy = gap1(l1[u] + sy, h1[u] + sy, loi1, hii1);
                     const double gz = gap1(l2[u] + sz, h2[u] + sz, loi2, hii2);
@@ -600,17 +608,19 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
         if (pj.w != 0.0) {
             int n0, n1, n2;
             unpack_img(je.y, n0, n1, n2);
+            double sx, sy, sz;
+            lattice_vec(n0, n1, n2, g.L, g.t, sx, sy, sz);
             if (!FILL) {
                 const double wj[3] = {pj.x, pj.y, pj.z};
 #pragma unroll
                 for (int a = 0; a < CL; ++a) {
-                    const double d2 = canon_d2(wi[a], wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]);
+                    const double d2 = canon_d2s(wi[a], wj, sx, sy, sz);
                     if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
                 }
             }
-            p0 = pj.x + (double)n0 * g.L[0];
-            pp1 = pj.y + (double)n1 * g.L[1];
-            p2 = pj.z + (double)n2 * g.L[2];
+            p0 = pj.x + sx;
+            pp1 = pj.y + sy;
+            p2 = pj.z + sz;
         }
         if (!FILL && eb + eo < e1) jmask[8 * (eb + eo) + b] = (unsigned char)col;
         const bool pass = col != 0;
@@ -662,7 +672,9 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
         bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
         if (ok) {
             const double wj[3] = {pj.x, pj.y, pj.z};
-            ok = canon_d2(wi, wj, n0, n1, n2, g.L[0], g.L[1], g.L[2]) < rl2;
+            double sx, sy, sz;
+            lattice_vec(n0, n1, n2, g.L, g.t, sx, sy, sz);
+            ok = canon_d2s(wi, wj, sx, sy, sz) < rl2;
         }
         return ok;
     };
@@ -726,14 +738,26 @@ void nbr_build(Ctx& c, const double* pos) {
     }
     g.rc = p.cutoff;
     g.rlist = p.cutoff + p.skin;
+    g.tric = is_tric(p) ? 1 : 0;
+    g.t = make_tric(p);
     // columns sized for ~8 atoms per cubic cluster
     const double V = p.box[0] * p.box[1] * p.box[2];
     const double rho = (double)n / V;
     const double a = std::cbrt((double)CL / rho);
-    g.ncx = std::max(1, (int)std::lround(p.box[0] / a));
-    g.ncy = std::max(1, (int)std::lround(p.box[1] / a));
-    g.wx = p.box[0] / g.ncx;
-    g.wy = p.box[1] / g.ncy;
+    // extent of the cell across its a and b faces: the edges, or for a
+    // triclinic cell the distances V/|b x c| and V/|c x a| between opposite
+    // faces (a pair within rlist differs by at most rlist/width in s_d)
+    double wid0 = p.box[0], wid1 = p.box[1];
+    if (g.tric) {
+        const double bx = p.tilt[0], cx = p.tilt[1], cy = p.tilt[2];
+        const double L0 = p.box[0], L1 = p.box[1], L2 = p.box[2];
+        wid0 = V / std::sqrt((L1 * L2) * (L1 * L2) + (bx * L2) * (bx * L2) + (bx * cy - L1 * cx) * (bx * cy - L1 * cx));
+        wid1 = V / (L0 * std::sqrt(L2 * L2 + cy * cy));
+    }
+    g.ncx = std::max(1, (int)std::lround(wid0 / a));
+    g.ncy = std::max(1, (int)std::lround(wid1 / a));
+    g.wx = wid0 / g.ncx;
+    g.wy = wid1 / g.ncy;
     g.Rx = (int)std::floor((g.rlist + 1e-6) / g.wx) + 1;
     g.Ry = (int)std::floor((g.rlist + 1e-6) / g.wy) + 1;
     g.Rz = (int)std::floor(g.rlist / p.box[2]) + 1;

@@ -62,6 +62,9 @@ struct PmeGeo {
     int K0, K1, K2;
     int nb0, nb1, nb2;
     double L[3], invL[3];
+    int tric;              // triclinic cell: fractional coordinates from t
+    Tric t;
+    double jyx, jzx, jzy;  // off-diagonal du/dr factors K0 R10, K0 R20, K1 R21 (R = H^-1)
 };
 
 // Base grid point, fractional offsets and brick of atom i.
@@ -71,8 +74,14 @@ __device__ __forceinline__ int pme_atom_setup(int i, const double* __restrict__ 
     const int K[3] = {G.K0, G.K1, G.K2};
     int base[3];
     T fr[3];
+    double s[3];
+    if (G.tric) {
+        frac_tric(w64[3 * (size_t)i], w64[3 * (size_t)i + 1], w64[3 * (size_t)i + 2], G.invL, G.t, s[0], s[1], s[2]);
+    } else {
+        for (int d = 0; d < 3; ++d) s[d] = w64[3 * (size_t)i + d] * G.invL[d];
+    }
     for (int d = 0; d < 3; ++d) {
-        double u = (double)K[d] * (w64[3 * (size_t)i + d] * G.invL[d]);
+        double u = (double)K[d] * s[d];
         double fl = floor(u);
         int b = (int)fl;
         double f = u - fl;
@@ -447,7 +456,16 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         }
         if (valid && sub == 0) {
             phi_out[i] = phi;
-            if (FORCE) f_out[i] = mk4<T>(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, T(0));
+            if (FORCE) {
+                if (G.tric) {
+                    // F = -q J^T g with J[d][k] = du_d/dr_k (lower triangular R = H^-1)
+                    const T jyx = (T)G.jyx, jzx = (T)G.jzx, jzy = (T)G.jzy;
+                    f_out[i] = mk4<T>(-qq * (kx * gxs), -qq * (ky * gys + jyx * gxs),
+                                      -qq * ((kz * gzs + jzy * gys) + jzx * gxs), T(0));
+                } else {
+                    f_out[i] = mk4<T>(-qq * kx * gxs, -qq * ky * gys, -qq * kz * gzs, T(0));
+                }
+            }
         }
     }
 }
@@ -464,6 +482,15 @@ static PmeGeo geo(const Ctx& c) {
         G.L[d] = c.prm.box[d];
         G.invL[d] = 1.0 / c.prm.box[d];
     }
+    G.tric = is_tric(c.prm) ? 1 : 0;
+    G.t = make_tric(c.prm);
+    // R = H^-1 below the diagonal: R10 = -txy/(L0 L1), R21 = -tyz/(L1 L2),
+    // R20 = (txy tyz - L1 txz)/(L0 L1 L2)
+    const double L0 = c.prm.box[0], L1 = c.prm.box[1], L2 = c.prm.box[2];
+    const double txy = c.prm.tilt[0], txz = c.prm.tilt[1], tyz = c.prm.tilt[2];
+    G.jyx = c.K[0] * (-txy / (L0 * L1));
+    G.jzx = c.K[0] * ((txy * tyz - L1 * txz) / (L0 * L1 * L2));
+    G.jzy = c.K[1] * (-tyz / (L1 * L2));
     return G;
 }
 

@@ -178,13 +178,29 @@ constexpr int JL_SLOT_BITS = 24; // j-list entry word: slot in the low bits, i-a
 constexpr int RED_BLOCKS = 512; // blocks of the FP64 partial-sum reductions
 
 // Geometry of the cluster (column) decomposition used by the neighbour list.
+// Triclinic cells: lattice vectors a = (L0, 0, 0), b = (txy, L1, 0),
+// c = (txz, tyz, L2). Derived coefficients (host, no contraction):
+// ryz = tyz/L2, cxy = txy/L1, cxz = (txz - tyz*cxy)/L2, so that the fractional
+// coordinates are s2 = z/L2, s1 = (y - z*ryz)/L1, s0 = ((x - y*cxy) - z*cxz)/L0.
+struct Tric {
+    double txy, txz, tyz;
+    double ryz, cxy, cxz;
+};
+
 struct Geom {
     double L[3], invL[3];
-    int ncx, ncy;     // column grid in x, y
-    double wx, wy;    // column widths
+    int ncx, ncy;     // column grid in x, y (fractional s0, s1 when triclinic)
+    double wx, wy;    // column widths (orthorhombic)
     double rc, rlist; // cutoff and list radius
     int Rx, Ry, Rz;   // column and z-image search ranges
+    int tric;         // nonzero: triclinic cell, tilts in t
+    Tric t;
 };
+
+// Tilt factors and fractional-coordinate coefficients of the system's cell
+// (all zero for an orthorhombic box), computed without contraction.
+Tric make_tric(const pq_params& p);
+inline bool is_tric(const pq_params& p) { return p.tilt[0] != 0.0 || p.tilt[1] != 0.0 || p.tilt[2] != 0.0; }
 
 // 1-D FFT plan (mixed radix 2/3/4/5 Stockham), twiddles in a device table.
 constexpr int FFT_MAX_STAGES = 12;
@@ -206,6 +222,13 @@ struct InfTab {
     const double* T[3];
     const double* S[3];
     double scale;     // 1 / (pi V)
+    // triclinic cells: |m|^2 = |R m'|^2 (R = H^-1) is not separable; Euler
+    // factors B[d] and signed frequencies M[d] per axis, and R below the
+    // diagonal; pa2 = pi^2 / alpha^2
+    int tric = 0;
+    const double* B[3];
+    const double* M[3];
+    double r00, r10, r11, r20, r21, r22, pa2;
 };
 
 struct Ctx {
@@ -262,7 +285,7 @@ struct Ctx {
     DBuf<double> inftab;     // T and S tables (FP64)
     Fft1D fft[3];
     InfTab inf{};
-    double fft_key[9] = {};  // (K, p, alpha, box, precision) the tables above were made for
+    double fft_key[12] = {}; // (K, p, alpha, box, tilts, precision) the tables above were made for
     bool fft_key_valid = false;
 
     // --- direct Ewald ---

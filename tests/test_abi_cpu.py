@@ -31,15 +31,16 @@ def test_library_loads_and_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == _declared()
     L = P.load()
-    assert L.pq_abi_version() == P.ABI_VERSION == 3
+    assert L.pq_abi_version() == P.ABI_VERSION == 4
     assert L.pq_coulomb_constant() == 14.3996454784
 
 
 def test_params_struct_layout_matches_header():
     import paper_2503_21176_amd as P
-    # box[3], cutoff, skin, alpha (6 doubles) + grid[3], order, kmax[3], method, flags (9 int32)
-    assert ctypes.sizeof(P.Params) == 6 * 8 + 9 * 4 + 4   # padded to 8-byte alignment
-    assert P.Params.grid.offset == 48 and P.Params.flags.offset == 80
+    # box[3], cutoff, skin, alpha (6 doubles) + grid[3], order, kmax[3], method, flags (9 int32),
+    # 4 bytes of padding, tilt[3]
+    assert ctypes.sizeof(P.Params) == 6 * 8 + 9 * 4 + 4 + 3 * 8
+    assert P.Params.grid.offset == 48 and P.Params.flags.offset == 80 and P.Params.tilt.offset == 88
     assert ctypes.sizeof(P.SolveInfo) == 24
 
 
@@ -51,6 +52,13 @@ def test_make_params_validation_on_host():
     assert p.method == P.METHOD_EWALD and list(p.kmax) == [8, 8, 8]
     with pytest.raises(ValueError):
         P.make_params(20.0, 8.0, 0.35, method="p3m")
+    # triclinic: rows a, b, c of a lower triangular matrix
+    H = [[20.0, 0, 0], [3.0, 21.0, 0], [-2.0, 4.0, 22.0]]
+    p = P.make_params(H, 8.0, 0.35, grid=32, order=4)
+    assert list(p.box) == [20.0, 21.0, 22.0] and list(p.tilt) == [3.0, -2.0, 4.0]
+    assert list(P.make_params(20.0, 8.0, 0.35, grid=32).tilt) == [0.0, 0.0, 0.0]
+    with pytest.raises(ValueError):
+        P.make_params([[20.0, 1.0, 0], [0, 21.0, 0], [0, 0, 22.0]], 8.0, 0.35, grid=32)
 
 
 def test_result_and_tune_struct_layouts():

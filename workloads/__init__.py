@@ -14,6 +14,8 @@ Workloads (units: Angstrom, elementary charge, eV):
 * ``serving_stream``  512 QEQ requests with log-uniform sizes and Poisson
                       arrival times.
 * ``diff_batch``      64 independent 2000-atom systems for the gradient checks.
+* ``triclinic_random`` random charges in a triclinic cell (box = the 3x3
+                      lattice matrix), for the triclinic parity cases.
 
 The Ewald splitting parameter for the workloads that do not state one follows
 ``alpha = sqrt(-ln(2*delta)) / rc`` with delta = 5e-4 (the paper's default
@@ -33,7 +35,8 @@ ALPHA_RC9 = 0.29202898720871845  # sqrt(-ln(1e-3)) / 9
 @dataclass
 class System:
     """One periodic system: positions (N,3) float64, charges (N,) float64,
-    orthorhombic box (3,) and the run parameters of its workload."""
+    orthorhombic box (3,) or triclinic lattice matrix (3,3), and the run
+    parameters of its workload."""
     name: str
     pos: np.ndarray
     q: np.ndarray
@@ -229,6 +232,27 @@ def diff_batch(n_sys: int = 64, n: int = 2000, density: float = 0.1, seed0: int 
         out.append(System("diff", pos, q, np.array([L, L, L]),
                           dict(cutoff=9.0, alpha=ALPHA_RC9, grid=48, order=5), chi=chi, eta=eta))
     return out
+
+
+def triclinic_random(n: int, edges, tilts, seed: int, dmin: float = 1.0, neutral: bool = True) -> System:
+    """Random system in a triclinic cell whose lattice vectors are the rows of
+    H = [[L0, 0, 0], [t_xy, L1, 0], [t_xz, t_yz, L2]] (``box`` is H): uniform
+    fractional coordinates (minimum separation dmin scaled to fractional units
+    by 0.7 of the shortest edge), mapped through H, and every atom moved by a
+    random lattice vector with components in {-1, 0, 1} so that positions lie
+    outside the cell too."""
+    rng = np.random.default_rng(seed)
+    L0, L1, L2 = (float(x) for x in edges)
+    txy, txz, tyz = (float(x) for x in tilts)
+    H = np.array([[L0, 0.0, 0.0], [txy, L1, 0.0], [txz, tyz, L2]])
+    s = random_positions(n, 1.0, rng, dmin / (0.7 * min(L0, L1, L2)))
+    s = s + rng.integers(-1, 2, size=(n, 3))
+    pos = s @ H
+    q = rng.normal(0.0, 1.0, size=n)
+    if neutral:
+        q -= q.mean()
+    chi, eta = qeq_parameters(n, rng)
+    return System("triclinic", pos, q, H, {}, chi=chi, eta=eta)
 
 
 def small_random(n: int, L: float, seed: int, dmin: float = 1.0, neutral: bool = True) -> System:
