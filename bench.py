@@ -101,6 +101,65 @@ def crossover(sizes=(250, 500, 1000, 2000, 3000, 4000, 5000, 6000, 8000, 12000, 
                       "library_auto_pme_min_atoms": P.auto_pme_min_atoms()}), flush=True)
 
 
+def triclinic_bench(steps=20, warmup=3, tilts=(0.25, -0.2, 0.3)):
+    """The 300k-atom phi+F evaluation in a triclinic cell against the same
+    atoms in the cubic box: the cubic system's fractional coordinates mapped
+    through H = [[L, 0, 0], [t_xy, L, 0], [t_xz, t_yz, L]] with tilts given as
+    fractions of L (same volume and density). Rebuild time, step time
+    (production configuration, autotuned), serialised phases and the pair
+    kernel's FP32 rate. One JSON line."""
+    import torch
+
+    import paper_2503_21176_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)  # noqa: E731
+    s = W.random_ionic()
+    L = float(s.box[0])
+    H = np.array([[L, 0, 0], [tilts[0] * L, L, 0], [tilts[1] * L, tilts[2] * L, L]])
+    cells = {"cubic": (s.pos, s.box), "triclinic": ((s.pos / L) @ H, H)}
+    q = t(s.q)
+    out = {"workload": "random ionic 300k, rc 10, PME 144^3 order 6", "tilts_over_L": list(tilts)}
+    for name, (pos_np, box) in cells.items():
+        prm = P.make_params(box, 10.0, W.ALPHA_RC10, grid=144, order=6)
+        pos = t(pos_np)
+        ctx = P.Context(0)
+        ctx.set_system(pos, prm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ctx.set_system(pos, prm)
+        torch.cuda.synchronize()
+        build_ms = (time.perf_counter() - t0) * 1e3 / 3
+        ctx.autotune(q, reps=5)
+        for _ in range(warmup):
+            ctx.coulomb(q)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            ctx.coulomb(q)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ctx.set_timing(2)
+        ctx.timings()
+        for _ in range(steps):
+            ctx.coulomb(q)
+        phases, cnt = ctx.timings()
+        ctx.set_timing(0)
+        ph = {k: round(v / max(1, cnt), 4) for k, v in phases.items()}
+        npairs = ctx.neighbor_count()
+        ctx.close()
+        out[name] = {"ms_per_step": round(ms, 4), "atom_evals_per_s": s.n / (ms / 1e3),
+                     "neighbor_build_ms": round(build_ms, 3), "half_pairs": int(npairs),
+                     "serialised_phases_ms": ph,
+                     "pair_tflops": npairs * PAIR_FLOPS / (ph["pair"] / 1e3) / 1e12}
+        log(f"[triclinic] {name}: {ms:.3f} ms/step, rebuild {build_ms:.2f} ms, {npairs} half pairs, phases {ph}")
+    print(json.dumps(out), flush=True)
+
+
 def md_bench(n=3000, steps=200, dt=0.5, n_krylov=6, seed=41):
     """Shadow XL-BOMD (pq_md_run) on a random ionic system at 0.1 atoms/A^3:
     masses 16/23/35.5 amu, hardness U(20, 25) eV, 300 K start, the repulsive
@@ -219,7 +278,12 @@ def main():
                     help="time shadow XL-BOMD steps (pq_md_run) on a 3000-atom system and exit")
     ap.add_argument("--md-sweep", action="store_true",
                     help="regular BO-MD over solver tolerances against shadow MD over Krylov steps and exit")
+    ap.add_argument("--triclinic", action="store_true",
+                    help="time the 300k-atom evaluation in a triclinic cell against the cubic box and exit")
     args = ap.parse_args()
+    if args.triclinic:
+        triclinic_bench()
+        return
     if args.crossover:
         crossover()
         return

@@ -163,3 +163,23 @@ def test_md_driver_rejects_tilted_cells(P):
         ctx.md_run(gpu(s.pos), gpu(np.zeros((s.n, 3))), gpu(np.full(s.n, 20.0)), gpu(s.chi), gpu(s.eta), h, 1,
                    dt_fs=0.5, dissipation=0)
     ctx.close()
+
+
+@pytest.mark.slow
+def test_triclinic_300k_sampled(P):
+    # the 300k-atom workload's fractional coordinates in a sheared cell of the
+    # same volume, at the benchmark's parameters; 48 sampled atoms
+    s0 = W.random_ionic()
+    L = float(s0.box[0])
+    H = np.array([[L, 0, 0], [0.25 * L, L, 0], [-0.2 * L, 0.3 * L, L]])
+    s = W.System("ionic-300k-triclinic", (s0.pos / L) @ H, s0.q, H)
+    a = W.ALPHA_RC10
+    say("[tric-300k] n=300000 rc=10 grid 144 order 6, tilts (0.25, -0.2, 0.3) L (48 sampled atoms)")
+    phi, F, E = run(P, s, P.make_params(H, 10.0, a, grid=144, order=6))
+    rows = np.random.default_rng(2).choice(s.n, 48, replace=False)
+    ref = O.spme_full(s.pos, s.q, s.box, a, 10.0, 144, 6, rows=rows)
+    ephi, ef = rel2(phi[rows], ref["phi"]), rms_rel(F[rows], ref["F"])
+    say(f"[tric-300k] phi rel {ephi:.2e}  F rms rel {ef:.2e}  E_rec {E[2]:.10g} vs {ref['E_rec']:.10g}")
+    assert ephi <= TOL_PHI and ef <= TOL_F
+    assert abs(E[2] - ref["E_rec"]) <= 1e-5 * abs(ref["E_rec"])
+    assert abs(E[0] - E[1:].sum()) <= 1e-12 * abs(E[0])
