@@ -18,20 +18,6 @@ __device__ __forceinline__ double canon_wrap(double x, double L, double invL) {
     return x - m;
 }
 
-// Canonical squared distance between w_i and the image n of w_j:
-// d = (w_j - w_i) + n*L per axis, d.d = (dx*dx + dy*dy) + dz*dz, no contraction.
-__device__ __forceinline__ double canon_d2(const double* __restrict__ wi, const double* __restrict__ wj,
-                                           int n0, int n1, int n2, double L0, double L1, double L2) {
-#pragma clang fp contract(off)
-    double dx = (wj[0] - wi[0]) + (double)n0 * L0;
-    double dy = (wj[1] - wi[1]) + (double)n1 * L1;
-    double dz = (wj[2] - wi[2]) + (double)n2 * L2;
-    double a = dx * dx;
-    double b = dy * dy;
-    double c = dz * dz;
-    return (a + b) + c;
-}
-
 // Canonical wrap into the triclinic cell: the c, b and a components are
 // removed in turn by the floor of the current fractional coordinate, every
 // product and difference rounded once (with zero tilts: canon_wrap per axis).

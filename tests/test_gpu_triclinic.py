@@ -154,6 +154,15 @@ def test_zero_tilt_matrix_takes_the_orthorhombic_path(P):
         assert np.array_equal(x, y)
 
 
+def test_tilts_beyond_half_an_edge_are_rejected(P):
+    s = W.triclinic_random(64, (12.0, 12.0, 12.0), (2.0, 1.0, -2.0), seed=27)
+    ctx = P.Context(0)
+    for H in ([[12.0, 0, 0], [6.5, 12.0, 0], [0, 0, 12.0]], [[12.0, 0, 0], [0, 12.0, 0], [0, -6.1, 12.0]]):
+        with pytest.raises(P.PQError):
+            ctx.set_system(gpu(s.pos), P.make_params(H, 5.0, 0.4, grid=24, order=5))
+    ctx.close()
+
+
 def test_md_driver_rejects_tilted_cells(P):
     s = W.triclinic_random(64, (12.0, 12.0, 12.0), (2.0, 1.0, -2.0), seed=26)
     ctx = P.Context(0)
