@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
         }
     }
     const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
-    const size_t e0 = (size_t)ic * lcap, e1 = e0 + lcount[ic];
+    const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
     const int eo = lane >> 3, b = lane & 7;
     const size_t base = FILL ? (size_t)jstart[ic] * CL : 0;
     // row r of list order is stored at row (r * sinv) mod nrow
@@ -662,7 +662,7 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
     const double4 pi4 = cpos[(size_t)ic * CL + a];
     const double wi[3] = {pi4.x, pi4.y, pi4.z};
     const double rl2 = g.rlist * g.rlist;
-    const size_t e0 = (size_t)ic * lcap, e1 = e0 + lcount[ic];
+    const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
     auto pair_at = [&](size_t e, int& j, int& n0, int& n1, int& n2) -> bool {
         const int2 je = lj[e];
         const size_t slot = (size_t)je.x * CL + b;
@@ -842,31 +842,34 @@ void nbr_build(Ctx& c, const double* pos) {
     c.ztb.ensure(nzt);
     PQ_LAUNCH(k_ztab, cdiv(nzt, 256), 256, 0, s, c.ncol, nbin, bw, c.col_cl.p, c.cl_lo.p, c.cl_hi.p, c.zta.p,
               c.ztb.p);
+    // The capacity check rides on the read-back of the atom-list row count:
+    // the atom-list count pass takes at most lcap entries per cluster, so an
+    // overflowing build stays in bounds and is then repeated with the larger
+    // capacity (a context's first build, or a denser system).
+    c.jcount.ensure(ncl + 1);
+    c.jstart.ensure(ncl + 1);
     for (int pass = 0;; ++pass) {
         c.lj.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap));
+        c.jmask.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap * CL));
         PQ_LAUNCH(k_list, cdiv(ncl, 4), 256, 0, s, ncl, g, c.cl_col.p, c.zta.p, c.ztb.p, nbin, bw, c.cl_lo.p,
                   c.cl_hi.p, c.lcount.p, c.lcap, c.lj.p);
         PQ_LAUNCH(k_max_int, 1, 1024, 0, s, c.lcount.p, ncl, c.flag.p + 2);
+        // atom-level j lists for the pair kernel: count pass
+        if (c.fp64)
+            PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p,
+                      c.cl_pos.p, c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
+        else
+            PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p,
+                      c.cl_pos.p, c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
+        scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
         PQ_HIP(hipMemcpyAsync(&hv[2], c.flag.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+        PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
         PQ_HIP(hipStreamSynchronize(s));
         const int mx = hv[2];
         if (mx <= c.lcap) break;
         PQ_REQUIRE(pass == 0, PQ_ERR_BOX, "cluster-pair list overflow");
         c.lcap = mx + mx / 8 + 8;
     }
-    c.jmask.ensure(std::max<size_t>(1, (size_t)ncl * c.lcap * CL));
-    // atom-level j lists for the pair kernel
-    c.jcount.ensure(ncl + 1);
-    c.jstart.ensure(ncl + 1);
-    if (c.fp64)
-        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
-    else
-        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
-    scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
-    PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
-    PQ_HIP(hipStreamSynchronize(s));
     const int rows = hv[3];
     PQ_REQUIRE(rows >= 0, PQ_ERR_BOX, "atom list overflow");
     c.njrows = rows;
