@@ -17,6 +17,33 @@ namespace pq {
 constexpr int VB = 256;   // threads per block of the vector kernels
 
 // ---- reductions -----------------------------------------------------------
+// MK sums over the VB threads of a block, reduced together (the same tree per
+// sum as block_sum); the totals land in thread 0's v[].
+template <int MK>
+__device__ __forceinline__ void block_sum_n(double (&v)[MK], double* lds /* (VB/64) * MK */) {
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int k = 0; k < MK; ++k) v[k] += __shfl_xor(v[k], o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < MK; ++k) lds[w * MK + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < MK; ++k) {
+            double t = 0.0;
+            for (int ww = 0; ww < VB / 64; ++ww) t += lds[ww * MK + k];
+            v[k] = t;
+        }
+    }
+    __syncthreads();
+}
+constexpr int MD_K = 8;   // dot products (or columns) reduced together
+
+// Partial sums of x (mode 0), x.y (mode 1) or x/y (mode 2) per block.
 __global__ __launch_bounds__(VB) void k_part_sum(const double* __restrict__ x, const double* __restrict__ y,
                                                  int64_t n, int mode, double* __restrict__ part) {
     __shared__ double red[VB / 64];
@@ -37,17 +64,25 @@ __device__ __forceinline__ int step_of(const int* jdev, int j) { return jdev ? *
 __global__ __launch_bounds__(VB) void k_part_final(const double* __restrict__ part, int nb, int nk, double alpha,
                                                    double* __restrict__ out, const int* __restrict__ jdev,
                                                    size_t ostride) {
-    __shared__ double red[VB / 64];
+    __shared__ double red[(VB / 64) * MD_K];
     if (jdev) {
         nk = *jdev + 1;
         out += (size_t)(*jdev) * ostride;
     }
-    for (int k = 0; k < nk; ++k) {
-        double v = 0.0;
-        for (int i = threadIdx.x; i < nb; i += VB) v += part[(size_t)k * nb + i];
-        v = block_sum<VB>(v, red);
-        if (threadIdx.x == 0) out[k] = alpha * v;
-        __syncthreads();
+    for (int k0 = 0; k0 < nk; k0 += MD_K) {
+        double v[MD_K];
+#pragma unroll
+        for (int k = 0; k < MD_K; ++k) {
+            v[k] = 0.0;
+            if (k0 + k < nk)
+                for (int i = threadIdx.x; i < nb; i += VB) v[k] += part[(size_t)(k0 + k) * nb + i];
+        }
+        block_sum_n<MD_K>(v, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < MD_K; ++k)
+                if (k0 + k < nk) out[k0 + k] = alpha * v[k];
+        }
     }
 }
 
@@ -235,19 +270,29 @@ void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const do
 }
 
 // ---- Gram-Schmidt -----------------------------------------------------------
-// part[k*nb + b] = partial of V_k . w for k < nk (nk = *jdev + 1 with jdev)
+// part[k*nb + b] = partial of V_k . w for k < nk (nk = *jdev + 1 with jdev),
+// MD_K dot products per pass over w, their block sums reduced together.
 __global__ __launch_bounds__(VB) void k_mdot(int64_t n, const double* __restrict__ V, size_t ld, int nk,
                                              const int* __restrict__ jdev, const double* __restrict__ w,
                                              double* __restrict__ part) {
-    __shared__ double red[VB / 64];
+    __shared__ double red[(VB / 64) * MD_K];
     if (jdev) nk = *jdev + 1;
-    for (int k = 0; k < nk; ++k) {
-        double v = 0.0;
-        const double* Vk = V + (size_t)k * ld;
-        for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) v += Vk[i] * w[i];
-        v = block_sum<VB>(v, red);
-        if (threadIdx.x == 0) part[(size_t)k * gridDim.x + blockIdx.x] = v;
-        __syncthreads();
+    for (int k0 = 0; k0 < nk; k0 += MD_K) {
+        double v[MD_K];
+#pragma unroll
+        for (int k = 0; k < MD_K; ++k) v[k] = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+            const double wi = w[i];
+#pragma unroll
+            for (int k = 0; k < MD_K; ++k)
+                if (k0 + k < nk) v[k] += V[(size_t)(k0 + k) * ld + i] * wi;
+        }
+        block_sum_n<MD_K>(v, red);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < MD_K; ++k)
+                if (k0 + k < nk) part[(size_t)(k0 + k) * gridDim.x + blockIdx.x] = v[k];
+        }
     }
 }
 // w -= sum_k h[k] V_k, k < nk (with jdev: nk = *jdev + 1, h advanced by *jdev * hstride)
@@ -281,13 +326,16 @@ static void orthogonalize_impl(Ctx& c, int64_t n, const double* V, size_t ld, in
     const int nb = red_blocks(n);
     c.part.ensure((size_t)(nk + 1) * nb + 16);
     const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
+    // the dot products of one pass
+    auto mdot = [&](double* dst, size_t ostride) {
+        PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
+        PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, dst, jdev, ostride);
+    };
     // pass 1
-    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, hcol, jdev, hstride);
+    mdot(hcol, hstride);
     PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, hstride, hcol, w);
     // pass 2 (re-orthogonalisation)
-    PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, tmp2, jdev, (size_t)0);
+    mdot(tmp2, (size_t)0);
     PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, (size_t)0, tmp2, w);
     PQ_LAUNCH(k_hadd, 1, 64, 0, s, nk, jdev, hstride, hcol, tmp2, hcol);
 }
