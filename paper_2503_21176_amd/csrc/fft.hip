@@ -63,7 +63,19 @@ __device__ __forceinline__ C mul_i(C a) {
 // cos and sin of 2 pi j / N for the composite radices
 template <int N>
 __device__ __forceinline__ constexpr double twc(int j) {
-    if constexpr (N == 8) {
+    if constexpr (N == 6) {
+        constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+        return c[j];
+    } else if constexpr (N == 10) {
+        constexpr double c[10] = {1.0, 0.80901699437494742410, 0.30901699437494742410, -0.30901699437494742410,
+                                   -0.80901699437494742410, -1.0, -0.80901699437494742410, -0.30901699437494742410,
+                                   0.30901699437494742410, 0.80901699437494742410};
+        return c[j];
+    } else if constexpr (N == 12) {
+        constexpr double c[12] = {1.0, 0.86602540378443864676, 0.5, 0.0, -0.5, -0.86602540378443864676, -1.0,
+                                   -0.86602540378443864676, -0.5, 0.0, 0.5, 0.86602540378443864676};
+        return c[j];
+    } else if constexpr (N == 8) {
         constexpr double c[8] = {1.0, 0.70710678118654752440, 0.0, -0.70710678118654752440,
                                  -1.0, -0.70710678118654752440, 0.0, 0.70710678118654752440};
         return c[j];
@@ -72,6 +84,7 @@ __device__ __forceinline__ constexpr double twc(int j) {
                                  -0.93969262078590838405, -0.5, 0.17364817766693034885, 0.76604444311897803520};
         return c[j];
     } else {
+        static_assert(N == 16, "no twiddle table for this length");
         constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
                                   0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
                                   -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
@@ -81,7 +94,20 @@ __device__ __forceinline__ constexpr double twc(int j) {
 }
 template <int N>
 __device__ __forceinline__ constexpr double tws(int j) {
-    if constexpr (N == 8) {
+    if constexpr (N == 6) {
+        constexpr double s[6] = {0.0, 0.86602540378443864676, 0.86602540378443864676, 0.0, -0.86602540378443864676,
+                                  -0.86602540378443864676};
+        return s[j];
+    } else if constexpr (N == 10) {
+        constexpr double s[10] = {0.0, 0.58778525229247312917, 0.95105651629515357212, 0.95105651629515357212,
+                                   0.58778525229247312917, 0.0, -0.58778525229247312917, -0.95105651629515357212,
+                                   -0.95105651629515357212, -0.58778525229247312917};
+        return s[j];
+    } else if constexpr (N == 12) {
+        constexpr double s[12] = {0.0, 0.5, 0.86602540378443864676, 1.0, 0.86602540378443864676, 0.5, 0.0, -0.5,
+                                   -0.86602540378443864676, -1.0, -0.86602540378443864676, -0.5};
+        return s[j];
+    } else if constexpr (N == 8) {
         constexpr double s[8] = {0.0, 0.70710678118654752440, 1.0, 0.70710678118654752440,
                                  0.0, -0.70710678118654752440, -1.0, -0.70710678118654752440};
         return s[j];
@@ -91,6 +117,7 @@ __device__ __forceinline__ constexpr double tws(int j) {
                                  -0.98480775301220805936, -0.64278760968653932632};
         return s[j];
     } else {
+        static_assert(N == 16, "no twiddle table for this length");
         constexpr double s[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
                                   1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
                                   0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
@@ -143,6 +170,12 @@ __device__ __forceinline__ void dft(C* v) {
     using T = decltype(C::x);
     if constexpr (R == 8) {
         dft_pq<2, 4, SIGN>(v);
+    } else if constexpr (R == 6) {
+        dft_pq<2, 3, SIGN>(v);
+    } else if constexpr (R == 10) {
+        dft_pq<2, 5, SIGN>(v);
+    } else if constexpr (R == 12) {
+        dft_pq<4, 3, SIGN>(v);
     } else if constexpr (R == 9) {
         dft_pq<3, 3, SIGN>(v);
     } else if constexpr (R == 16) {
@@ -731,12 +764,22 @@ static void upload_twiddles(Ctx& c, const std::vector<double>& tw, const int* of
     }
 }
 
-// Register radices (R1 >= R2, the smallest R1) with R1 R2 = n, or 0, 0.
+// Register radices (R1 >= R2, the smallest R1) with R1 R2 = n, or 0, 0. The
+// composite radices 6, 10 and 12 are taken only for lengths with no pair of
+// the others (30, 50, 54, 60, 90, 96, 100, 120).
 static void col2_radices(int n, int& r1, int& r2) {
     static const int R[] = {2, 3, 4, 5, 8, 9, 16};
+    static const int RX[] = {2, 3, 4, 5, 6, 8, 9, 10, 12, 16};
     r1 = r2 = 0;
     for (int a : R)
         for (int b : R)
+            if (b <= a && a * b == n && (r1 == 0 || a < r1)) {
+                r1 = a;
+                r2 = b;
+            }
+    if (r1 != 0) return;
+    for (int a : RX)
+        for (int b : RX)
             if (b <= a && a * b == n && (r1 == 0 || a < r1)) {
                 r1 = a;
                 r2 = b;
@@ -865,6 +908,8 @@ static bool col2_launch(int r1, int r2, dim3 grid, hipStream_t s, const V2<T>* w
     PQ_COL2(9, 2) PQ_COL2(5, 4) PQ_COL2(8, 3) PQ_COL2(5, 5) PQ_COL2(9, 3) PQ_COL2(8, 4) PQ_COL2(9, 4)
     PQ_COL2(8, 5) PQ_COL2(9, 5) PQ_COL2(16, 3) PQ_COL2(8, 8) PQ_COL2(9, 8) PQ_COL2(16, 5) PQ_COL2(9, 9)
     PQ_COL2(16, 8) PQ_COL2(16, 9) PQ_COL2(16, 16)
+    PQ_COL2(6, 5) PQ_COL2(10, 5) PQ_COL2(9, 6) PQ_COL2(10, 6) PQ_COL2(10, 9) PQ_COL2(12, 8) PQ_COL2(10, 10)
+    PQ_COL2(12, 10)
 #undef PQ_COL2
     return false;
 }
@@ -885,6 +930,7 @@ static bool x2_launch(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn
     PQ_X2(3, 2) PQ_X2(4, 2) PQ_X2(3, 3) PQ_X2(5, 2) PQ_X2(4, 3) PQ_X2(5, 3) PQ_X2(4, 4) PQ_X2(9, 2)
     PQ_X2(5, 4) PQ_X2(8, 3) PQ_X2(5, 5) PQ_X2(9, 3) PQ_X2(8, 4) PQ_X2(9, 4) PQ_X2(8, 5) PQ_X2(9, 5)
     PQ_X2(16, 3) PQ_X2(8, 8) PQ_X2(9, 8) PQ_X2(16, 5) PQ_X2(9, 9) PQ_X2(16, 8) PQ_X2(16, 9) PQ_X2(16, 16)
+    PQ_X2(6, 5) PQ_X2(10, 5) PQ_X2(9, 6) PQ_X2(10, 6) PQ_X2(10, 9) PQ_X2(12, 8) PQ_X2(10, 10) PQ_X2(12, 10)
 #undef PQ_X2
     return false;
 }

@@ -50,10 +50,13 @@ def rms_rel(a, b):
     return float(np.sqrt(np.mean(np.sum((a - b) ** 2, 1))) / np.sqrt(np.mean(np.sum(b ** 2, 1))))
 
 
-# 20 = 5*4, 27 = 9*3, 45 = 9*5, 81 = 9*9, 48 = 16*3 (two register radices);
-# 30, 50, 60 take the Stockham passes; the last case mixes both per axis
+# Two register radices: 20 = 5*4, 27 = 9*3, 45 = 9*5, 81 = 9*9, 48 = 16*3, and
+# with the composite radices 30 = 6*5, 50 = 10*5, 54 = 9*6, 60 = 10*6, 90 = 10*9,
+# 96 = 12*8, 100 = 10*10, 120 = 12*10; 75 and 108 take the Stockham passes.
+# The mixed cases take different paths per axis.
 @pytest.mark.parametrize("grid", [(20, 20, 20), (27, 27, 27), (30, 30, 30), (45, 45, 45), (50, 50, 50),
-                                  (60, 60, 60), (81, 81, 81), (30, 48, 27)])
+                                  (54, 54, 54), (60, 60, 60), (81, 81, 81), (30, 48, 27), (90, 96, 100),
+                                  (120, 75, 108)])
 def test_fft_paths(P, grid):
     n = 400
     L = (n / 0.1) ** (1 / 3)
