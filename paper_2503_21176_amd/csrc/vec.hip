@@ -61,13 +61,15 @@ __device__ __forceinline__ int step_of(const int* jdev, int j) { return jdev ? *
 
 // out[k] = alpha * sum of part[k*nb .. k*nb+nb-1], k < nk; with jdev:
 // nk = *jdev + 1 and out advanced by *jdev * ostride
+// With acc, also acc[k] += out[k] (acc advanced by *jdev * astride with jdev).
 __global__ __launch_bounds__(VB) void k_part_final(const double* __restrict__ part, int nb, int nk, double alpha,
                                                    double* __restrict__ out, const int* __restrict__ jdev,
-                                                   size_t ostride) {
+                                                   size_t ostride, double* __restrict__ acc, size_t astride) {
     __shared__ double red[(VB / 64) * MD_K];
     if (jdev) {
         nk = *jdev + 1;
         out += (size_t)(*jdev) * ostride;
+        if (acc) acc += (size_t)(*jdev) * astride;
     }
     for (int k0 = 0; k0 < nk; k0 += MD_K) {
         double v[MD_K];
@@ -80,8 +82,12 @@ __global__ __launch_bounds__(VB) void k_part_final(const double* __restrict__ pa
         block_sum_n<MD_K>(v, red);
         if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < MD_K; ++k)
-                if (k0 + k < nk) out[k0 + k] = alpha * v[k];
+            for (int k = 0; k < MD_K; ++k) {
+                if (k0 + k >= nk) break;
+                const double r = alpha * v[k];
+                out[k0 + k] = r;
+                if (acc) acc[k0 + k] = acc[k0 + k] + r;
+            }
         }
     }
 }
@@ -92,14 +98,16 @@ void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, doubl
     const int nb = red_blocks(n);
     c.part.ensure(nb + 16);
     PQ_LAUNCH(k_part_sum, nb, VB, 0, s, x, y, n, mode, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, alpha, out, (const int*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, alpha, out, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
 }
 
 void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s) { reduce(c, x, nullptr, n, 0, 1.0, out, s); }
 void sum_vector_into(const double* x, int64_t n, double* out, double* part, hipStream_t s) {
     const int nb = red_blocks(n);
     PQ_LAUNCH(k_part_sum, nb, VB, 0, s, x, (const double*)nullptr, n, 0, part);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, part, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, part, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
 }
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s) {
     reduce(c, x, y, n, 1, 1.0, out, s);
@@ -266,7 +274,8 @@ void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const do
     const int nb = red_blocks(n);
     c.part.ensure(2 * nb + 16);
     PQ_LAUNCH(k_part_shadow, nb, VB, 0, s, n, chi, v, u, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 2, 1.0, out2, (const int*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 2, 1.0, out2, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
 }
 
 // ---- Gram-Schmidt -----------------------------------------------------------
@@ -308,17 +317,6 @@ __global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, in
         w[i] = acc;
     }
 }
-// out[k] = a[k] + b[k], k < nk (with jdev: nk = *jdev + 1, a and out advanced by *jdev * stride)
-__global__ void k_hadd(int nk, const int* __restrict__ jdev, size_t stride, const double* __restrict__ a,
-                       const double* __restrict__ b, double* __restrict__ out) {
-    if (jdev) {
-        nk = *jdev + 1;
-        a += (size_t)(*jdev) * stride;
-        out += (size_t)(*jdev) * stride;
-    }
-    for (int k = threadIdx.x; k < nk; k += blockDim.x) out[k] = a[k] + b[k];
-}
-
 // CGS2 of w against V_0..V_{nk-1}; coefficients into hcol. With jdev the
 // column is that of step *jdev: nk = *jdev + 1, hcol = h0 + *jdev * hstride.
 static void orthogonalize_impl(Ctx& c, int64_t n, const double* V, size_t ld, int nk, const int* jdev,
@@ -327,17 +325,16 @@ static void orthogonalize_impl(Ctx& c, int64_t n, const double* V, size_t ld, in
     c.part.ensure((size_t)(nk + 1) * nb + 16);
     const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
     // the dot products of one pass
-    auto mdot = [&](double* dst, size_t ostride) {
+    auto mdot = [&](double* dst, size_t ostride, double* acc, size_t astride) {
         PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
-        PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, dst, jdev, ostride);
+        PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, dst, jdev, ostride, acc, astride);
     };
     // pass 1
-    mdot(hcol, hstride);
+    mdot(hcol, hstride, (double*)nullptr, (size_t)0);
     PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, hstride, hcol, w);
-    // pass 2 (re-orthogonalisation)
-    mdot(tmp2, (size_t)0);
+    // pass 2 (re-orthogonalisation); its coefficients are also added to the column
+    mdot(tmp2, (size_t)0, hcol, hstride);
     PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, (size_t)0, tmp2, w);
-    PQ_LAUNCH(k_hadd, 1, 64, 0, s, nk, jdev, hstride, hcol, tmp2, hcol);
 }
 void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
                    hipStream_t s) {
@@ -444,7 +441,8 @@ void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const dou
     const int nb = red_blocks(n);
     c.part.ensure(nb + 16);
     PQ_LAUNCH(k_part_energy, nb, VB, 0, s, n, q, chi, u, a, phi, c.part.p);
-    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, out, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
 }
 
 // ---- device-indexed steps (graph-captured Arnoldi iterations) --------------
