@@ -92,69 +92,75 @@ __global__ void k_md_kinetic(int64_t n, const double* __restrict__ v, const doub
 
 // Repulsive stand-in for V_short: per pair (j, image) with 0 < r < rc,
 // E = A exp(-r/rho); atom i gets F_i = sum (A/rho) exp(-r/rho) (r_i - r_j')/r and
-// E_i = 1/2 sum E. Positions: the wrapped FP64 coordinates.
+// E_i = 1/2 sum E. Positions: the wrapped FP64 coordinates. One wavefront per
+// atom i, its lanes taking every 64th partner j; the lane sums are combined by
+// a fixed butterfly, and part[block] holds the block's energy.
+constexpr int MD_SHORT_WAVES = MD_TILE / 64;   // atoms per block
 __global__ __launch_bounds__(MD_TILE) void k_md_short(int n, const double* __restrict__ w, double L0, double L1,
                                                       double L2, double rc, double A, double rho,
                                                       double* __restrict__ f, double* __restrict__ part) {
-    __shared__ double sx[MD_TILE * 3];
-    __shared__ double red[MD_TILE / 64];
-    const int i = blockIdx.x * MD_TILE + threadIdx.x;
-    const bool valid = i < n;
-    const double xi = valid ? w[3 * (size_t)i] : 0.0, yi = valid ? w[3 * (size_t)i + 1] : 0.0,
-                 zi = valid ? w[3 * (size_t)i + 2] : 0.0;
+    __shared__ double red[MD_SHORT_WAVES];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * MD_SHORT_WAVES + wv;
     const double rc2 = rc * rc, inv_rho = 1.0 / rho;
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-    for (int j0 = 0; j0 < n; j0 += MD_TILE) {
-        const int jl = j0 + threadIdx.x;
-        if (jl < n) {
-            sx[3 * threadIdx.x] = w[3 * (size_t)jl];
-            sx[3 * threadIdx.x + 1] = w[3 * (size_t)jl + 1];
-            sx[3 * threadIdx.x + 2] = w[3 * (size_t)jl + 2];
+    if (i < n) {
+        const double xi = w[3 * (size_t)i], yi = w[3 * (size_t)i + 1], zi = w[3 * (size_t)i + 2];
+        for (int j = lane; j < n; j += 64) {
+            // minimum image, then every image within the cutoff
+            double d0 = w[3 * (size_t)j] - xi, d1 = w[3 * (size_t)j + 1] - yi, d2 = w[3 * (size_t)j + 2] - zi;
+            d0 -= L0 * rint(d0 / L0);
+            d1 -= L1 * rint(d1 / L1);
+            d2 -= L2 * rint(d2 / L2);
+            const int a0 = (int)ceil((-rc - d0) / L0), b0 = (int)floor((rc - d0) / L0);
+            const int a1 = (int)ceil((-rc - d1) / L1), b1 = (int)floor((rc - d1) / L1);
+            const int a2 = (int)ceil((-rc - d2) / L2), b2 = (int)floor((rc - d2) / L2);
+            for (int p = a0; p <= b0; ++p)
+                for (int q = a1; q <= b1; ++q)
+                    for (int r = a2; r <= b2; ++r) {
+                        const double ex = d0 + p * L0, ey = d1 + q * L1, ez = d2 + r * L2;
+                        const double r2 = ex * ex + ey * ey + ez * ez;
+                        if (r2 >= rc2 || r2 == 0.0) continue;
+                        const double rr = sqrt(r2);
+                        const double v = A * exp(-rr * inv_rho);
+                        const double g = v * inv_rho / rr;   // -dE/dr / r
+                        fx -= g * ex;
+                        fy -= g * ey;
+                        fz -= g * ez;
+                        e += 0.5 * v;
+                    }
         }
-        __syncthreads();
-        const int m = min(MD_TILE, n - j0);
-        if (valid)
-            for (int t = 0; t < m; ++t) {
-                // minimum image, then every image within the cutoff
-                double d0 = sx[3 * t] - xi, d1 = sx[3 * t + 1] - yi, d2 = sx[3 * t + 2] - zi;
-                d0 -= L0 * rint(d0 / L0);
-                d1 -= L1 * rint(d1 / L1);
-                d2 -= L2 * rint(d2 / L2);
-                const int a0 = (int)ceil((-rc - d0) / L0), b0 = (int)floor((rc - d0) / L0);
-                const int a1 = (int)ceil((-rc - d1) / L1), b1 = (int)floor((rc - d1) / L1);
-                const int a2 = (int)ceil((-rc - d2) / L2), b2 = (int)floor((rc - d2) / L2);
-                for (int p = a0; p <= b0; ++p)
-                    for (int q = a1; q <= b1; ++q)
-                        for (int r = a2; r <= b2; ++r) {
-                            const double ex = d0 + p * L0, ey = d1 + q * L1, ez = d2 + r * L2;
-                            const double r2 = ex * ex + ey * ey + ez * ez;
-                            if (r2 >= rc2 || r2 == 0.0) continue;
-                            const double rr = sqrt(r2);
-                            const double v = A * exp(-rr * inv_rho);
-                            const double g = v * inv_rho / rr;   // -dE/dr / r
-                            fx -= g * ex;
-                            fy -= g * ey;
-                            fz -= g * ez;
-                            e += 0.5 * v;
-                        }
-            }
-        __syncthreads();
     }
-    if (valid) {
-        f[3 * (size_t)i] += fx;
-        f[3 * (size_t)i + 1] += fy;
-        f[3 * (size_t)i + 2] += fz;
+    fx = wave_sum(fx);
+    fy = wave_sum(fy);
+    fz = wave_sum(fz);
+    e = wave_sum(e);
+    if (lane == 0) {
+        if (i < n) {
+            f[3 * (size_t)i] += fx;
+            f[3 * (size_t)i + 1] += fy;
+            f[3 * (size_t)i + 2] += fz;
+        }
+        red[wv] = e;
     }
-    e = block_sum<MD_TILE>(e, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = e;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < MD_SHORT_WAVES; ++k) t += red[k];
+        part[blockIdx.x] = t;
+    }
 }
 
 __global__ void k_md_record(const double* __restrict__ kin_part, int nk, const double* __restrict__ sr_part, int ns,
                             const double* __restrict__ e_pot, double evals, double* __restrict__ row) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // one wavefront: lane-strided partial sums, then a fixed butterfly
+    if (blockIdx.x != 0 || threadIdx.x >= 64) return;
     double ke = 0.0, es = 0.0;
-    for (int k = 0; k < nk; ++k) ke += kin_part[k];
-    for (int k = 0; k < ns; ++k) es += sr_part[k];
+    for (int k = threadIdx.x; k < nk; k += 64) ke += kin_part[k];
+    for (int k = threadIdx.x; k < ns; k += 64) es += sr_part[k];
+    ke = wave_sum(ke);
+    es = wave_sum(es);
+    if (threadIdx.x != 0) return;
     row[0] = ke;
     row[1] = e_pot[0];
     row[2] = es;
@@ -204,7 +210,7 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
     DBuf<double> f, x, qn, esh, kin, srp, hist2, rows;
     const int nb3 = (int)cdiv(3 * n, 256), nb1 = (int)cdiv(n, 256);
     const int kb = std::min<int>(256, std::max(1, nb1));
-    const int sb = (int)cdiv(n, MD_TILE);
+    const int sb = (int)cdiv(n, MD_SHORT_WAVES);
     f.ensure(3 * n);
     x.ensure(n);
     qn.ensure(n);
