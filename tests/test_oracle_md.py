@@ -81,3 +81,57 @@ def test_shadow_step_at_the_ground_state_is_regular_bo():
     assert np.allclose(Fs, F, rtol=1e-10, atol=1e-12)
     assert abs(Es - E) < 1e-10 * abs(E)
     assert np.abs(x).max() < 1e-9
+
+
+def test_shadow_force_is_minus_gradient_of_shadow_energy_at_fixed_n():
+    # Away from the ground state (n != q*) the shadow force at fixed n is
+    # -dU/dR of the shadow energy U(R, n) = E(R, q[n](R), n) (eq. qeq_energy
+    # with the linearised Coulomb term); q[n] is recomputed at every probe, so
+    # this also checks that its R-dependence drops out (the stationarity of
+    # q[n] under the charge constraint). Central differences, h = 1e-5 A.
+    s = W.small_random(12, (12 / 0.1) ** (1 / 3), seed=21)
+    rng = np.random.default_rng(5)
+    eta = rng.uniform(20.0, 25.0, s.n)
+    _, _, _, qstar = M.regular_state(s.pos, s.box, COUL, s.chi, eta, 0.0)
+    n_vec = qstar + rng.normal(0.0, 0.15, s.n)
+    n_vec -= n_vec.mean()
+
+    def energy(p):
+        return M.shadow_state(p, s.box, COUL, s.chi, eta, 0.0, n_vec, 1)[2]
+
+    F, _, _, _, q = M.shadow_state(s.pos, s.box, COUL, s.chi, eta, 0.0, n_vec, 1)
+    assert np.abs(q - n_vec).max() > 0.05          # genuinely off the ground state
+    h = 1e-5
+    fd = np.zeros((s.n, 3))
+    for i in range(s.n):
+        for d in range(3):
+            p1, p2 = s.pos.copy(), s.pos.copy()
+            p1[i, d] += h
+            p2[i, d] -= h
+            fd[i, d] = -(energy(p1) - energy(p2)) / (2 * h)
+    scale = np.abs(F).max()
+    assert np.abs(fd - F).max() < 1e-6 * scale, (np.abs(fd - F).max(), scale)
+
+
+def test_charged_shadow_md_conserves_energy_to_second_order():
+    # Charged NVE run of the full shadow loop (velocity Verlet on the shadow
+    # potential, extended-charge Verlet step with K = 5 dissipation): the
+    # total shadow energy fluctuates as dt^2, and the extended charges n stay
+    # close to q[n] (eq. Jnddot drives n towards the ground state).
+    s = W.small_random(16, (16 / 0.1) ** (1 / 3), seed=23)
+    n = s.n
+    rng = np.random.default_rng(7)
+    eta = rng.uniform(20.0, 25.0, n)
+    vel = rng.normal(0, 1e-2, (n, 3))
+    mass = np.full(n, 20.0)
+    _, _, _, q0 = M.regular_state(s.pos, s.box, COUL, s.chi, eta, 0.0)
+    hist = np.tile(q0, (M.history_length(5), 1))
+    dev = []
+    for dt, steps in ((1.0, 30), (0.5, 60)):
+        pos, _, h, e = M.md_run(s.pos, vel, mass, s.box, COUL, s.chi, eta, hist, steps, dt=dt, n_krylov=4,
+                                dissipation=5, rep_a=100.0, rep_rho=0.4)
+        dev.append(np.max(np.abs(e[:, 3] - e[0, 3])))
+        _, _, _, qs = M.regular_state(pos, s.box, COUL, s.chi, eta, 0.0)
+        assert np.abs(h[0] - qs).max() < 2e-3, np.abs(h[0] - qs).max()
+    ratio = dev[0] / dev[1]
+    assert 3.0 < ratio < 5.0, (ratio, dev)
