@@ -175,6 +175,25 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
  * Bulk arithmetic is FP32; energies and charge sums are reduced in FP64. */
 pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy);
 
+/* ---- Coulomb evaluation without device allocation ------------------------ */
+/* For callers that cannot allocate device memory during the call: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same evaluation and outputs as pq_coulomb (bitwise the same values); the
+ * FP64 reduction partials and the evaluation's device scalars live in a
+ * static device array of PQ_NOALLOC_SCRATCH_BYTES per device (held until the
+ * process ends) instead of context buffers, and the pair kernel runs on the
+ * context's stream. The call allocates and frees nothing: pq_set_system must
+ * have been called on the context (it sizes the per-atom buffers), and
+ * phase timing must be off (PQ_ERR_STATE otherwise). PQ_ERR_TOO_LARGE, with
+ * nothing launched, if the PME grid needs more than the scratch holds:
+ * (grid[0]/2 + 1) * grid[1] + 16 partial sums must fit in
+ * PQ_NOALLOC_SCRATCH_BYTES/8 - 592 doubles (grid[0] = grid[1] <= 509).
+ * Every call on one device shares that device's scratch array: calls that
+ * overlap on the same device (two contexts, two streams, two threads) race
+ * and must be ordered by the caller. */
+#define PQ_NOALLOC_SCRATCH_BYTES (1u << 20)
+pq_status pq_coulomb_noalloc(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy);
+
 /* ---- phase timing ---------------------------------------------------------- */
 /* Phases of one Coulomb evaluation, timed with HIP events recorded on the
  * context's stream around each phase's kernels (the time the device spends

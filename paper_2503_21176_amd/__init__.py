@@ -31,7 +31,7 @@ EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create"
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
-           "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history"]
+           "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history", "pq_coulomb_noalloc"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -97,6 +97,7 @@ def load() -> ctypes.CDLL:
         "pq_set_system": (i32, [vp, i64, vp, ctypes.POINTER(Params)]),
         "pq_neighbor_pairs": (i32, [vp, i64, vp, ctypes.POINTER(i64)]),
         "pq_coulomb": (i32, [vp, vp, vp, vp, vp]),
+        "pq_coulomb_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "pq_set_timing": (i32, [vp, i32]),
         "pq_timings": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "pq_qeq_solve": (i32, [vp, vp, vp, dbl, dbl, i32, i32, vp, vp, vp, vp, ctypes.POINTER(SolveInfo)]),
@@ -306,6 +307,17 @@ class Context:
         self._sync_stream()
         _check(self.lib.pq_coulomb(self.h, _ptr(q), _ptr(o_phi), _ptr(o_f), _ptr(o_e)))
         return o_phi, o_f, o_e
+
+    def coulomb_noalloc(self, q, phi, force, energy):
+        """pq_coulomb_noalloc into caller-provided outputs (each FP64 device
+        tensor or None: phi (n,), force (n, 3), energy (4,)); allocates nothing."""
+        q = self._vec(q, self.n, "q")
+        for t, shape, name in ((phi, (self.n,), "phi"), (force, (self.n, 3), "force"), (energy, (4,), "energy")):
+            if t is not None and not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                                      and t.is_contiguous() and tuple(t.shape) == shape and t.device == self.device):
+                raise ValueError(f"{name} must be a contiguous FP64 tensor of shape {shape} on {self.device}")
+        self._sync_stream()
+        _check(self.lib.pq_coulomb_noalloc(self.h, _ptr(q), _ptr(phi), _ptr(force), _ptr(energy)))
 
     def qeq_solve(self, chi, eta, q_tot=0.0, tol=1e-6, max_it=500, restart=50, q0=None, force=False,
                   energy=True) -> QeqResult:

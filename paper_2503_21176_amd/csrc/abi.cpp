@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "pmeqeq.h"
@@ -21,6 +22,45 @@ std::recursive_mutex& device_mem_lock() {
 }
 
 void set_error(const std::string& m) { g_err = m; }
+
+// ---------------------------------------------------------------------------
+// Reduction scratch of pq_coulomb_noalloc: one file-scope device array (each
+// device holds its own copy for the life of the process). Layout in doubles:
+// [0, 64) device scalars, [64, 64 + RED_BLOCKS + 16) total-charge partials,
+// the rest block partials. Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): pq_create
+// resolves each device's copy with hipGetSymbolAddress, once per device, and
+// the kernels receive that address.
+// ---------------------------------------------------------------------------
+constexpr size_t SCRATCH_DOUBLES = PQ_NOALLOC_SCRATCH_BYTES / sizeof(double);
+constexpr size_t SCRATCH_QPART = 64;
+constexpr size_t SCRATCH_PART = SCRATCH_QPART + RED_BLOCKS + 16;
+static_assert(SCRATCH_PART + 4096 < SCRATCH_DOUBLES, "scratch too small");
+
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+bool g_scratch_done[MAX_DEVICES] = {};
+
+// With `device` current: resolves this device's copy of the scratch array
+// (first call per device); returns it, or nullptr if the lookup failed.
+double* scratch_for_device(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_done[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p) {
+            g_scratch_ptr[device] = static_cast<double*>(p);
+        } else {
+            (void)hipGetLastError();
+            g_scratch_ptr[device] = nullptr;
+        }
+        g_scratch_done[device] = true;
+    }
+    return g_scratch_ptr[device];
+}
 
 Ctx::~Ctx() {
     std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
@@ -148,14 +188,23 @@ void ensure_eval(Ctx& c) {
     c.phi_k.ensure(n * rsz(c));
     c.f_r.ensure(n * 4 * rsz(c));
     c.f_k.ensure(n * 4 * rsz(c));
-    c.scal.ensure(64);
-    // reduction partials: sized once for every reduction the solvers issue and
-    // the PME energy partials (one per spectral column), so nothing grows while
-    // an evaluation is being recorded into a graph
+}
+
+// Reduction partials and device scalars of the evaluations and solvers: sized
+// once for every reduction the solvers issue and the PME energy partials (one
+// per spectral column), so nothing grows while an evaluation is being
+// recorded into a graph. Allocated by the first evaluation or solve, not by
+// pq_set_system (pq_coulomb_noalloc never needs them).
+size_t red_part_need(const Ctx& c) {
     size_t need = (size_t)RED_BLOCKS * 520 + 4096;
     if (c.prm.method == PQ_METHOD_PME)
         need = std::max(need, (size_t)(c.prm.grid[0] / 2 + 1) * (size_t)c.prm.grid[1] + 16);
-    c.part.ensure(need);
+    return need;
+}
+
+void ensure_red(Ctx& c) {
+    c.scal.ensure(64);
+    c.part.ensure(red_part_need(c));
     c.qpart.ensure((size_t)RED_BLOCKS + 16);
 }
 
@@ -197,6 +246,15 @@ void ensure_side(Ctx& c) {
 void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s) {
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     ensure_eval(c);
+    ensure_red(c);
+    c.ews.part = c.part.p;
+    c.ews.part_n = c.part.n;
+    c.ews.qpart = c.qpart.p;
+    c.ews.scal = c.scal.p;
+    coulomb_eval_ws(c, q, phi, force, energy, s);
+}
+
+void coulomb_eval_ws(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s) {
     const bool fo = force != nullptr;
     c.want_energy = energy != nullptr;
     PhaseEvents E(c, s);
@@ -222,7 +280,7 @@ void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* e
         E.end(PQ_PHASE_PAIR, ps);
         // the total charge (background term) is only needed by the final
         // combine: summed after the pair kernel, off the reciprocal-space chain
-        sum_vector_into(q, c.n, c.scal.p + 0, c.qpart.p, ps);
+        sum_vector_into(q, c.n, c.ews.scal + 0, c.ews.qpart, ps);
         if (ps != s) ev_record(c.ev_join, ps);
     };
     if (c.prm.method == PQ_METHOD_PME) {
@@ -294,6 +352,9 @@ pq_status pq_create(pq_ctx** out, int device, void* stream) {
     PQ_HIP(hipGetDeviceCount(&ndev));
     PQ_REQUIRE(device >= 0 && device < ndev, PQ_ERR_INVALID, "no such HIP device");
     PQ_HIP(hipSetDevice(device));
+    // this device's copy of the no-allocation scratch (pq_coulomb_noalloc
+    // reports a failed lookup)
+    (void)scratch_for_device(device);
     Ctx* c = new Ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
@@ -491,6 +552,54 @@ pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, d
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
     PQ_HIP(hipSetDevice(c.device));
     coulomb_eval(c, q, phi, force, energy, c.stream);
+    return PQ_OK;
+    PQ_API_END
+}
+
+pq_status pq_coulomb_noalloc(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_REQUIRE(!c.timing, PQ_ERR_STATE, "phase timing must be off (it creates events)");
+    PQ_HIP(hipSetDevice(c.device));
+    double* base = scratch_for_device(c.device);
+    PQ_REQUIRE(base != nullptr, PQ_ERR_STATE, "the scratch array of this device could not be resolved");
+    // the per-atom buffers that pq_set_system sized
+    const size_t n = (size_t)c.n;
+    PQ_REQUIRE(c.phi_r.n >= n * rsz(c) && c.phi_k.n >= n * rsz(c) && c.f_r.n >= n * 4 * rsz(c) &&
+                   c.f_k.n >= n * 4 * rsz(c),
+               PQ_ERR_STATE, "per-atom buffers not sized");
+    const size_t part_n = SCRATCH_DOUBLES - SCRATCH_PART;
+    // partials: energy assembly (3 per reduction block), and one per spectral
+    // column (PME) or per k-vector tile (direct Ewald)
+    const size_t need = std::max<size_t>(3 * RED_BLOCKS + 16,
+                                         c.prm.method == PQ_METHOD_PME
+                                             ? (size_t)(c.prm.grid[0] / 2 + 1) * (size_t)c.prm.grid[1] + 16
+                                             : (size_t)(c.nk + 255) / 256 + 16);
+    if (need > part_n) {
+        set_error("PME grid needs " + std::to_string(need) + " partial sums; the no-allocation scratch holds " +
+                  std::to_string(part_n) + " ((grid[0]/2 + 1) * grid[1] + 16 must not exceed it)");
+        return PQ_ERR_TOO_LARGE;
+    }
+    // every scratch word the evaluation reads is written by it first (the
+    // scalars and partials are assigned, not accumulated), so nothing is
+    // cleared; the pair kernel runs on the context's stream (no second stream)
+    const bool serial = c.serial;
+    c.serial = true;
+    c.ews.part = base + SCRATCH_PART;
+    c.ews.part_n = part_n;
+    c.ews.qpart = base + SCRATCH_QPART;
+    c.ews.scal = base;
+    try {
+        coulomb_eval_ws(c, q, phi, force, energy, c.stream);
+    } catch (...) {
+        c.serial = serial;
+        c.ews = Ctx::EvalWs{};
+        throw;
+    }
+    c.serial = serial;
+    c.ews = Ctx::EvalWs{};
     return PQ_OK;
     PQ_API_END
 }

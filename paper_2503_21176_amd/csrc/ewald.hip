@@ -273,16 +273,16 @@ static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
             const size_t fb = (size_t)n * sizeof(V4<T>);
             PQ_LAUNCH(k_zero_bytes, std::max(1u, std::min(cdiv(fb, 256), 4096u)), 256, 0, s, c.f_k.p, fb);
         }
-        PQ_LAUNCH(k_zero_bytes, 1, 64, 0, s, reinterpret_cast<unsigned char*>(c.scal.p + 1), sizeof(double));
+        PQ_LAUNCH(k_zero_bytes, 1, 64, 0, s, reinterpret_cast<unsigned char*>(c.ews.scal + 1), sizeof(double));
         return;
     }
     const int nb = cdiv(c.nk, EW_TILE);
-    PQ_REQUIRE(c.part.n >= (size_t)nb + 16 && c.spart.n >= (size_t)c.ew_nch * c.nk &&
+    PQ_REQUIRE(c.ews.part_n >= (size_t)nb + 16 && c.spart.n >= (size_t)c.ew_nch * c.nk &&
                    c.gpart.n >= (size_t)c.ew_nkch * n,
                PQ_ERR_STATE, "direct-Ewald workspaces not sized");
     PQ_LAUNCH(k_sfac<T>, dim3(nb, c.ew_nch), EW_TILE, 0, s, n, c.nk, c.ew_cs, c.kn.p, c.w64.p, fr, q, c.spart.p);
-    PQ_LAUNCH(k_sfac_sum, nb, EW_TILE, 0, s, c.nk, c.ew_nch, c.kc.p, c.spart.p, c.sfac.p, c.part.p);
-    PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.part.p, nb, c.scal.p + 1);
+    PQ_LAUNCH(k_sfac_sum, nb, EW_TILE, 0, s, c.nk, c.ew_nch, c.kc.p, c.spart.p, c.sfac.p, c.ews.part);
+    PQ_LAUNCH(k_sum_part_e, 1, 256, 0, s, c.ews.part, nb, c.ews.scal + 1);
     if (n == 0) return;
     const dim3 g(cdiv(n, EW_TILE), c.ew_nkch);
     if (force) {
@@ -296,7 +296,7 @@ static void ewald_eval_t(Ctx& c, const double* q, bool force, hipStream_t s) {
     }
 }
 
-// phi, f (original order, without KE) into c.phi_k, c.f_k; E_rec (without KE) into c.scal[1]
+// phi, f (original order, without KE) into c.phi_k, c.f_k; E_rec (without KE) into c.ews.scal[1]
 void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s) {
     if (c.fp64)
         ewald_eval_t<double>(c, q, force, s);

@@ -972,12 +972,12 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     // z forward + convolution + z inverse: sequences over (y, mx), elements stride X*K1
     const int tz = col_tile(K2, esz, c.fft_budget);
     // one energy partial per spectral column (mx, my); sized by set_system
-    PQ_REQUIRE(c.part.n >= (size_t)X * K1 + 16, PQ_ERR_STATE, "energy partials not sized");
-    double* ep = c.want_energy ? c.part.p : nullptr;
+    PQ_REQUIRE(c.ews.part_n >= (size_t)X * K1 + 16, PQ_ERR_STATE, "energy partials not sized");
+    double* ep = c.want_energy ? c.ews.part : nullptr;
     if (!col2_launch<-1, true, T>(z1, z2, dim3(cdiv(X, CT), K1), s, wn2, X, (size_t)X * K1, (size_t)X, spec, cv, ep))
         PQ_LAUNCH((k_fft_col<-1, true, T>), dim3(cdiv(X, tz), K1), 256, (2 * K2 * tz + pz.ntw) * esz, s, pz, tw2, X,
                   tz, (size_t)X * K1, (size_t)X, spec, cv, ep);
-    if (c.want_energy) PQ_LAUNCH(k_sum_part, 1, 1024, 0, s, c.part.p, X * K1, c.scal.p + 1);
+    if (c.want_energy) PQ_LAUNCH(k_sum_part, 1, 1024, 0, s, c.ews.part, X * K1, c.ews.scal + 1);
     // y inverse
     if (!col2_launch<1, false, T>(y1, y2, dim3(cdiv(X, CT), K2), s, wn1, X, (size_t)X, (size_t)X * K1, spec, cv,
                                   (double*)nullptr))
@@ -989,7 +989,7 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
                   grid);
 }
 
-// grid (real, Q) -> grid (real, psi = conv(Q)); E_rec (without KE) into c.scal[1]
+// grid (real, Q) -> grid (real, psi = conv(Q)); E_rec (without KE) into c.ews.scal[1]
 // when c.want_energy
 void fft_convolve(Ctx& c, hipStream_t s) {
     if (c.fp64)

@@ -37,7 +37,7 @@ struct Work {
         c.kw.ensure(ld * W_N);
         c.kv.ensure(ld * (size_t)(m + 1));
         c.kh.ensure(gs_size(m) + 8);
-        c.scal.ensure(64);
+        ensure_red(c);
         V = c.kv.p;
         st = c.kh.p;
     }

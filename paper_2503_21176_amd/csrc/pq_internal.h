@@ -305,6 +305,17 @@ struct Ctx {
     DBuf<double> qpart;      // partials of the total-charge sum (on the pair kernel's stream)
     DBuf<double> scal;       // small device scalars
     double* pinned = nullptr;// pinned host scalars
+    // Reduction workspace of the evaluation in progress: block partials
+    // (part_n doubles), the partials of the total-charge sum and the
+    // evaluation's device scalars (0: total charge, 1: reciprocal energy
+    // without KE). coulomb_eval points it at part / qpart / scal above;
+    // pq_coulomb_noalloc points it into the library's static scratch array.
+    struct EvalWs {
+        double* part = nullptr;
+        size_t part_n = 0;
+        double* qpart = nullptr;
+        double* scal = nullptr;
+    } ews;
 
     // --- tuned launch shapes (pq_autotune) ---
     bool want_energy = true; // the current evaluation reports energies (E_rec reduction)
@@ -371,7 +382,7 @@ void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s
               const std::function<void()>& at_fork = {});
 // fft.hip
 void fft_setup(Ctx& c);
-void fft_convolve(Ctx& c, hipStream_t s);   // grid -> psi in place; energy partials into c.part
+void fft_convolve(Ctx& c, hipStream_t s);   // grid -> psi in place; energy partials into c.ews.part
 // ewald.hip
 void ewald_setup(Ctx& c);
 void ewald_eval(Ctx& c, const double* q, bool force, hipStream_t s);   // into c.phi_k, c.f_k
@@ -380,12 +391,17 @@ void sum_vector(Ctx& c, const double* x, int64_t n, double* out, hipStream_t s);
 // the same with a caller-provided partial buffer (>= RED_BLOCKS + 16 doubles)
 void sum_vector_into(const double* x, int64_t n, double* out, double* part, hipStream_t s);
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s);
-// after the total charge is in c.scal[0]
+// after the total charge is in c.ews.scal[0]
 void combine(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s);
 
 // high-level evaluation used by the ABI and the Krylov solvers (abi.cpp)
 void ensure_side(Ctx& c);   // creates the pair kernel's stream and fork/join events
+void ensure_red(Ctx& c);    // reduction partials and device scalars (part, qpart, scal)
 void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy,
                   hipStream_t s);
+// the same on the reduction workspace c.ews as it stands (allocates nothing
+// once pq_set_system has sized the per-atom buffers)
+void coulomb_eval_ws(Ctx& c, const double* q, double* phi, double* force, double* energy,
+                     hipStream_t s);
 
 }  // namespace pq

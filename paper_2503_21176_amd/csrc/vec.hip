@@ -173,19 +173,19 @@ __global__ void k_energy_final(const double* __restrict__ part, int nb, const do
 void combine(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s) {
     const int64_t n = c.n;
     const int nb = red_blocks(n);
-    c.part.ensure(3 * nb + 16);
+    PQ_REQUIRE(c.ews.part_n >= (size_t)(3 * nb + 16), PQ_ERR_STATE, "energy partials not sized");
     const double a = c.prm.alpha;
     const double V = c.prm.box[0] * c.prm.box[1] * c.prm.box[2];
     const double cself = -2.0 * a / std::sqrt(PI);
     const double cbg = -PI / (V * a * a);
     if (c.fp64)
-        PQ_LAUNCH(k_combine<double>, nb, VB, 0, s, n, q, c.scal.p + 0, as<double>(c.phi_r), as<double4>(c.f_r),
-                  as<double>(c.phi_k), as<double4>(c.f_k), cself, cbg, phi, force, c.part.p);
+        PQ_LAUNCH(k_combine<double>, nb, VB, 0, s, n, q, c.ews.scal + 0, as<double>(c.phi_r), as<double4>(c.f_r),
+                  as<double>(c.phi_k), as<double4>(c.f_k), cself, cbg, phi, force, c.ews.part);
     else
-        PQ_LAUNCH(k_combine<float>, nb, VB, 0, s, n, q, c.scal.p + 0, as<float>(c.phi_r), as<float4>(c.f_r),
+        PQ_LAUNCH(k_combine<float>, nb, VB, 0, s, n, q, c.ews.scal + 0, as<float>(c.phi_r), as<float4>(c.f_r),
                   as<float>(c.phi_k),
-                  as<float4>(c.f_k), cself, cbg, phi, force, c.part.p);
-    if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.part.p, nb, c.scal.p + 1, energy);
+                  as<float4>(c.f_k), cself, cbg, phi, force, c.ews.part);
+    if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.ews.part, nb, c.ews.scal + 1, energy);
 }
 
 // ---- elementwise kernels ----------------------------------------------------
