@@ -259,6 +259,44 @@ def md_sweep(n=300, steps=1000, dt=0.5, seed=51):
     ctx.close()
 
 
+def krylov_study():
+    """Operator products that each Krylov method needs to reach the serving
+    tolerance (relative residual 1e-5) on requests of the serving stream,
+    against the atom count: restarted GMRES(50), full GMRES (restart = the
+    product budget) and preconditioned MINRES, at the stream's own hardness
+    U(5, 10) eV (indefinite C) and shifted by +15 eV (positive definite C)."""
+    import torch
+
+    import paper_2503_21176_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)  # noqa: E731
+    sizes = (64, 128, 256, 512, 1024, 2048, 4000)
+    ctx = P.Context(0)
+    for k, n in enumerate(sizes):
+        r = W.serving_request(n, 90_000 + k)
+        prm = P.make_params(r.box, r.params["cutoff"], r.params["alpha"], grid=r.params["grid"],
+                            order=r.params["order"])
+        ctx.set_system(t(r.pos), prm)
+        for shift in (0.0, 15.0):
+            eta = t(r.eta + shift)
+            budget = min(3 * n + 100, 12000)
+            for name, solver, restart in (("gmres50", "gmres", 50), ("gmres_full", "gmres", min(budget, 4096)),
+                                          ("minres", "minres", 1)):
+                ctx.set_solver(solver)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = ctx.qeq_solve(t(r.chi), eta, tol=1e-5, max_it=budget, restart=restart, q0=t(r.q),
+                                    energy=False)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                print(json.dumps({"krylov": name, "n": n, "grid": r.params["grid"], "hardness_shift_eV": shift,
+                                  "budget": budget, "converged": res.status == 0, "products": res.iterations,
+                                  "rel_residual": res.rel_residual, "ms": round(ms, 2)}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,7 +318,13 @@ def main():
                     help="regular BO-MD over solver tolerances against shadow MD over Krylov steps and exit")
     ap.add_argument("--triclinic", action="store_true",
                     help="time the 300k-atom evaluation in a triclinic cell against the cubic box and exit")
+    ap.add_argument("--krylov-study", action="store_true",
+                    help="products to tol 1e-5 against system size on serving-stream requests (GMRES(50), "
+                         "full GMRES, MINRES; stated and +15 eV hardness) and exit")
     args = ap.parse_args()
+    if args.krylov_study:
+        krylov_study()
+        return
     if args.triclinic:
         triclinic_bench()
         return

@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define PQ_ABI_VERSION 4
+#define PQ_ABI_VERSION 5
 
 typedef enum pq_status {
     PQ_OK = 0,
@@ -220,24 +220,45 @@ pq_status pq_set_timing(pq_ctx* ctx, int on);
 pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count);
 
 /* ---- charge equilibration ----------------------------------------------- */
+/* Krylov method of a context's QEQ solves (pq_qeq_solve, pq_qeq_vjp and the
+ * regular mode of pq_md_run); the paper solves the system with GMRES, CG "or
+ * related approaches" (Section "Regular Born-Oppenheimer MD for a Charge
+ * Equilibration Model"), and C is indefinite when pairs closer than
+ * KE/sqrt(u_i u_j) exist, which rules out CG:
+ *   PQ_SOLVER_GMRES   restarted GMRES(restart), Jacobi diag(u, 1) on the right
+ *                     (the default);
+ *   PQ_SOLVER_MINRES  preconditioned MINRES on the symmetric bordered matrix
+ *                     with the SPD preconditioner diag(u, 1) (Paige and
+ *                     Saunders): short recurrences, O(n) memory, no restart
+ *                     length.
+ * vjp_restart (1..PQ_MAX_RESTART) is the GMRES restart length of the adjoint
+ * solve in pq_qeq_vjp (default 50). */
+enum { PQ_SOLVER_GMRES = 0, PQ_SOLVER_MINRES = 1 };
+#define PQ_MAX_RESTART 4096
+pq_status pq_set_solver(pq_ctx* ctx, int32_t solver, int32_t vjp_restart);
+
 /* Regular QEQ (Section "Regular Born-Oppenheimer MD for a Charge
  * Equilibration Model"): minimise E(q) = sum q chi + 1/2 sum u q^2 + E_Coul(q)
  * subject to sum q = q_tot, i.e. solve the bordered system of eq. linear_qeq
  *   [[C, 1], [1^T, 0]] [q; lambda] = [-chi; q_tot],  C v = u o v + phi[v]
- * matrix-free (the paper's Cv identity) by restarted GMRES(restart) with the
- * Jacobi preconditioner diag(u, 1) applied on the right, FP64 Krylov vectors
- * and FP64 orthogonalisation, each product one FP32-bulk Coulomb evaluation.
- * Stops when the true relative residual ||b - M z||/||b|| <= tol or after
- * max_it products (PQ_WARN_NOT_CONVERGED, last iterate returned).
+ * matrix-free (the paper's Cv identity) by the context's Krylov method
+ * (pq_set_solver): restarted GMRES(restart) (1 <= restart <= PQ_MAX_RESTART;
+ * restart >= max_it is full GMRES) with the Jacobi preconditioner diag(u, 1)
+ * applied on the right, or preconditioned MINRES (restart ignored); FP64
+ * Krylov vectors and FP64 orthogonalisation, each product one FP32-bulk
+ * Coulomb evaluation. Stops when the true relative residual
+ * ||b - M z||/||b|| <= tol or after max_it products (PQ_WARN_NOT_CONVERGED,
+ * last iterate returned; info->rel_residual holds its true residual).
  *   chi, eta (= u): device n FP64; q0: device n FP64 start vector or NULL (0);
  *   q: device n FP64 output; force: device n*3 FP64 output F = -dE/dR at the
  *   solution, or NULL; energy: device FP64[1] output E(q), or NULL;
  *   info: host, may be NULL. Host-synchronising (convergence checks).
- * Each Arnoldi step (operator product, orthogonalisation, Givens update) is
- * one launch of a HIP graph that the context builds at its first solve of a
- * system and reuses across restarts and calls; the host reads the residual
- * estimate of step j - 1 while step j runs, so a solve may execute one
- * product beyond the step it converges at (counted in info->iterations). */
+ * Each solver step (operator product, then orthogonalisation and Givens
+ * update, or the MINRES recurrences) is one launch of a HIP graph that the
+ * context builds at its first solve of a system and reuses across restarts
+ * and calls; the host reads the residual estimate of step j - 1 while step j
+ * runs, so a solve may execute one product beyond the step it converges at
+ * (counted in info->iterations). */
 pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot,
                        double tol, int max_it, int restart, const double* q0,
                        double* q, double* force, double* energy, pq_solve_info* info);
@@ -259,7 +280,8 @@ pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, doub
 
 /* Vector-Jacobian product through the regular QEQ solution q*(R, chi, u)
  * (training through the solve, Section "Validation and Performance"):
- * adjoint solve [[C,1],[1^T,0]] [a; mu] = [gbar; 0] (same GMRES, same tol),
+ * adjoint solve [[C,1],[1^T,0]] [a; mu] = [gbar; 0] (the context's Krylov
+ * method, GMRES with the restart length set by pq_set_solver, to tol),
  * then dL/dchi = -a, dL/du_i = -a_i q*_i, dL/dR = F[a + q*] - F[a] - F[q*].
  * With gbar == NULL the upstream is the QEQ energy itself and the envelope
  * theorem gives dE/dR = -F[q*], dE/dchi = q*, dE/du = q*^2/2 (no solve).
@@ -380,6 +402,8 @@ typedef struct pq_request {
     double tol;
     int32_t max_it;
     int32_t restart;
+    int32_t solver;           /* PQ_SOLVER_GMRES or PQ_SOLVER_MINRES */
+    int32_t reserved;         /* 0 */
     pq_params params;
 } pq_request;
 

@@ -18,7 +18,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 
-ABI_VERSION = 4
+ABI_VERSION = 5
 PQ_OK = 0
 FLAG_FP64 = 1
 PQ_WARN_NOT_CONVERGED = 1
@@ -26,12 +26,14 @@ STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_
           -3: "PQ_ERR_CAPACITY", -4: "PQ_ERR_NOMEM", -5: "PQ_ERR_HIP", -6: "PQ_ERR_TOO_LARGE",
           -7: "PQ_ERR_NAN", -8: "PQ_ERR_STATE", -9: "PQ_ERR_TIMEOUT"}
 METHOD_PME, METHOD_EWALD, METHOD_AUTO = 0, 1, 2
+SOLVERS = {"gmres": 0, "minres": 1}
 
 EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create", "pq_set_stream",
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
-           "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history", "pq_coulomb_noalloc"]
+           "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history", "pq_coulomb_noalloc",
+           "pq_set_solver"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -66,7 +68,7 @@ class Request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("pos", ctypes.c_void_p), ("chi", ctypes.c_void_p),
                 ("eta", ctypes.c_void_p), ("q0", ctypes.c_void_p), ("q_tot", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_it", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("params", Params)]
+                ("solver", ctypes.c_int32), ("reserved", ctypes.c_int32), ("params", Params)]
 
 
 class Result(ctypes.Structure):
@@ -98,6 +100,7 @@ def load() -> ctypes.CDLL:
         "pq_neighbor_pairs": (i32, [vp, i64, vp, ctypes.POINTER(i64)]),
         "pq_coulomb": (i32, [vp, vp, vp, vp, vp]),
         "pq_coulomb_noalloc": (i32, [vp, vp, vp, vp, vp]),
+        "pq_set_solver": (i32, [vp, i32, i32]),
         "pq_set_timing": (i32, [vp, i32]),
         "pq_timings": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "pq_qeq_solve": (i32, [vp, vp, vp, dbl, dbl, i32, i32, vp, vp, vp, vp, ctypes.POINTER(SolveInfo)]),
@@ -319,6 +322,12 @@ class Context:
         self._sync_stream()
         _check(self.lib.pq_coulomb_noalloc(self.h, _ptr(q), _ptr(phi), _ptr(force), _ptr(energy)))
 
+    def set_solver(self, solver="gmres", vjp_restart=50):
+        """Krylov method of this context's QEQ solves: "gmres" (restarted,
+        right Jacobi) or "minres" (preconditioned, short recurrences);
+        vjp_restart is the GMRES restart length of the adjoint solve."""
+        _check(self.lib.pq_set_solver(self.h, SOLVERS[solver], int(vjp_restart)))
+
     def qeq_solve(self, chi, eta, q_tot=0.0, tol=1e-6, max_it=500, restart=50, q0=None, force=False,
                   energy=True) -> QeqResult:
         chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")
@@ -370,7 +379,9 @@ class Context:
                                   _ptr(n_hist), int(steps), ctypes.byref(cfg), e.ctypes.data_as(ctypes.c_void_p)))
         return e
 
-    def qeq_vjp(self, chi, eta, q_star, gbar=None, tol=1e-8, max_it=1000):
+    def qeq_vjp(self, chi, eta, q_star, gbar=None, tol=1e-8, max_it=1000, with_status=False):
+        """(d_pos, d_chi, d_eta), plus the status of the adjoint solve
+        (PQ_WARN_NOT_CONVERGED possible with gbar) when with_status."""
         chi, eta = self._vec(chi, self.n, "chi"), self._vec(eta, self.n, "eta")
         q_star = self._vec(q_star, self.n, "q_star")
         gbar = self._vec(gbar, self.n, "gbar")
@@ -379,19 +390,42 @@ class Context:
         dchi = torch.empty(N, dtype=torch.float64, device=dev)
         deta = torch.empty(N, dtype=torch.float64, device=dev)
         self._sync_stream()
-        _check(self.lib.pq_qeq_vjp(self.h, _ptr(chi), _ptr(eta), _ptr(q_star), _ptr(gbar), float(tol),
-                                   int(max_it), _ptr(dpos), _ptr(dchi), _ptr(deta)), allow_warn=True)
-        return dpos, dchi, deta
+        st = _check(self.lib.pq_qeq_vjp(self.h, _ptr(chi), _ptr(eta), _ptr(q_star), _ptr(gbar), float(tol),
+                                        int(max_it), _ptr(dpos), _ptr(dchi), _ptr(deta)), allow_warn=True)
+        return (dpos, dchi, deta, st) if with_status else (dpos, dchi, deta)
+
+
+class NotConvergedError(PQError):
+    """A QEQ solve inside an autograd function stopped at max_it above its
+    tolerance: the energy, the charges and the gradients (which hold only at
+    the solution) would be wrong, so they are not returned."""
+
+    def __init__(self, what, iterations, rel_residual, tol):
+        RuntimeError.__init__(self, f"PQ_WARN_NOT_CONVERGED: {what} stopped after {iterations} products at relative "
+                                    f"residual {rel_residual:.3e} > tol {tol:.1e}")
+        self.code = PQ_WARN_NOT_CONVERGED
+        self.iterations, self.rel_residual = iterations, rel_residual
+
+
+def _solve_or_raise(context, chi, eta, q_tot, tol, max_it, restart, energy):
+    r = context.qeq_solve(chi.detach(), eta.detach(), q_tot=q_tot, tol=tol, max_it=max_it, restart=restart,
+                          energy=energy)
+    if r.status != PQ_OK:
+        raise NotConvergedError("QEQ solve", r.iterations, r.rel_residual, tol)
+    return r
 
 
 class QEQEnergy(torch.autograd.Function):
     """E(R, chi, u) = min_q E(R, q) on sum q = q_tot, with the hand-written
     adjoint (envelope theorem) as backward: dE/dR = -F[q*], dE/dchi = q*,
-    dE/du = q*^2/2. The context must hold the system at positions `pos`."""
+    dE/du = q*^2/2. The context must hold the system at positions `pos`.
+    Raises NotConvergedError if the solve does not reach tol within max_it
+    products (the envelope gradients hold only at the solution)."""
 
     @staticmethod
-    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8):
-        r = context.qeq_solve(chi.detach(), eta.detach(), q_tot=q_tot, tol=tol, energy=True)
+    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8, max_it: int = 500,
+                restart: int = 50):
+        r = _solve_or_raise(context, chi, eta, q_tot, tol, max_it, restart, True)
         ctx.context = context
         ctx.save_for_backward(chi.detach(), eta.detach(), r.q)
         return r.energy[0].clone()
@@ -399,25 +433,31 @@ class QEQEnergy(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         chi, eta, q = ctx.saved_tensors
-        dpos, dchi, deta = ctx.context.qeq_vjp(chi, eta, q, None)
-        return g * dpos, g * dchi, g * deta, None, None, None
+        dpos, dchi, deta, _ = ctx.context.qeq_vjp(chi, eta, q, None, with_status=True)
+        return g * dpos, g * dchi, g * deta, None, None, None, None, None
 
 
 class QEQCharges(torch.autograd.Function):
-    """q*(R, chi, u); backward solves the adjoint bordered system."""
+    """q*(R, chi, u); backward solves the adjoint bordered system. Raises
+    NotConvergedError if the solve or the adjoint solve does not reach tol
+    within max_it products."""
 
     @staticmethod
-    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8):
-        r = context.qeq_solve(chi.detach(), eta.detach(), q_tot=q_tot, tol=tol, energy=False)
-        ctx.context, ctx.tol = context, tol
+    def forward(ctx, pos, chi, eta, context: Context, q_tot: float = 0.0, tol: float = 1e-8, max_it: int = 500,
+                restart: int = 50):
+        r = _solve_or_raise(context, chi, eta, q_tot, tol, max_it, restart, False)
+        ctx.context, ctx.tol, ctx.max_it = context, tol, max_it
         ctx.save_for_backward(chi.detach(), eta.detach(), r.q)
         return r.q.clone()
 
     @staticmethod
     def backward(ctx, g):
         chi, eta, q = ctx.saved_tensors
-        dpos, dchi, deta = ctx.context.qeq_vjp(chi, eta, q, g.contiguous(), tol=ctx.tol)
-        return dpos, dchi, deta, None, None, None
+        dpos, dchi, deta, st = ctx.context.qeq_vjp(chi, eta, q, g.contiguous(), tol=ctx.tol, max_it=ctx.max_it,
+                                                   with_status=True)
+        if st != PQ_OK:
+            raise NotConvergedError("adjoint solve", -1, float("nan"), ctx.tol)
+        return dpos, dchi, deta, None, None, None, None, None
 
 
 def request_footprint(n: int, params: Params, restart: int = 50) -> float:
@@ -439,14 +479,15 @@ class Server:
         self.h = h
         self._keep = {}
 
-    def submit(self, pos, chi, eta, params: Params, q0=None, q_tot=0.0, tol=1e-5, max_it=200, restart=50) -> int:
+    def submit(self, pos, chi, eta, params: Params, q0=None, q_tot=0.0, tol=1e-5, max_it=200, restart=50,
+               solver="gmres") -> int:
         import numpy as np
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (pos, chi, eta)]
         q0a = None if q0 is None else np.ascontiguousarray(q0, dtype=np.float64)
         n = arrs[1].shape[0]
         req = Request(n, arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
                       None if q0a is None else q0a.ctypes.data, float(q_tot), float(tol), int(max_it), int(restart),
-                      params)
+                      SOLVERS[solver], 0, params)
         t = ctypes.c_uint64()
         _check(self.lib.pq_server_submit(self.h, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = n

@@ -1,5 +1,6 @@
-// Charge equilibration on the device: restarted GMRES on the bordered QEQ
-// system (eq. linear_qeq, matrix-free through the Cv identity), the shadow
+// Charge equilibration on the device: restarted GMRES or preconditioned
+// MINRES on the bordered QEQ system (eq. linear_qeq, matrix-free through the
+// Cv identity; the paper names GMRES, CG and related approaches), the shadow
 // step (eqs. diag_linear_qeq and Jnddot) and vector-Jacobian products through
 // the QEQ solve. Krylov vectors, inner products and orthogonalisation are
 // FP64 on the device; each operator product is one FP32-bulk Coulomb
@@ -23,7 +24,7 @@ namespace {
 size_t round_ld(int64_t n) { return (size_t)((n + 63) / 64 * 64); }
 
 // Work vectors of the solvers (each ld doubles).
-enum { W_B = 0, W_X, W_R, W_W, W_T, W_PHI, W_PHI2, W_D, W_VJ, W_N };
+enum { W_B = 0, W_X, W_R, W_W, W_T, W_PHI, W_PHI2, W_D, W_VJ, W_M1, W_M2, W_M3, W_M4, W_N };
 
 struct Work {
     Ctx& c;
@@ -76,11 +77,15 @@ void arnoldi_step(Work& W, const OpFn& op, int64_t nv) {
     givens_j(W.st, m, c.kj.p, W.st + gs_hist(m), s);
 }
 
-// The Arnoldi step as an instantiated HIP graph, built once per operator,
-// system and workspace by recording the step's launches (cached in the
-// context; pq_set_system invalidates it). Returns nullptr when graphs are off
-// or the build fails (the caller then launches the step's kernels directly).
-hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, const void* opkey) {
+// One solver step (an Arnoldi step, or a MINRES step) as an instantiated HIP
+// graph, built once per operator, system and workspace by recording the
+// step's launches (cached in the context; pq_set_system invalidates it).
+// Returns nullptr when graphs are off or the build fails (the caller then
+// launches the step's kernels directly). A cached graph of another key is
+// destroyed only after the context's stream has drained, so no launch of it
+// can still be in flight.
+hipGraphExec_t step_graph(Work& W, const std::function<void()>& body, int64_t nv, uintptr_t kind,
+                          const void* opkey) {
     Ctx& c = W.c;
     if (!c.graphs || c.timing) return nullptr;
     std::vector<uintptr_t> key = {kind, (uintptr_t)opkey, (uintptr_t)nv, (uintptr_t)W.m, (uintptr_t)W.ld,
@@ -89,6 +94,7 @@ hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, c
                                   (uintptr_t)c.fft_budget, (uintptr_t)c.fork_at};
     if (c.kgraph && key == c.kgraph_key) return c.kgraph;
     if (c.kgraph) {
+        PQ_HIP(hipStreamSynchronize(c.stream));
         (void)hipGraphExecDestroy(c.kgraph);
         c.kgraph = nullptr;
         c.kgraph_key.clear();
@@ -100,7 +106,7 @@ hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, c
     if (ok) {
         graph_rec() = &rec;
         try {
-            arnoldi_step(W, op, nv);
+            body();
         } catch (...) {
             ok = false;
         }
@@ -118,6 +124,21 @@ hipGraphExec_t step_graph(Work& W, const OpFn& op, int64_t nv, uintptr_t kind, c
     return ex;
 }
 
+// Host buffer of residual estimates with room for m values.
+void ensure_pinned_hist(Ctx& c, int m) {
+    if (c.pinned_hist && c.pinned_hist_n >= m) return;
+    std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
+    if (c.pinned_hist) {
+        PQ_HIP(hipStreamSynchronize(c.stream));
+        (void)hipHostFree(c.pinned_hist);
+        c.pinned_hist = nullptr;
+        c.pinned_hist_n = 0;
+    }
+    const int cap = std::max(m, 520);
+    PQ_HIP(hipHostMalloc((void**)&c.pinned_hist, (size_t)cap * sizeof(double), hipHostMallocDefault));
+    c.pinned_hist_n = cap;
+}
+
 // GMRES(m) for A x = b with vectors of length nv, x in/out (x_zero: x = 0 on
 // entry). fixed: exactly m products from x = 0, no host synchronisation.
 // Each Arnoldi step is one graph launch; the host reads the residual estimate
@@ -133,10 +154,7 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
     GmresOut out;
     double bnorm = 1.0;
     c.kj.ensure(4);
-    if (!c.pinned_hist) {
-        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
-        PQ_HIP(hipHostMalloc((void**)&c.pinned_hist, 520 * sizeof(double), hipHostMallocDefault));
-    }
+    ensure_pinned_hist(c, m);
     for (auto& ev : c.kev)
         if (!ev) PQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     if (!fixed) {
@@ -164,7 +182,7 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
             return out;
         }
     }
-    hipGraphExec_t step = step_graph(W, op, nv, kind, opkey);
+    hipGraphExec_t step = step_graph(W, [&] { arnoldi_step(W, op, nv); }, nv, kind, opkey);
     const double* hist = W.st + gs_hist(m);
     for (;;) {
         gmres_start(W.st, m, W.sc(1), s);
@@ -180,7 +198,7 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
             out.products++;
             ++launched;
             if (fixed) continue;
-            PQ_HIP(hipMemcpyAsync(c.pinned_hist, hist, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+            PQ_HIP(hipMemcpyAsync(c.pinned_hist + j, hist + j, sizeof(double), hipMemcpyDeviceToHost, s));
             PQ_HIP(hipEventRecord(c.kev[j & 1], s));
             if (j >= 1) {
                 PQ_HIP(hipEventSynchronize(c.kev[(j - 1) & 1]));
@@ -212,6 +230,112 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
     }
 }
 
+// Preconditioned MINRES for the symmetric bordered system M z = b (n + 1
+// unknowns) with D = diag(u, 1); z in/out in x (x_zero: z = 0 on entry). One
+// step (v = y / beta, the product y = M v, the Lanczos and Givens updates and
+// the solution update) is one graph launch; the host reads the estimate of
+// step k - 1 while step k runs. The estimate phibar is the D^-1-norm of the
+// residual: a cycle ends when it falls to target * ||b||_{D^-1}, and then the
+// true relative residual ||b - M z||_2 / ||b||_2 decides; if it is still above
+// tol, a new cycle starts from z with the target lowered by their ratio.
+GmresOut minres(Work& W, const OpFn& op, const double* eta, int64_t n, const double* b, double* x, bool x_zero,
+                double tol, int max_it) {
+    Ctx& c = W.c;
+    hipStream_t s = c.stream;
+    const int64_t nv = n + 1;
+    double* r1 = W.w(W_R);
+    double* r2 = W.w(W_M1);
+    double* y = W.w(W_W);
+    double* v = W.w(W_VJ);
+    double* wa = W.w(W_M2);
+    double* wb = W.w(W_M3);
+    double* t = W.w(W_M4);
+    double* ms = W.sc(20);   // MR_N scalars
+    static_assert(16 + 20 + MR_N <= 64, "MINRES scalars exceed the device scalar block");
+    GmresOut out;
+    ensure_pinned_hist(c, 2);
+    for (auto& ev : c.kev)
+        if (!ev) PQ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    dot_vector(c, b, b, nv, W.sc(0), s);
+    const double bnorm = std::sqrt(read_scalar(c, W.sc(0), s));
+    if (bnorm == 0.0) {
+        axpby(nv, 0.0, b, 0.0, nullptr, x, s);
+        out.converged = true;
+        return out;
+    }
+    minres_start(c, n, b, eta, y, ms, s);
+    const double bnorm_d = read_scalar(c, ms + MR_BETA1, s);
+    if (x_zero) axpby(nv, 0.0, b, 0.0, nullptr, x, s);
+    auto body = [&] {
+        minres_v(nv, y, ms, v, s);
+        op(v, y);
+        minres_update(c, n, y, r1, r2, v, eta, wa, wb, x, ms, s);
+    };
+    hipGraphExec_t step = nullptr;
+    bool have_step = false;
+    double target = tol;
+    // r1 = b - M z
+    if (x_zero) {
+        axpby(nv, 1.0, b, 0.0, nullptr, r1, s);
+    } else {
+        op(x, t);
+        out.products++;
+        axpby(nv, 1.0, b, -1.0, t, r1, s);
+    }
+    dot_vector(c, r1, r1, nv, W.sc(1), s);
+    out.relres = std::sqrt(read_scalar(c, W.sc(1), s)) / bnorm;
+    if (out.relres <= tol) {
+        out.converged = true;
+        return out;
+    }
+    for (;;) {
+        if (out.products >= max_it) return out;
+        minres_start(c, n, r1, eta, y, ms, s);
+        axpby(nv, 1.0, r1, 0.0, nullptr, r2, s);
+        axpby(nv, 0.0, r1, 0.0, nullptr, wa, s);
+        axpby(nv, 0.0, r1, 0.0, nullptr, wb, s);
+        if (!have_step) {
+            step = step_graph(W, body, nv, 3, eta);
+            have_step = true;
+        }
+        const double stop = target * bnorm_d;
+        int launched = 0;
+        bool hit = false;
+        for (int k = 0;; ++k) {
+            if (out.products >= max_it) break;
+            if (step)
+                PQ_HIP(hipGraphLaunch(step, s));
+            else
+                body();
+            out.products++;
+            ++launched;
+            PQ_HIP(hipMemcpyAsync(c.pinned_hist + (k & 1), ms + MR_PHIBAR, sizeof(double), hipMemcpyDeviceToHost, s));
+            PQ_HIP(hipEventRecord(c.kev[k & 1], s));
+            if (k >= 1) {
+                PQ_HIP(hipEventSynchronize(c.kev[(k - 1) & 1]));
+                if (c.pinned_hist[(k - 1) & 1] <= stop) {
+                    hit = true;
+                    break;
+                }
+            }
+        }
+        if (!hit && launched > 0) PQ_HIP(hipEventSynchronize(c.kev[(launched - 1) & 1]));
+        // true residual (also the next cycle's start)
+        op(x, t);
+        out.products++;
+        axpby(nv, 1.0, b, -1.0, t, r1, s);
+        dot_vector(c, r1, r1, nv, W.sc(1), s);
+        out.relres = std::sqrt(read_scalar(c, W.sc(1), s)) / bnorm;
+        if (out.relres <= tol) {
+            out.converged = true;
+            return out;
+        }
+        if (out.products >= max_it) return out;
+        target *= std::max(0.01, 0.5 * tol / out.relres);
+        out.restarts++;
+    }
+}
+
 void check_finite_host(double v, const char* what) {
     PQ_REQUIRE(std::isfinite(v), PQ_ERR_INVALID, std::string(what) + " must be finite");
 }
@@ -232,8 +356,23 @@ OpFn bordered_op(Work& W, const double* eta) {
     };
 }
 
-// bordered solve for right-hand side [rhs_q; rhs_l]; the solution z = P^-1 x is
-// left as q = x_q/u in qout and lambda in *lam_dev.
+// bordered QEQ product without preconditioning (MINRES):
+//   out = [u o v_q + phi[v_q] + v_l ; sum v_q]
+OpFn plain_op(Work& W, const double* eta) {
+    return [&W, eta](const double* v, double* out) {
+        Ctx& c = W.c;
+        hipStream_t s = c.stream;
+        const int64_t n = c.n;
+        double* phi = W.w(W_PHI2);
+        coulomb_eval(c, v, phi, nullptr, nullptr, s);
+        reduce(c, v, nullptr, n, 0, 1.0, W.sc(4), s);
+        bordered_plain(n, v, eta, phi, W.sc(4), out, s);
+    };
+}
+
+// bordered solve for right-hand side [rhs_q; rhs_l] by the context's Krylov
+// method. GMRES: the solution z = P^-1 x is left as q = x_q/u in qout;
+// MINRES: z = x, q = x_q. lambda is x[n] in both.
 GmresOut bordered_solve(Work& W, const double* eta, const double* rhs_q, double rhs_l, bool negate_rhs,
                         const double* q0, double tol, int max_it, double* qout) {
     Ctx& c = W.c;
@@ -248,6 +387,15 @@ GmresOut bordered_solve(Work& W, const double* eta, const double* rhs_q, double 
         vmul(n, q0, eta, 1.0, x, s);
         set_scalar(x + n, 0.0, s);
         xz = false;
+    }
+    if (c.solver == PQ_SOLVER_MINRES) {
+        if (q0) {
+            axpby(n, 1.0, q0, 0.0, nullptr, x, s);
+            set_scalar(x + n, 0.0, s);
+        }
+        GmresOut o = minres(W, plain_op(W, eta), eta, n, b, x, !q0, tol, max_it);
+        axpby(n, 1.0, x, 0.0, nullptr, qout, s);
+        return o;
     }
     OpFn op = bordered_op(W, eta);
     GmresOut o = gmres(W, op, n + 1, b, x, xz, tol, max_it, false, 1, eta);
@@ -278,18 +426,30 @@ using namespace pq;
 
 extern "C" {
 
+pq_status pq_set_solver(pq_ctx* ctx, int32_t solver, int32_t vjp_restart) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
+    PQ_REQUIRE(solver == PQ_SOLVER_GMRES || solver == PQ_SOLVER_MINRES, PQ_ERR_INVALID, "unknown solver");
+    PQ_REQUIRE(vjp_restart >= 1 && vjp_restart <= PQ_MAX_RESTART, PQ_ERR_INVALID, "vjp_restart must be in 1..4096");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    c.solver = solver;
+    c.vjp_restart = vjp_restart;
+    return PQ_OK;
+    PQ_API_END
+}
+
 pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot, double tol, int max_it,
                        int restart, const double* q0, double* q, double* force, double* energy, pq_solve_info* info) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx && chi && eta && q, PQ_ERR_INVALID, "ctx, chi, eta and q must not be NULL");
-    PQ_REQUIRE(tol > 0.0 && max_it >= 1 && restart >= 1 && restart <= 512, PQ_ERR_INVALID,
-               "need tol > 0, max_it >= 1, 1 <= restart <= 512");
+    PQ_REQUIRE(tol > 0.0 && max_it >= 1 && restart >= 1 && restart <= PQ_MAX_RESTART, PQ_ERR_INVALID,
+               "need tol > 0, max_it >= 1, 1 <= restart <= 4096");
     check_finite_host(q_tot, "q_tot");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_HIP(hipSetDevice(c.device));
     hipStream_t s = c.stream;
-    Work W(c, restart);
+    Work W(c, c.solver == PQ_SOLVER_MINRES ? 1 : restart);
     GmresOut o = bordered_solve(W, eta, chi, q_tot, true, q0, tol, max_it, q);
     double lam = read_scalar(c, W.w(W_X) + c.n, s);
     if (force || energy) {
@@ -381,7 +541,7 @@ pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const do
         return PQ_OK;
     }
     PQ_REQUIRE(tol > 0.0 && max_it >= 1, PQ_ERR_INVALID, "need tol > 0 and max_it >= 1");
-    Work W(c, 50);
+    Work W(c, c.solver == PQ_SOLVER_MINRES ? 1 : c.vjp_restart);
     c.kf.ensure((size_t)n * 3);
     double* a = W.w(W_D);
     GmresOut o = bordered_solve(W, eta, gbar, 0.0, false, nullptr, tol, max_it, a);

@@ -350,6 +350,9 @@ struct Ctx {
     std::vector<uintptr_t> kgraph_key;
     DBuf<int> kj;                     // device step index j
     double* pinned_hist = nullptr;    // host copy of the residual estimates
+    int pinned_hist_n = 0;            // its capacity (doubles)
+    int solver = PQ_SOLVER_GMRES;     // Krylov method of the QEQ solves (pq_set_solver)
+    int vjp_restart = 50;             // GMRES restart length of the adjoint solve
     hipEvent_t kev[2] = {nullptr, nullptr};
 
     ~Ctx();

@@ -36,7 +36,7 @@ struct Req {
     std::vector<double> pos, chi, eta, q0;
     bool has_q0;
     double q_tot, tol;
-    int max_it, restart;
+    int max_it, restart, solver;
     pq_params params;
     double footprint;
     double t_submit, t_start = 0, t_done = 0;
@@ -86,7 +86,7 @@ double request_footprint(int64_t n, const pq_params& p, int restart) {
         const double nk = ((2.0 * p.kmax[0] + 1) * (2.0 * p.kmax[1] + 1) * (2.0 * p.kmax[2] + 1)) / 2.0 + 1.0;
         grid = nk * (16 + 8 + 16) + 2048.0 * 256.0 * (16 + 32);
     }
-    const double kry = ((double)n + 64) * 8.0 * (9 + restart + 1);
+    const double kry = ((double)n + 64) * 8.0 * (13 + restart + 1);
     return 1.25 * (pairs + jatoms + atoms + grid + kry) + (1 << 20);
 }
 
@@ -158,6 +158,7 @@ void run_request(pq_server* S, pq_server::Slot* sl, Req& r) {
     if (ok && r.has_q0)
         ok = hipMemcpyAsync(dq0, r.q0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) == hipSuccess;
     if (!ok) st = PQ_ERR_HIP;
+    if (st == PQ_OK) st = pq_set_solver(ctx, r.solver, 50);
     if (st == PQ_OK) st = pq_set_system(ctx, n, dpos, &r.params);
     if (st == PQ_OK)
         st = pq_qeq_solve(ctx, dchi, deta, r.q_tot, r.tol, r.max_it, r.restart, r.has_q0 ? dq0 : nullptr, dq,
@@ -288,7 +289,9 @@ pq_status pq_server_submit(pq_server* S, const pq_request* req, uint64_t* ticket
     PQ_API_BEGIN
     PQ_REQUIRE(S && req && ticket, PQ_ERR_INVALID, "server, request and ticket must not be NULL");
     PQ_REQUIRE(req->n >= 1 && req->pos && req->chi && req->eta, PQ_ERR_INVALID, "request needs n, pos, chi, eta");
-    PQ_REQUIRE(req->tol > 0 && req->max_it >= 1 && req->restart >= 1, PQ_ERR_INVALID, "bad solver settings");
+    PQ_REQUIRE(req->tol > 0 && req->max_it >= 1 && req->restart >= 1 && req->restart <= PQ_MAX_RESTART &&
+                   (req->solver == PQ_SOLVER_GMRES || req->solver == PQ_SOLVER_MINRES),
+               PQ_ERR_INVALID, "bad solver settings");
     auto r = std::make_shared<Req>();
     const int64_t n = req->n;
     r->n = n;
@@ -301,8 +304,9 @@ pq_status pq_server_submit(pq_server* S, const pq_request* req, uint64_t* ticket
     r->tol = req->tol;
     r->max_it = req->max_it;
     r->restart = req->restart;
+    r->solver = req->solver;
     r->params = req->params;
-    r->footprint = request_footprint(n, req->params, req->restart);
+    r->footprint = request_footprint(n, req->params, req->solver == PQ_SOLVER_MINRES ? 1 : req->restart);
     if (r->footprint > S->cfg.hbm_budget_bytes) {
         set_error("request footprint " + std::to_string(r->footprint) + " B exceeds the server budget");
         return PQ_ERR_TOO_LARGE;

@@ -20,6 +20,10 @@ __host__ __device__ inline size_t gs_t(int m) { return gs_y(m) + m; }
 __host__ __device__ inline size_t gs_hist(int m) { return gs_t(m) + m + 2; }   // residual estimates, m
 __host__ __device__ inline size_t gs_size(int m) { return gs_hist(m) + m + 1; }
 
+// Device scalar state of the preconditioned MINRES solver (FP64, MR_N words).
+enum { MR_BETA = 0, MR_BETA1, MR_OLDB, MR_ALFA, MR_BETA2, MR_DBAR, MR_EPS, MR_PHIBAR, MR_CS, MR_SN, MR_PHI,
+       MR_DELTA, MR_OLDEPS, MR_DENOM, MR_N };
+
 // mode 0: sum x; 1: sum x*y; 2: sum x/y. out = alpha * result (device scalar)
 void reduce(Ctx& c, const double* x, const double* y, int64_t n, int mode, double alpha, double* out, hipStream_t s);
 void axpby(int64_t n, double a, const double* x, double b, const double* y, double* z, hipStream_t s);
@@ -50,5 +54,16 @@ void normalize_j(int64_t n, const double* w, const double* nrm2, double* st, int
 void givens_j(double* st, int m, int* jdev, double* hist, hipStream_t s);
 void set_int(int* p, int v, hipStream_t s);
 void set_scalar(double* b, double v, hipStream_t s);
+// preconditioned MINRES on the bordered system (n + 1 unknowns, D = diag(u, 1)):
+// cycle start from the residual r (y = D^-1 r, beta1 = sqrt(r . y)), the
+// vector v = y / beta that the step applies the operator to, and the rest of
+// the step after y = M v (the estimate phibar lands in ms[MR_PHIBAR])
+void minres_start(Ctx& c, int64_t n, const double* r, const double* u, double* y, double* ms, hipStream_t s);
+void minres_v(int64_t nv, const double* y, const double* ms, double* v, hipStream_t s);
+void minres_update(Ctx& c, int64_t n, double* y, double* r1, double* r2, const double* v, const double* u, double* wa,
+                   double* wb, double* x, double* ms, hipStream_t s);
+// out = [u o v + phi + v_n ; *vsum] (the bordered product without preconditioning)
+void bordered_plain(int64_t n, const double* v, const double* u, const double* phi, const double* vsum, double* out,
+                    hipStream_t s);
 
 }  // namespace pq

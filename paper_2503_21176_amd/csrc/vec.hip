@@ -514,4 +514,172 @@ __global__ void k_set_scalar(double* __restrict__ b, double v) {
 }
 void set_scalar(double* b, double v, hipStream_t s) { PQ_LAUNCH(k_set_scalar, 1, 64, 0, s, b, v); }
 
+// ---- preconditioned MINRES (Paige and Saunders) -------------------------------
+// For the symmetric bordered system M z = b with the SPD preconditioner
+// D = diag(u, 1): a Lanczos recurrence in the D^-1 inner product, the QR
+// factorisation of its tridiagonal matrix by Givens rotations, and the
+// solution update by the three-term direction recurrence. The scalars live in
+// ms[MR_*] on the device, so a whole step (product included) is recordable
+// into a graph. nv = n + 1; d_i = u_i for i < n, d_n = 1.
+__device__ __forceinline__ double mr_d(const double* __restrict__ u, int64_t n, int64_t i) { return i < n ? u[i] : 1.0; }
+
+// y = r / d, partials of r . y (start of a cycle: beta1^2)
+__global__ __launch_bounds__(VB) void k_mr_prec(int64_t n, const double* __restrict__ r, const double* __restrict__ u,
+                                                double* __restrict__ y, double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    double v = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i <= n; i += (int64_t)gridDim.x * VB) {
+        const double t = r[i] / mr_d(u, n, i);
+        y[i] = t;
+        v += r[i] * t;
+    }
+    v = block_sum<VB>(v, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+__global__ void k_mr_init(double* __restrict__ ms) {
+    if (threadIdx.x != 0) return;
+    const double b = sqrt(fmax(ms[MR_BETA2], 0.0));
+    ms[MR_BETA] = b;
+    ms[MR_BETA1] = b;
+    ms[MR_OLDB] = 0.0;
+    ms[MR_DBAR] = 0.0;
+    ms[MR_EPS] = 0.0;
+    ms[MR_PHIBAR] = b;
+    ms[MR_CS] = -1.0;
+    ms[MR_SN] = 0.0;
+    ms[MR_PHI] = 0.0;
+    ms[MR_DELTA] = 0.0;
+    ms[MR_OLDEPS] = 0.0;
+    ms[MR_DENOM] = 0.0;
+}
+
+// v = y / beta
+__global__ void k_mr_v(int64_t nv, const double* __restrict__ y, const double* __restrict__ ms, double* __restrict__ v) {
+    const double b = ms[MR_BETA];
+    const double inv = b > 0.0 ? 1.0 / b : 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < nv; i += (int64_t)gridDim.x * VB) v[i] = y[i] * inv;
+}
+
+// y -= (beta / oldb) r1 (no term at the first step, oldb = 0); partials of v . y
+__global__ __launch_bounds__(VB) void k_mr_a(int64_t nv, double* __restrict__ y, const double* __restrict__ r1,
+                                             const double* __restrict__ v, const double* __restrict__ ms,
+                                             double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    const double ob = ms[MR_OLDB];
+    const double c1 = ob > 0.0 ? ms[MR_BETA] / ob : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < nv; i += (int64_t)gridDim.x * VB) {
+        const double t = y[i] - c1 * r1[i];
+        y[i] = t;
+        acc += v[i] * t;
+    }
+    acc = block_sum<VB>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// t = y - (alfa / beta) r2; r1 = r2; r2 = t; y = t / d; partials of t . y
+__global__ __launch_bounds__(VB) void k_mr_b(int64_t n, double* __restrict__ y, double* __restrict__ r1,
+                                             double* __restrict__ r2, const double* __restrict__ u,
+                                             const double* __restrict__ ms, double* __restrict__ part) {
+    __shared__ double red[VB / 64];
+    const double b = ms[MR_BETA];
+    const double c2 = b > 0.0 ? ms[MR_ALFA] / b : 0.0;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i <= n; i += (int64_t)gridDim.x * VB) {
+        const double t = y[i] - c2 * r2[i];
+        r1[i] = r2[i];
+        r2[i] = t;
+        const double z = t / mr_d(u, n, i);
+        y[i] = z;
+        acc += t * z;
+    }
+    acc = block_sum<VB>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// Givens step on the tridiagonal column (alfa, beta) and the residual
+// estimate phibar (the D^-1 norm of the residual)
+__global__ void k_mr_givens(double* __restrict__ ms) {
+    if (threadIdx.x != 0) return;
+    const double alfa = ms[MR_ALFA];
+    const double oldb = ms[MR_BETA];
+    const double beta = sqrt(fmax(ms[MR_BETA2], 0.0));
+    const double cs = ms[MR_CS], sn = ms[MR_SN], dbar = ms[MR_DBAR];
+    const double oldeps = ms[MR_EPS];
+    const double delta = cs * dbar + sn * alfa;
+    const double gbar = sn * dbar - cs * alfa;
+    const double eps = sn * beta;
+    const double dbar2 = -cs * beta;
+    const double gamma = fmax(hypot(gbar, beta), 1e-300);
+    const double c = gbar / gamma, s = beta / gamma;
+    const double phibar = ms[MR_PHIBAR];
+    ms[MR_OLDB] = oldb;
+    ms[MR_BETA] = beta;
+    ms[MR_OLDEPS] = oldeps;
+    ms[MR_DELTA] = delta;
+    ms[MR_EPS] = eps;
+    ms[MR_DBAR] = dbar2;
+    ms[MR_CS] = c;
+    ms[MR_SN] = s;
+    ms[MR_PHI] = c * phibar;
+    ms[MR_PHIBAR] = s * phibar;
+    ms[MR_DENOM] = 1.0 / gamma;
+}
+
+// wn = (v - oldeps wb - delta wa) / gamma; wb = wa; wa = wn; x += phi wn
+__global__ void k_mr_x(int64_t nv, const double* __restrict__ v, double* __restrict__ wa, double* __restrict__ wb,
+                       double* __restrict__ x, const double* __restrict__ ms) {
+    const double oe = ms[MR_OLDEPS], de = ms[MR_DELTA], dn = ms[MR_DENOM], ph = ms[MR_PHI];
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < nv; i += (int64_t)gridDim.x * VB) {
+        const double a = wa[i];
+        const double wn = (v[i] - oe * wb[i] - de * a) * dn;
+        wb[i] = a;
+        wa[i] = wn;
+        x[i] = x[i] + ph * wn;
+    }
+}
+
+static unsigned vgrid(int64_t nv) { return (unsigned)std::min<int64_t>(cdiv(nv, VB), 4096); }
+
+void minres_start(Ctx& c, int64_t n, const double* r, const double* u, double* y, double* ms, hipStream_t s) {
+    const int nb = red_blocks(n + 1);
+    c.part.ensure(nb + 16);
+    PQ_LAUNCH(k_mr_prec, nb, VB, 0, s, n, r, u, y, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, ms + MR_BETA2, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_mr_init, 1, 64, 0, s, ms);
+}
+void minres_v(int64_t nv, const double* y, const double* ms, double* v, hipStream_t s) {
+    PQ_LAUNCH(k_mr_v, vgrid(nv), VB, 0, s, nv, y, ms, v);
+}
+void minres_update(Ctx& c, int64_t n, double* y, double* r1, double* r2, const double* v, const double* u, double* wa,
+                   double* wb, double* x, double* ms, hipStream_t s) {
+    const int64_t nv = n + 1;
+    const int nb = red_blocks(nv);
+    c.part.ensure(nb + 16);
+    PQ_LAUNCH(k_mr_a, nb, VB, 0, s, nv, y, r1, v, ms, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, ms + MR_ALFA, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_mr_b, nb, VB, 0, s, n, y, r1, r2, u, ms, c.part.p);
+    PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, 1, 1.0, ms + MR_BETA2, (const int*)nullptr, (size_t)0,
+              (double*)nullptr, (size_t)0);
+    PQ_LAUNCH(k_mr_givens, 1, 64, 0, s, ms);
+    PQ_LAUNCH(k_mr_x, vgrid(nv), VB, 0, s, nv, v, wa, wb, x, ms);
+}
+
+// unpreconditioned bordered product: out = [u o v + phi + v_n ; *vsum]
+__global__ void k_bordered_plain(int64_t n, const double* __restrict__ v, const double* __restrict__ u,
+                                 const double* __restrict__ phi, const double* __restrict__ vsum,
+                                 double* __restrict__ out) {
+    const double vl = v[n];
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB)
+        out[i] = u[i] * v[i] + phi[i] + vl;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *vsum;
+}
+void bordered_plain(int64_t n, const double* v, const double* u, const double* phi, const double* vsum, double* out,
+                    hipStream_t s) {
+    PQ_LAUNCH(k_bordered_plain, vgrid(n), VB, 0, s, n, v, u, phi, vsum, out);
+}
+
 }  // namespace pq

@@ -31,7 +31,7 @@ def test_library_loads_and_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert sorted(P.EXPORTS) == _declared()
     L = P.load()
-    assert L.pq_abi_version() == P.ABI_VERSION == 4
+    assert L.pq_abi_version() == P.ABI_VERSION == 5
     assert L.pq_coulomb_constant() == 14.3996454784
 
 
@@ -66,6 +66,8 @@ def test_result_and_tune_struct_layouts():
     # q pointer, energy, solve info (24), status + pad, three doubles, message[256]
     assert P.Result.message.offset == 8 + 8 + 24 + 8 + 24
     assert ctypes.sizeof(P.Result) == 8 + 8 + 24 + 8 + 24 + 256
+    assert P.Request.params.offset == 8 + 4 * 8 + 2 * 8 + 4 * 4
+    assert ctypes.sizeof(P.Request) == P.Request.params.offset + ctypes.sizeof(P.Params)
     assert ctypes.sizeof(P.TuneResult) == 32 and P.TuneResult.fft_lds_bytes.offset == 24
 
 

@@ -2,12 +2,16 @@
 PME 48^3 order 5, cutoff 9 A), against the dense FP64 oracle.
 
 With the workload's hardness U(5, 10) eV the QEQ matrix is indefinite (about
-half of its eigenvalues are negative, see the design notes) and GMRES does
-not reach a tight tolerance in a bounded number of products, so that case
-checks the envelope-theorem gradient at the oracle's solution q*. A
-well-posed variant of the same geometry (hardness U(20, 25) eV) runs the whole
-device pipeline: solve, envelope gradient and the adjoint solve of a general
-vector-Jacobian product.
+half of its eigenvalues are negative): restarted GMRES stalls, and full GMRES
+(restart = product budget) needs about n products. Both are run: the
+envelope-theorem gradient at the oracle's solution q*, the honest
+non-convergence report of GMRES(50), and a full-GMRES solve (FP64 form) to
+1e-7 with the device gradients at its solution. A well-posed variant of the same geometry
+(hardness U(20, 25) eV) runs the whole device pipeline: solve, envelope
+gradient and the adjoint solve of a general vector-Jacobian product.
+Gradient tolerance 1e-5 relative (the force tolerance of the FP32 form); on
+the indefinite system the charges carry up to cond * (backward error) of
+solve error, which is added to it.
 """
 import sys
 
@@ -73,6 +77,33 @@ def test_envelope_gradient_workload_hardness(P, member):
     ctx.close()
 
 
+def test_full_gmres_at_workload_hardness(P, member):
+    s, coul, A = member
+    M = Q.bordered(A, s.eta)
+    kappa = np.linalg.cond(M)
+    z = np.linalg.solve(M, np.concatenate([-s.chi, [0.0]]))
+    qd = z[:-1]
+    # FP64 form: with the FP32-bulk operator the residual of this system
+    # stalls near 5e-5 (its rounding, amplified by the conditioning)
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), P.make_params(s.box, 9.0, W.ALPHA_RC9, grid=48, order=5, fp64=True))
+    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=1e-7, max_it=3000, restart=3000)
+    q = r.q.cpu().numpy()
+    back = Q.bordered_residual(A, s.chi, s.eta, 0.0, q, r.lam)
+    fwd = rel(np.append(q, r.lam), z)
+    say(f"[grad-workload-full] full GMRES (FP64 form): status {r.status}, {r.iterations} products, relres "
+        f"{r.rel_residual:.2e} (oracle {back:.2e}), cond {kappa:.3g}, forward err {fwd:.2e}")
+    assert r.status == 0
+    assert back < 1e-6
+    assert fwd <= 1.01 * kappa * back
+    dpos, dchi, deta = ctx.qeq_vjp(gpu(s.chi), gpu(s.eta), r.q)
+    dR = -Q.force(s.pos, qd, s.box, coul)
+    e = rel(dpos.cpu().numpy(), dR)
+    say(f"[grad-workload-full] dE/dR rel err {e:.2e}")
+    assert e < 1.01 * kappa * back + 1e-5
+    ctx.close()
+
+
 def test_full_pipeline_well_posed(P, member):
     s, coul, A = member
     eta = np.random.default_rng(77).uniform(20.0, 25.0, s.n)
@@ -88,24 +119,27 @@ def test_full_pipeline_well_posed(P, member):
     say(f"[grad-posdef] solve: its {r.iterations} relres {r.rel_residual:.2e} cond {kappa:.1f} "
         f"q err {rel(q, qd):.2e}")
     assert r.status == 0
-    assert rel(q, qd) < 30 * kappa * 1e-6
+    back = Q.bordered_residual(A, s.chi, eta, 0.0, q, r.lam)
+    lam = np.linalg.solve(M, np.concatenate([-s.chi, [0.0]]))[-1]
+    assert rel(np.append(q, r.lam), np.append(qd, lam)) <= 1.01 * kappa * back
     # envelope gradient through the solve
     dpos, dchi, deta = ctx.qeq_vjp(gpu(s.chi), gpu(eta), r.q)
     dR = -Q.force(s.pos, qd, s.box, coul)
     say(f"[grad-posdef] dE/dR {rel(dpos.cpu().numpy(), dR):.2e}")
-    assert rel(dpos.cpu().numpy(), dR) < 30 * kappa * 1e-6
+    assert rel(dpos.cpu().numpy(), dR) < 1e-5
     # general VJP: adjoint solve on the device
     g = np.random.default_rng(78).normal(size=s.n)
-    gp, gc, ge = ctx.qeq_vjp(gpu(s.chi), gpu(eta), r.q, gpu(g), tol=3e-7)
+    gp, gc, ge, st = ctx.qeq_vjp(gpu(s.chi), gpu(eta), r.q, gpu(g), tol=3e-7, with_status=True)
+    assert st == 0
     z = np.linalg.solve(M, np.concatenate([g, [0.0]]))
     a = z[:-1]
     ref_c, ref_e = -a, -a * qd
     errs = (rel(gc.cpu().numpy(), ref_c), rel(ge.cpu().numpy(), ref_e))
     say(f"[grad-posdef] VJP dchi {errs[0]:.2e} deta {errs[1]:.2e}")
-    assert max(errs) < 60 * kappa * 1e-6
+    assert max(errs) < 1e-5
     # dL/dR = F[a + q] - F[a] - F[q] with the oracle's forces
     ref_R = Q.force(s.pos, a + qd, s.box, coul) - Q.force(s.pos, a, s.box, coul) - Q.force(s.pos, qd, s.box, coul)
     eR = rel(gp.cpu().numpy(), ref_R)
     say(f"[grad-posdef] VJP dR {eR:.2e}")
-    assert eR < 60 * kappa * 1e-6
+    assert eR < 1e-5
     ctx.close()

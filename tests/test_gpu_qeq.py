@@ -2,12 +2,16 @@
 dense oracle built from the same Coulomb operator (same alpha, cutoff, grid,
 order).
 
-The operator products are FP32-bulk Coulomb evaluations with a relative
-error of ~3e-7, so a solution differs from the dense FP64 solution by up to
-cond(M) times that. The tests therefore check (a) the backward error: the
-residual of the GPU solution in the oracle's FP64 bordered system, which does
-not depend on the conditioning, and (b) the forward error against a bound of
-30 * cond(M) * 1e-6 (relative).
+Tolerances:
+* solves: the backward error (the residual of the GPU solution z = [q; lambda]
+  in the oracle's FP64 bordered system) must be below 5e-6, and the forward
+  error of z is bounded by the perturbation theorem for linear systems,
+  ||z - z*|| / ||z*|| <= cond(M) * backward error (checked with 1 % slack);
+* gradients and vector-Jacobian products: 1e-5 relative, the force tolerance
+  of the FP32 form (2e-5 for dE/du = q^2/2, whose relative error is twice that
+  of q), about ten times the errors measured on MI355X;
+* the FP32-bulk products bound the attainable residual near 1e-7 (cond ~ 14)
+  to 1e-6 (cond ~ 500), so solves ask for 3e-7 and 2e-6 respectively.
 """
 import sys
 
@@ -23,6 +27,7 @@ from oracle import qeq as Q
 pytestmark = pytest.mark.gpu
 
 EPS_OP = 1e-6   # bound on the relative error of one FP32-bulk operator product
+TOL_GRAD = 1e-5  # gradients and vector-Jacobian products (relative L2)
 
 
 def say(*a):
@@ -80,14 +85,19 @@ def make_ctx(P, s, coul):
     return ctx
 
 
-@pytest.mark.parametrize("which,restart,q0,tol", [("posdef", 50, False, 1e-7), ("posdef", 6, True, 1e-7),
-                                                  ("workload", 128, False, 1e-6)])
-def test_qeq_solve_matches_dense(P, system, system_workload, which, restart, q0, tol):
+@pytest.mark.parametrize("which,solver,restart,q0,tol", [("posdef", "gmres", 50, False, 1e-7),
+                                                         ("posdef", "gmres", 6, True, 1e-7),
+                                                         ("workload", "gmres", 128, False, 1e-6),
+                                                         ("posdef", "minres", 1, False, 1e-7),
+                                                         ("posdef", "minres", 1, True, 1e-7),
+                                                         ("workload", "minres", 1, False, 1e-6)])
+def test_qeq_solve_matches_dense(P, system, system_workload, which, solver, restart, q0, tol):
     s, coul, A = system if which == "posdef" else system_workload
-    say(f"[qeq-{which}] n={s.n} restart={restart} q0={q0} tol={tol}")
+    say(f"[qeq-{which}] {solver} n={s.n} restart={restart} q0={q0} tol={tol}")
     ctx = make_ctx(P, s, coul)
+    ctx.set_solver(solver)
     q0v = gpu(np.random.default_rng(3).normal(0, 0.2, s.n)) if q0 else None
-    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), q_tot=0.0, tol=tol, max_it=400, restart=restart, q0=q0v,
+    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), q_tot=0.0, tol=tol, max_it=1200, restart=restart, q0=q0v,
                       force=True)
     torch.cuda.synchronize()
     q = host(r.q)
@@ -95,7 +105,8 @@ def test_qeq_solve_matches_dense(P, system, system_workload, which, restart, q0,
     M = Q.bordered(A, s.eta)
     kappa = np.linalg.cond(M)
     back = Q.bordered_residual(A, s.chi, s.eta, 0.0, q, r.lam)
-    fwd = np.linalg.norm(q - qd) / np.linalg.norm(qd)
+    z, zd = np.concatenate([q, [r.lam]]), np.concatenate([qd, [lam]])
+    fwd = np.linalg.norm(z - zd) / np.linalg.norm(zd)
     say(f"[qeq] its={r.iterations} restarts={r.restarts} gpu relres={r.rel_residual:.2e} "
         f"oracle backward err={back:.2e} forward err={fwd:.2e} cond={kappa:.1f}")
     assert r.status == 0
@@ -103,9 +114,11 @@ def test_qeq_solve_matches_dense(P, system, system_workload, which, restart, q0,
     # to the solve's residual, |sum q - Q_tot| <= back * ||b||
     assert abs(q.sum()) <= back * np.linalg.norm(np.concatenate([s.chi, [0.0]])) + 1e-12
     assert back < 5e-6
-    assert fwd < 30 * kappa * EPS_OP
-    assert abs(r.lam - lam) < 30 * kappa * EPS_OP * max(1.0, abs(lam))
-    if restart < 20:
+    assert fwd <= 1.01 * kappa * back
+    # the reported residual is measured with the FP32-bulk operator, the
+    # oracle's in FP64: they differ by the operator's rounding (~3e-7)
+    assert abs(r.rel_residual - back) < 0.1 * back + 5e-7
+    if solver == "gmres" and restart < 20:
         assert r.restarts >= 1
     # energy and force at the solution
     E = float(host(r.energy)[0])
@@ -113,7 +126,49 @@ def test_qeq_solve_matches_dense(P, system, system_workload, which, restart, q0,
     assert abs(E - Ed) < 1e-5 * abs(Ed)
     Fd = Q.force(s.pos, qd, s.box, coul)
     F = host(r.force)
-    assert np.linalg.norm(F - Fd) / np.linalg.norm(Fd) < 30 * kappa * EPS_OP
+    # F[q] is linear in q: its error is the charge error (cond * back) plus
+    # the FP32 rounding of the evaluation
+    assert np.linalg.norm(F - Fd) / np.linalg.norm(Fd) < 1.01 * kappa * back + TOL_GRAD
+    ctx.close()
+
+
+def test_autograd_raises_when_the_solve_does_not_converge(P, system_workload):
+    """At the workloads' hardness restarted GMRES stalls: the autograd
+    functions must raise rather than return an unconverged energy, charges or
+    envelope gradients."""
+    s, coul, A = system_workload
+    ctx = make_ctx(P, s, coul)
+    pos = gpu(s.pos).requires_grad_(True)
+    chi = gpu(s.chi).requires_grad_(True)
+    eta = gpu(s.eta).requires_grad_(True)
+    with pytest.raises(P.NotConvergedError):
+        P.QEQEnergy.apply(pos, chi, eta, ctx, 0.0, 1e-8, 40, 20)
+    with pytest.raises(P.NotConvergedError):
+        P.QEQCharges.apply(pos, chi, eta, ctx, 0.0, 1e-8, 40, 20)
+    ctx.close()
+
+
+def test_autograd_full_gmres_on_the_indefinite_system(P, system_workload):
+    """Full GMRES (restart = max_it) solves the indefinite system; the
+    envelope gradients through QEQEnergy then match the dense oracle."""
+    s, coul, A = system_workload
+    ctx = make_ctx(P, s, coul)
+    pos = gpu(s.pos).requires_grad_(True)
+    chi = gpu(s.chi).requires_grad_(True)
+    eta = gpu(s.eta).requires_grad_(True)
+    # the FP32-bulk products bound the attainable residual near cond * 1e-9
+    # (about 7e-7 here): ask for 2e-6
+    E = P.QEQEnergy.apply(pos, chi, eta, ctx, 0.0, 2e-6, 400, 400)
+    E.backward()
+    Ed, qd, dR, dc, de = G.qeq_energy_and_grad(s.pos, s.box, coul, s.chi, s.eta)
+    kappa = np.linalg.cond(Q.bordered(A, s.eta))
+    errs = [np.linalg.norm(host(a) - b) / np.linalg.norm(b) for a, b in ((pos.grad, dR), (chi.grad, dc), (eta.grad, de))]
+    say(f"[autograd-indefinite] cond {kappa:.1f} E {float(E):.9g} vs {Ed:.9g} grad errs {errs}")
+    # E is a small difference of large terms here: bound its error by the scale of the terms
+    scale = np.abs(qd * s.chi).sum() + 0.5 * np.sum(s.eta * qd * qd)
+    assert abs(float(E) - Ed) < 1e-6 * scale
+    # cond 511: the charges carry up to cond * 2e-6 of solve error; measured 3e-6
+    assert max(errs) < 3 * TOL_GRAD
     ctx.close()
 
 
@@ -182,16 +237,14 @@ def test_shadow_fixed_point(P, system):
 def test_vjp_energy_envelope(P, system):
     s, coul, A = system
     ctx = make_ctx(P, s, coul)
-    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=1e-9, max_it=400)
+    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=3e-7, max_it=400)
+    assert r.status == 0
     dpos, dchi, deta = ctx.qeq_vjp(gpu(s.chi), gpu(s.eta), r.q)
     torch.cuda.synchronize()
     _, qd, dR, dc, de = G.qeq_energy_and_grad(s.pos, s.box, coul, s.chi, s.eta)
-    kappa = np.linalg.cond(Q.bordered(A, s.eta))
-    tol = 30 * kappa * EPS_OP
-    say(f"[vjp-energy] dR err {np.linalg.norm(host(dpos) - dR) / np.linalg.norm(dR):.2e} tol {tol:.1e}")
-    assert np.linalg.norm(host(dpos) - dR) / np.linalg.norm(dR) < tol
-    assert np.linalg.norm(host(dchi) - dc) / np.linalg.norm(dc) < tol
-    assert np.linalg.norm(host(deta) - de) / np.linalg.norm(de) < 2 * tol
+    errs = [np.linalg.norm(host(a) - b) / np.linalg.norm(b) for a, b in ((dpos, dR), (dchi, dc), (deta, de))]
+    say(f"[vjp-energy] errs {errs} tol {TOL_GRAD:.1e}")
+    assert errs[0] < TOL_GRAD and errs[1] < TOL_GRAD and errs[2] < 2 * TOL_GRAD
     ctx.close()
 
 
@@ -199,15 +252,15 @@ def test_vjp_general_upstream(P, system):
     s, coul, A = system
     g = np.random.default_rng(8).normal(size=s.n)
     ctx = make_ctx(P, s, coul)
-    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=1e-9, max_it=400)
-    dpos, dchi, deta = ctx.qeq_vjp(gpu(s.chi), gpu(s.eta), r.q, gpu(g), tol=1e-9)
+    r = ctx.qeq_solve(gpu(s.chi), gpu(s.eta), tol=3e-7, max_it=400)
+    assert r.status == 0
+    dpos, dchi, deta, st = ctx.qeq_vjp(gpu(s.chi), gpu(s.eta), r.q, gpu(g), tol=3e-7, with_status=True)
     torch.cuda.synchronize()
+    assert st == 0
     dR, dc, de = G.qeq_vjp(s.pos, s.box, coul, s.chi, s.eta, g)
-    kappa = np.linalg.cond(Q.bordered(A, s.eta))
-    tol = 30 * kappa * EPS_OP
     errs = [np.linalg.norm(host(a) - b) / np.linalg.norm(b) for a, b in ((dpos, dR), (dchi, dc), (deta, de))]
-    say(f"[vjp-general] errs {errs} tol {tol:.1e}")
-    assert max(errs) < 3 * tol
+    say(f"[vjp-general] errs {errs} tol {TOL_GRAD:.1e}")
+    assert max(errs) < TOL_GRAD
     ctx.close()
 
 
@@ -217,19 +270,20 @@ def test_autograd_function(P, system):
     pos = gpu(s.pos).requires_grad_(True)
     chi = gpu(s.chi).requires_grad_(True)
     eta = gpu(s.eta).requires_grad_(True)
-    E = P.QEQEnergy.apply(pos, chi, eta, ctx, 0.0, 1e-9)
+    E = P.QEQEnergy.apply(pos, chi, eta, ctx, 0.0, 3e-7)
     E.backward()
     _, qd, dR, dc, de = G.qeq_energy_and_grad(s.pos, s.box, coul, s.chi, s.eta)
-    kappa = np.linalg.cond(Q.bordered(A, s.eta))
-    assert np.linalg.norm(host(pos.grad) - dR) / np.linalg.norm(dR) < 30 * kappa * EPS_OP
-    assert np.linalg.norm(host(chi.grad) - dc) / np.linalg.norm(dc) < 30 * kappa * EPS_OP
+    e1 = [np.linalg.norm(host(a) - b) / np.linalg.norm(b) for a, b in ((pos.grad, dR), (chi.grad, dc), (eta.grad, de))]
     # charges function: gradient of sum(w * q*) equals the general VJP
     w = np.random.default_rng(9).normal(size=s.n)
     chi2 = gpu(s.chi).requires_grad_(True)
-    qs = P.QEQCharges.apply(gpu(s.pos), chi2, gpu(s.eta), ctx, 0.0, 1e-9)
+    qs = P.QEQCharges.apply(gpu(s.pos), chi2, gpu(s.eta), ctx, 0.0, 3e-7)
     (qs * gpu(w)).sum().backward()
     _, dcw, _ = G.qeq_vjp(s.pos, s.box, coul, s.chi, s.eta, w)
-    assert np.linalg.norm(host(chi2.grad) - dcw) / np.linalg.norm(dcw) < 90 * kappa * EPS_OP
+    e2 = np.linalg.norm(host(chi2.grad) - dcw) / np.linalg.norm(dcw)
+    say(f"[autograd] energy grads {e1} charges VJP {e2:.2e}")
+    assert e1[0] < TOL_GRAD and e1[1] < TOL_GRAD and e1[2] < 2 * TOL_GRAD
+    assert e2 < TOL_GRAD
     ctx.close()
 
 
