@@ -132,11 +132,25 @@ double pq_coulomb_constant(void);
 const char* pq_last_error(void);
 
 /* ---- context ------------------------------------------------------------ */
+/* Device-memory allocator for a context's workspaces (the Python binding
+ * passes torch's caching allocator). alloc(bytes, user_data) returns device
+ * memory on the context's device, or NULL on failure (the call then returns
+ * PQ_ERR_NOMEM); free(ptr, user_data) takes back a block that alloc
+ * returned. Both are called on the thread that calls into the context, with
+ * the context's device current. The library frees a block only after a
+ * device-wide synchronisation, so no queued kernel still uses it. */
+typedef struct pq_allocator {
+    void* (*alloc)(size_t bytes, void* user_data);
+    void (*free)(void* ptr, void* user_data);
+    void* user_data;
+} pq_allocator;
+
 /* Creates a context on HIP device `device`; work is enqueued on `stream`
  * (a hipStream_t, NULL = the device's null stream). The context owns its
  * device workspaces (allocated on first use, grown on demand, freed by
- * pq_destroy). */
-pq_status pq_create(pq_ctx** out, int device, void* stream);
+ * pq_destroy), taken from `alloc` (copied; NULL, or NULL members:
+ * hipMalloc / hipFree). */
+pq_status pq_create(pq_ctx** out, int device, void* stream, const pq_allocator* alloc);
 pq_status pq_set_stream(pq_ctx* ctx, void* stream);
 pq_status pq_destroy(pq_ctx* ctx);
 

@@ -60,6 +60,14 @@ class TuneResult(ctypes.Structure):
                 ("ms_default", ctypes.c_double), ("fft_lds_bytes", ctypes.c_int32), ("pair_fork", ctypes.c_int32)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user_data", ctypes.c_void_p)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_double)]
 
@@ -93,7 +101,7 @@ def load() -> ctypes.CDLL:
         "pq_abi_version": (i32, []),
         "pq_coulomb_constant": (dbl, []),
         "pq_last_error": (ctypes.c_char_p, []),
-        "pq_create": (i32, [ctypes.POINTER(vp), i32, vp]),
+        "pq_create": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Allocator)]),
         "pq_set_stream": (i32, [vp, vp]),
         "pq_destroy": (i32, [vp]),
         "pq_set_system": (i32, [vp, i64, vp, ctypes.POINTER(Params)]),
@@ -218,14 +226,37 @@ class QeqResult:
     status: int
 
 
-class Context:
-    """One system on one device; calls are ordered on torch's current stream."""
+def _torch_allocator(device: torch.device) -> Allocator:
+    """The library's workspaces from torch's caching allocator (on the
+    stream that is current when a block is taken)."""
 
-    def __init__(self, device: int = 0):
+    def alloc(nbytes, _ud):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, torch.cuda.current_stream(device))
+        except Exception:  # out of memory: the library reports PQ_ERR_NOMEM
+            return None
+
+    def free(ptr, _ud):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:  # interpreter shutdown: torch's allocator is gone with the process
+            pass
+
+    return Allocator(ALLOC_FN(alloc), FREE_FN(free), None)
+
+
+class Context:
+    """One system on one device; calls are ordered on torch's current stream.
+    Workspaces come from torch's caching allocator (allocator="torch") or
+    from hipMalloc (allocator=None)."""
+
+    def __init__(self, device: int = 0, allocator: str | None = "torch"):
         self.lib = load()
         self.device = torch.device("cuda", device)
+        self._alloc = _torch_allocator(self.device) if allocator == "torch" else None
         h = ctypes.c_void_p()
-        _check(self.lib.pq_create(ctypes.byref(h), device, None))
+        _check(self.lib.pq_create(ctypes.byref(h), device, None,
+                                  ctypes.byref(self._alloc) if self._alloc is not None else None))
         self.h = h
         self.n = 0
 

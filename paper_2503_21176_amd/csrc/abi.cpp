@@ -344,7 +344,7 @@ double pq_coulomb_constant(void) { return KE; }
 
 const char* pq_last_error(void) { return pq::g_err.c_str(); }
 
-pq_status pq_create(pq_ctx** out, int device, void* stream) {
+pq_status pq_create(pq_ctx** out, int device, void* stream, const pq_allocator* alloc) {
     PQ_API_BEGIN
     PQ_REQUIRE(out != nullptr, PQ_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -355,9 +355,12 @@ pq_status pq_create(pq_ctx** out, int device, void* stream) {
     // this device's copy of the no-allocation scratch (pq_coulomb_noalloc
     // reports a failed lookup)
     (void)scratch_for_device(device);
+    PQ_REQUIRE(!alloc || (alloc->alloc == nullptr) == (alloc->free == nullptr), PQ_ERR_INVALID,
+               "an allocator needs both alloc and free (or neither)");
     Ctx* c = new Ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
+    if (alloc) c->alloc = *alloc;
     std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
     if (hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete c;
@@ -392,6 +395,7 @@ pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_para
     PQ_REQUIRE(ctx != nullptr && pos != nullptr, PQ_ERR_INVALID, "ctx or pos is NULL");
     validate(n, prm);
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_HIP(hipSetDevice(c.device));
     c.have_system = false;
     ++c.gen;
@@ -414,6 +418,7 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
     PQ_REQUIRE(ctx != nullptr && n_pairs != nullptr, PQ_ERR_INVALID, "ctx or n_pairs is NULL");
     PQ_REQUIRE(cap >= 0, PQ_ERR_INVALID, "cap must be >= 0");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_HIP(hipSetDevice(c.device));
     const int64_t tot = nbr_export_pairs(c, pairs ? cap : 0, pairs);
@@ -431,6 +436,7 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx and q must not be NULL");
     PQ_REQUIRE(reps >= 1 && reps <= 1000, PQ_ERR_INVALID, "reps must be in 1..1000");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_REQUIRE(!c.timing, PQ_ERR_STATE, "phase timing must be off while tuning");
     PQ_HIP(hipSetDevice(c.device));
@@ -505,6 +511,7 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
                "fft_lds_bytes must be 0 or in 1024..65536");
     PQ_REQUIRE(t->pair_fork >= 0 && t->pair_fork <= 2, PQ_ERR_INVALID, "pair_fork must be in 0..2");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     c.fft_budget = t->fft_lds_bytes ? t->fft_lds_bytes : 18432;
     c.fork_at = t->pair_fork;
     PQ_HIP(hipSetDevice(c.device));
@@ -529,6 +536,7 @@ pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && ms != nullptr && count != nullptr, PQ_ERR_INVALID, "NULL argument");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_HIP(hipSetDevice(c.device));
     for (int k = 0; k < PQ_NPHASE; ++k) ms[k] = 0.0;
     *count = (int64_t)c.ev_pending.size();
@@ -550,6 +558,7 @@ pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, d
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_HIP(hipSetDevice(c.device));
     coulomb_eval(c, q, phi, force, energy, c.stream);
     return PQ_OK;
@@ -560,6 +569,7 @@ pq_status pq_coulomb_noalloc(pq_ctx* ctx, const double* q, double* phi, double* 
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_REQUIRE(!c.timing, PQ_ERR_STATE, "phase timing must be off (it creates events)");
     PQ_HIP(hipSetDevice(c.device));

@@ -32,12 +32,17 @@ struct Work {
     int m;
     double* V;
     double* st;
+    double* up = nullptr;   // chunk sums of long-basis combinations (m + 1 > 32)
     double* w(int k) { return c.kw.p + (size_t)k * ld; }
     double* sc(int k) { return c.scal.p + 16 + k; }   // device scalars 16..63
     Work(Ctx& cc, int mm) : c(cc), ld(round_ld(cc.n + 1)), m(mm) {
         c.kw.ensure(ld * W_N);
         c.kv.ensure(ld * (size_t)(m + 1));
         c.kh.ensure(gs_size(m) + 8);
+        if (m + 1 > 32) {
+            c.kup.ensure(vcomb_chunks(m + 1) * ld);
+            up = c.kup.p;
+        }
         ensure_red(c);
         V = c.kv.p;
         st = c.kh.p;
@@ -71,7 +76,7 @@ void arnoldi_step(Work& W, const OpFn& op, int64_t nv) {
     double* w = W.w(W_W);
     copy_j(nv, W.V, W.ld, c.kj.p, xj, s);
     op(xj, w);
-    orthogonalize_j(c, nv, W.V, W.ld, m, c.kj.p, w, W.st, W.st + gs_t(m), s);
+    orthogonalize_j(c, nv, W.V, W.ld, m, c.kj.p, w, W.st, W.st + gs_t(m), W.up, s);
     dot_vector(c, w, w, nv, W.sc(2), s);
     normalize_j(nv, w, W.sc(2), W.st, m, W.V, W.ld, c.kj.p, s);
     givens_j(W.st, m, c.kj.p, W.st + gs_hist(m), s);
@@ -89,7 +94,8 @@ hipGraphExec_t step_graph(Work& W, const std::function<void()>& body, int64_t nv
     Ctx& c = W.c;
     if (!c.graphs || c.timing) return nullptr;
     std::vector<uintptr_t> key = {kind, (uintptr_t)opkey, (uintptr_t)nv, (uintptr_t)W.m, (uintptr_t)W.ld,
-                                  (uintptr_t)c.kv.p, (uintptr_t)c.kw.p, (uintptr_t)c.kh.p, (uintptr_t)c.scal.p,
+                                  (uintptr_t)c.kv.p, (uintptr_t)c.kw.p, (uintptr_t)c.kh.p, (uintptr_t)W.up,
+                                  (uintptr_t)c.scal.p,
                                   (uintptr_t)c.part.p, (uintptr_t)c.kj.p, (uintptr_t)c.gen, (uintptr_t)c.pair_grid,
                                   (uintptr_t)c.fft_budget, (uintptr_t)c.fork_at};
     if (c.kgraph && key == c.kgraph_key) return c.kgraph;
@@ -213,7 +219,7 @@ GmresOut gmres(Work& W, const OpFn& op, int64_t nv, const double* b, double* x, 
             if (!fixed && launched > 0) PQ_HIP(hipEventSynchronize(c.kev[(launched - 1) & 1]));
         }
         backsolve(W.st, m, jdone, s);
-        xupdate(nv, W.V, W.ld, jdone, W.st + gs_y(m), x, s);
+        xupdate(nv, W.V, W.ld, jdone, W.st + gs_y(m), x, W.up, s);
         if (fixed) return out;
         // true residual
         op(x, w);
@@ -432,6 +438,7 @@ pq_status pq_set_solver(pq_ctx* ctx, int32_t solver, int32_t vjp_restart) {
     PQ_REQUIRE(solver == PQ_SOLVER_GMRES || solver == PQ_SOLVER_MINRES, PQ_ERR_INVALID, "unknown solver");
     PQ_REQUIRE(vjp_restart >= 1 && vjp_restart <= PQ_MAX_RESTART, PQ_ERR_INVALID, "vjp_restart must be in 1..4096");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     c.solver = solver;
     c.vjp_restart = vjp_restart;
     return PQ_OK;
@@ -446,6 +453,7 @@ pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double
                "need tol > 0, max_it >= 1, 1 <= restart <= 4096");
     check_finite_host(q_tot, "q_tot");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_HIP(hipSetDevice(c.device));
     hipStream_t s = c.stream;
@@ -475,6 +483,7 @@ pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, doub
     PQ_REQUIRE(n_krylov >= 1 && n_krylov <= 512, PQ_ERR_INVALID, "n_krylov must be in 1..512");
     check_finite_host(q_tot, "q_tot");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_HIP(hipSetDevice(c.device));
     hipStream_t s = c.stream;
@@ -526,6 +535,7 @@ pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const do
     PQ_API_BEGIN
     PQ_REQUIRE(ctx && chi && eta && q_star, PQ_ERR_INVALID, "ctx, chi, eta and q_star must not be NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_HIP(hipSetDevice(c.device));
     hipStream_t s = c.stream;

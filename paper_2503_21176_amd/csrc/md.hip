@@ -294,6 +294,7 @@ extern "C" pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const doub
         PQ_REQUIRE(ctx && pos && vel && mass && chi && eta && n_hist && cfg, PQ_ERR_INVALID,
                    "ctx, pos, vel, mass, chi, eta, n_hist and cfg must not be NULL");
         Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+        AllocScope alloc_scope(c);
         PQ_HIP(hipSetDevice(c.device));
         md_run(c, pos, vel, mass, chi, eta, q_tot, n_hist, steps, *cfg, energies);
         return PQ_OK;

@@ -137,11 +137,20 @@ inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b);
 // synchronise must never meet a stream that is being captured.
 std::recursive_mutex& device_mem_lock();
 
-// Device buffer owned by a context; grows on demand, never shrinks.
+// The allocator of the context whose entry point is running on this thread
+// (AllocScope sets it); null: hipMalloc / hipFree.
+inline const pq_allocator*& tl_alloc() {
+    thread_local const pq_allocator* a = nullptr;
+    return a;
+}
+
+// Device buffer owned by a context; grows on demand, never shrinks. It
+// remembers the allocator that gave it its block and returns the block there.
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
+    pq_allocator owner{};
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
@@ -151,11 +160,20 @@ struct DBuf {
         std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
         release();
         if (m == 0) return;
+        const size_t bytes = m * sizeof(T);
+        const pq_allocator* a = tl_alloc();
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, m * sizeof(T));
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw Error(PQ_ERR_NOMEM, "hipMalloc of " + std::to_string(m * sizeof(T)) + " bytes failed");
+        if (a && a->alloc && a->free) {
+            q = a->alloc(bytes, a->user_data);
+            if (!q) throw Error(PQ_ERR_NOMEM, "allocator callback failed for " + std::to_string(bytes) + " bytes");
+            owner = *a;
+        } else {
+            hipError_t e = hipMalloc(&q, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(PQ_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+            }
+            owner = pq_allocator{};
         }
         p = static_cast<T*>(q);
         n = m;
@@ -165,9 +183,13 @@ struct DBuf {
         std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
         // kernels queued on any stream may still use the old buffer
         (void)hipDeviceSynchronize();
-        (void)hipFree(p);
+        if (owner.free)
+            owner.free(p, owner.user_data);
+        else
+            (void)hipFree(p);
         p = nullptr;
         n = 0;
+        owner = pq_allocator{};
     }
     size_t bytes() const { return n * sizeof(T); }
 };
@@ -234,6 +256,7 @@ struct InfTab {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    pq_allocator alloc{};    // workspace allocator (pq_create); null members: hipMalloc
     bool have_system = false;
     bool fp64 = false;       // bulk arithmetic in FP64 (PQ_FLAG_FP64) instead of FP32
     int64_t n = 0;
@@ -340,6 +363,7 @@ struct Ctx {
     DBuf<double> kw;         // work vectors
     DBuf<double> kh;         // Hessenberg and small solver state
     DBuf<double> kf;         // force scratch n*3 (x2)
+    DBuf<double> kup;        // chunk sums of the long-basis vector combinations
     size_t kld = 0;
     int km = 0;
 
@@ -356,6 +380,16 @@ struct Ctx {
     hipEvent_t kev[2] = {nullptr, nullptr};
 
     ~Ctx();
+};
+
+// Makes a context's allocator the current one of this thread for the
+// duration of an entry point (restored on exit, also by an exception).
+struct AllocScope {
+    const pq_allocator* prev;
+    explicit AllocScope(const Ctx& c) : prev(tl_alloc()) { tl_alloc() = c.alloc.alloc ? &c.alloc : nullptr; }
+    ~AllocScope() { tl_alloc() = prev; }
+    AllocScope(const AllocScope&) = delete;
+    AllocScope& operator=(const AllocScope&) = delete;
 };
 
 // Typed view of a precision-dependent byte buffer.

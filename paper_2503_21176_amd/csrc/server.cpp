@@ -267,7 +267,7 @@ pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg) {
     for (int k = 0; k < cfg->slots; ++k) {
         auto sl = std::make_unique<pq_server::Slot>();
         PQ_HIP(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
-        pq_status st = pq_create(&sl->ctx, cfg->device, sl->stream);
+        pq_status st = pq_create(&sl->ctx, cfg->device, sl->stream, nullptr);
         if (st != PQ_OK) throw Error(st, pq_last_error());
         // slots launch their kernels directly; Arnoldi-step graphs are kept
         // for contexts driven from one thread (several slots replaying their

@@ -35,20 +35,21 @@ void jac_out(int64_t n, const double* x, const double* t, const double* u, const
 void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const double* u, double* out2, hipStream_t s);
 void shadow_q(int64_t n, const double* chi, const double* v, const double* u, const double* sums, double qtot,
               double* q, double* lam, hipStream_t s);
-void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
-                   hipStream_t s);
 void normalize(int64_t n, const double* w, const double* nrm2, double* hsub, double* out, hipStream_t s);
-void givens(double* st, int m, int j, double* resid, hipStream_t s);
 void gmres_start(double* st, int m, const double* nrm2, hipStream_t s);
 void backsolve(double* st, int m, int k, hipStream_t s);
-void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, hipStream_t s);
+// x += sum_{k < nk} y[k] V_k; up: chunk sums (vcomb_chunks(nk) x ld) when nk > 32
+void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, double* up, hipStream_t s);
+size_t vcomb_chunks(int nk);
 void qeq_energy(Ctx& c, int64_t n, const double* q, const double* chi, const double* u, const double* a,
                 const double* phi, double* out, hipStream_t s);
 void copy_scalar(const double* a, double* b, hipStream_t s);
 // device-indexed forms: the step index j is *jdev (graph-captured steps)
 void copy_j(int64_t n, const double* V, size_t ld, const int* jdev, double* out, hipStream_t s);
+// CGS2 of w against V_0..V_{*jdev} into column *jdev of H; up: chunk sums
+// (vcomb_chunks(m + 1) x ld) when m + 1 > 32
 void orthogonalize_j(Ctx& c, int64_t n, const double* V, size_t ld, int m, const int* jdev, double* w, double* st,
-                     double* tmp2, hipStream_t s);
+                     double* tmp2, double* up, hipStream_t s);
 void normalize_j(int64_t n, const double* w, const double* nrm2, double* st, int m, double* V, size_t ld,
                  const int* jdev, hipStream_t s);
 void givens_j(double* st, int m, int* jdev, double* hist, hipStream_t s);

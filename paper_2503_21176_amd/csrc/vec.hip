@@ -279,32 +279,66 @@ void shadow_sums(Ctx& c, int64_t n, const double* chi, const double* v, const do
 }
 
 // ---- Gram-Schmidt -----------------------------------------------------------
-// part[k*nb + b] = partial of V_k . w for k < nk (nk = *jdev + 1 with jdev),
-// MD_K dot products per pass over w, their block sums reduced together.
+// part[k*nb + b] = partial of V_k . w, nk = *jdev + 1 basis vectors with jdev.
+// Grid (nb, ceil(nk_max / MD_K)): workgroup (b, c) takes MD_K dot products of
+// chunk c over the b-th slice of the rows (the same slices and the same tree
+// for every dot product), so long bases keep the whole device busy.
 __global__ __launch_bounds__(VB) void k_mdot(int64_t n, const double* __restrict__ V, size_t ld, int nk,
                                              const int* __restrict__ jdev, const double* __restrict__ w,
                                              double* __restrict__ part) {
     __shared__ double red[(VB / 64) * MD_K];
     if (jdev) nk = *jdev + 1;
-    for (int k0 = 0; k0 < nk; k0 += MD_K) {
-        double v[MD_K];
+    const int k0 = blockIdx.y * MD_K;
+    if (k0 >= nk) return;
+    double v[MD_K];
 #pragma unroll
-        for (int k = 0; k < MD_K; ++k) v[k] = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
-            const double wi = w[i];
+    for (int k = 0; k < MD_K; ++k) v[k] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const double wi = w[i];
 #pragma unroll
-            for (int k = 0; k < MD_K; ++k)
-                if (k0 + k < nk) v[k] += V[(size_t)(k0 + k) * ld + i] * wi;
-        }
-        block_sum_n<MD_K>(v, red);
-        if (threadIdx.x == 0) {
+        for (int k = 0; k < MD_K; ++k)
+            if (k0 + k < nk) v[k] += V[(size_t)(k0 + k) * ld + i] * wi;
+    }
+    block_sum_n<MD_K>(v, red);
+    if (threadIdx.x == 0) {
 #pragma unroll
-            for (int k = 0; k < MD_K; ++k)
-                if (k0 + k < nk) part[(size_t)(k0 + k) * gridDim.x + blockIdx.x] = v[k];
+        for (int k = 0; k < MD_K; ++k)
+            if (k0 + k < nk) part[(size_t)(k0 + k) * gridDim.x + blockIdx.x] = v[k];
+    }
+}
+// The final sums of k_mdot's partials, one workgroup per chunk of MD_K:
+// out[k] = sum of part[k*nb .. k*nb+nb-1] (with jdev: nk = *jdev + 1 and out
+// advanced by *jdev * ostride); with acc also acc[k] += out[k].
+__global__ __launch_bounds__(VB) void k_mdot_final(const double* __restrict__ part, int nb, int nk,
+                                                   double* __restrict__ out, const int* __restrict__ jdev,
+                                                   size_t ostride, double* __restrict__ acc, size_t astride) {
+    __shared__ double red[(VB / 64) * MD_K];
+    if (jdev) {
+        nk = *jdev + 1;
+        out += (size_t)(*jdev) * ostride;
+        if (acc) acc += (size_t)(*jdev) * astride;
+    }
+    const int k0 = blockIdx.x * MD_K;
+    if (k0 >= nk) return;
+    double v[MD_K];
+#pragma unroll
+    for (int k = 0; k < MD_K; ++k) {
+        v[k] = 0.0;
+        if (k0 + k < nk)
+            for (int i = threadIdx.x; i < nb; i += VB) v[k] += part[(size_t)(k0 + k) * nb + i];
+    }
+    block_sum_n<MD_K>(v, red);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < MD_K; ++k) {
+            if (k0 + k >= nk) break;
+            out[k0 + k] = v[k];
+            if (acc) acc[k0 + k] = acc[k0 + k] + v[k];
         }
     }
 }
-// w -= sum_k h[k] V_k, k < nk (with jdev: nk = *jdev + 1, h advanced by *jdev * hstride)
+// w -= sum_k h[k] V_k, k < nk (with jdev: nk = *jdev + 1, h advanced by
+// *jdev * hstride); one pass for bases of at most KU vectors
 __global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const int* __restrict__ jdev,
                           size_t hstride, const double* __restrict__ h, double* __restrict__ w) {
     if (jdev) {
@@ -317,32 +351,74 @@ __global__ void k_mupdate(int64_t n, const double* __restrict__ V, size_t ld, in
         w[i] = acc;
     }
 }
-// CGS2 of w against V_0..V_{nk-1}; coefficients into hcol. With jdev the
-// column is that of step *jdev: nk = *jdev + 1, hcol = h0 + *jdev * hstride.
-static void orthogonalize_impl(Ctx& c, int64_t n, const double* V, size_t ld, int nk, const int* jdev,
-                               size_t hstride, double* w, double* hcol, double* tmp2, hipStream_t s) {
+// Longer bases in two passes: grid (rows, chunks of KU vectors) writes
+// up[c*ld + i] = sum over chunk c of h[k] V_k[i]; then every row adds its
+// chunk sums in chunk order: w += sign * sum_c up[c*ld + i].
+constexpr int KU = 32;
+__global__ void k_vcomb_part(int64_t n, const double* __restrict__ V, size_t ld, int nk, const int* __restrict__ jdev,
+                             size_t hstride, const double* __restrict__ h, double* __restrict__ up) {
+    if (jdev) {
+        nk = *jdev + 1;
+        h += (size_t)(*jdev) * hstride;
+    }
+    const int k0 = blockIdx.y * KU;
+    if (k0 >= nk) return;
+    const int k1 = min(nk, k0 + KU);
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        double acc = 0.0;
+        for (int k = k0; k < k1; ++k) acc += h[k] * V[(size_t)k * ld + i];
+        up[(size_t)blockIdx.y * ld + i] = acc;
+    }
+}
+__global__ void k_vcomb_apply(int64_t n, int nk, const int* __restrict__ jdev, const double* __restrict__ up, size_t ld,
+                              double sign, double* __restrict__ w) {
+    if (jdev) nk = *jdev + 1;
+    const int nc = (nk + KU - 1) / KU;
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        double t = 0.0;
+        for (int c = 0; c < nc; ++c) t += up[(size_t)c * ld + i];
+        w[i] = w[i] + sign * t;
+    }
+}
+size_t vcomb_chunks(int nk) { return (size_t)((nk + KU - 1) / KU); }
+
+// w += sign * sum_{k < nk} h[k] V_k (nk_max bounds the device count with jdev)
+static void vcomb(int64_t n, const double* V, size_t ld, int nk_max, const int* jdev, size_t hstride, const double* h,
+                  double sign, double* up, double* w, hipStream_t s) {
+    const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
+    const unsigned nc = (unsigned)vcomb_chunks(nk_max);
+    PQ_LAUNCH(k_vcomb_part, dim3(g, nc), VB, 0, s, n, V, ld, nk_max, jdev, hstride, h, up);
+    PQ_LAUNCH(k_vcomb_apply, g, VB, 0, s, n, nk_max, jdev, (const double*)up, ld, sign, w);
+}
+
+// CGS2 of w against V_0..V_{nk-1} (nk = *jdev + 1, at most m + 1); the
+// coefficients of step *jdev go to column *jdev of H (stride m + 1), the
+// re-orthogonalisation's into tmp2 and added to the column; up: chunk sums
+// (vcomb_chunks(m + 1) x ld) when m + 1 > KU.
+void orthogonalize_j(Ctx& c, int64_t n, const double* V, size_t ld, int m, const int* jdev, double* w, double* st,
+                     double* tmp2, double* up, hipStream_t s) {
+    const int nk = m + 1;
+    const size_t hstride = (size_t)(m + 1);
     const int nb = red_blocks(n);
+    const unsigned kc = cdiv(nk, MD_K);
     c.part.ensure((size_t)(nk + 1) * nb + 16);
     const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
-    // the dot products of one pass
     auto mdot = [&](double* dst, size_t ostride, double* acc, size_t astride) {
-        PQ_LAUNCH(k_mdot, nb, VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
-        PQ_LAUNCH(k_part_final, 1, VB, 0, s, c.part.p, nb, nk, 1.0, dst, jdev, ostride, acc, astride);
+        PQ_LAUNCH(k_mdot, dim3(nb, kc), VB, 0, s, n, V, ld, nk, jdev, w, c.part.p);
+        PQ_LAUNCH(k_mdot_final, kc, VB, 0, s, (const double*)c.part.p, nb, nk, dst, jdev, ostride, acc, astride);
+    };
+    auto update = [&](size_t hs, const double* h) {
+        if (nk <= KU)
+            PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, hs, h, w);
+        else
+            vcomb(n, V, ld, nk, jdev, hs, h, -1.0, up, w, s);
     };
     // pass 1
-    mdot(hcol, hstride, (double*)nullptr, (size_t)0);
-    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, hstride, hcol, w);
+    mdot(st, hstride, (double*)nullptr, (size_t)0);
+    update(hstride, st);
     // pass 2 (re-orthogonalisation); its coefficients are also added to the column
-    mdot(tmp2, (size_t)0, hcol, hstride);
-    PQ_LAUNCH(k_mupdate, g, VB, 0, s, n, V, ld, nk, jdev, (size_t)0, tmp2, w);
-}
-void orthogonalize(Ctx& c, int64_t n, const double* V, size_t ld, int nk, double* w, double* hcol, double* tmp2,
-                   hipStream_t s) {
-    orthogonalize_impl(c, n, V, ld, nk, nullptr, 0, w, hcol, tmp2, s);
-}
-void orthogonalize_j(Ctx& c, int64_t n, const double* V, size_t ld, int m, const int* jdev, double* w, double* st,
-                     double* tmp2, hipStream_t s) {
-    orthogonalize_impl(c, n, V, ld, m + 1, jdev, (size_t)(m + 1), w, st, tmp2, s);
+    mdot(tmp2, (size_t)0, st, hstride);
+    update((size_t)0, tmp2);
 }
 
 // V_{j+1} = w / h, h = sqrt(nrm2) stored into H(j+1, j); zero vector if h == 0
@@ -357,34 +433,9 @@ void normalize(int64_t n, const double* w, const double* nrm2, double* hsub, dou
     PQ_LAUNCH(k_normalize, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, w, nrm2, hsub, out);
 }
 
-// ---- small dense GMRES state (one thread) ------------------------------------
+// ---- small dense GMRES state ---------------------------------------------------
 // Layout of st (m = restart length): H (m+1) x m column-major at 0,
 // g[m+1] at GS_G, cs[m] at GS_C, sn[m] at GS_S, y[m] at GS_Y, scalars at GS_X.
-__global__ void k_givens(double* __restrict__ st, int m, int j, double* __restrict__ resid_out) {
-    if (threadIdx.x != 0) return;
-    double* H = st;
-    double* g = st + gs_g(m);
-    double* cs = st + gs_c(m);
-    double* sn = st + gs_s(m);
-    double* col = H + (size_t)j * (m + 1);
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-    }
-    const double a = col[j], b = col[j + 1];
-    const double r = hypot(a, b);
-    const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
-    cs[j] = c;
-    sn[j] = s;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    g[j + 1] = -s * g[j];
-    g[j] = c * g[j];
-    if (resid_out) *resid_out = fabs(g[j + 1]);
-}
-void givens(double* st, int m, int j, double* resid, hipStream_t s) { PQ_LAUNCH(k_givens, 1, 64, 0, s, st, m, j, resid); }
-
 // start of a cycle: g = (beta, 0, ...), beta = sqrt(nrm2)
 __global__ void k_gmres_start(double* __restrict__ st, int m, const double* __restrict__ nrm2) {
     if (threadIdx.x != 0) return;
@@ -394,20 +445,33 @@ __global__ void k_gmres_start(double* __restrict__ st, int m, const double* __re
 }
 void gmres_start(double* st, int m, const double* nrm2, hipStream_t s) { PQ_LAUNCH(k_gmres_start, 1, 64, 0, s, st, m, nrm2); }
 
-// y = R^-1 g for the first k columns
-__global__ void k_backsolve(double* __restrict__ st, int m, int k) {
-    if (threadIdx.x != 0) return;
+// y = R^-1 g for the first k columns, column by column: y_i = t_i / R_ii,
+// then t_r -= R_ri y_i for every r < i at once (column i of H is contiguous)
+constexpr int BS_T = 1024;
+__global__ __launch_bounds__(BS_T) void k_backsolve(double* __restrict__ st, int m, int k) {
+    extern __shared__ double t[];
+    __shared__ double yi;
     const double* H = st;
     const double* g = st + gs_g(m);
     double* y = st + gs_y(m);
+    for (int r = threadIdx.x; r < k; r += BS_T) t[r] = g[r];
+    __syncthreads();
     for (int i = k - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
-        const double d = H[(size_t)i * (m + 1) + i];
-        y[i] = d != 0.0 ? t / d : 0.0;
+        const double* col = H + (size_t)i * (m + 1);
+        if (threadIdx.x == 0) {
+            const double d = col[i];
+            yi = d != 0.0 ? t[i] / d : 0.0;
+            y[i] = yi;
+        }
+        __syncthreads();
+        const double v = yi;
+        for (int r = threadIdx.x; r < i; r += BS_T) t[r] -= col[r] * v;
+        __syncthreads();
     }
 }
-void backsolve(double* st, int m, int k, hipStream_t s) { PQ_LAUNCH(k_backsolve, 1, 64, 0, s, st, m, k); }
+void backsolve(double* st, int m, int k, hipStream_t s) {
+    if (k > 0) PQ_LAUNCH(k_backsolve, 1, BS_T, (size_t)k * sizeof(double), s, st, m, k);
+}
 
 // x += sum_k y[k] V_k
 __global__ void k_xupdate(int64_t n, const double* __restrict__ V, size_t ld, int nk, const double* __restrict__ y,
@@ -418,8 +482,11 @@ __global__ void k_xupdate(int64_t n, const double* __restrict__ V, size_t ld, in
         x[i] = acc;
     }
 }
-void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, hipStream_t s) {
-    PQ_LAUNCH(k_xupdate, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, V, ld, nk, y, x);
+void xupdate(int64_t n, const double* V, size_t ld, int nk, const double* y, double* x, double* up, hipStream_t s) {
+    if (nk <= KU)
+        PQ_LAUNCH(k_xupdate, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, V, ld, nk, y, x);
+    else
+        vcomb(n, V, ld, nk, (const int*)nullptr, (size_t)0, y, 1.0, up, x, s);
 }
 
 // QEQ energy: E = sum q chi + 1/2 sum u q^2 + 1/2 sum q phi  (shadow: 1/2 sum (2q - n) phi_n)
@@ -470,20 +537,13 @@ void normalize_j(int64_t n, const double* w, const double* nrm2, double* st, int
                  const int* jdev, hipStream_t s) {
     PQ_LAUNCH(k_normalize_j, std::min<int64_t>(cdiv(n, VB), 4096), VB, 0, s, n, w, nrm2, st, m, V, ld, jdev);
 }
-// Givens update of column j = *jdev; |g[j+1]| into hist[j]; then *jdev = j + 1
-__global__ void k_givens_j(double* __restrict__ st, int m, int* __restrict__ jdev, double* __restrict__ hist) {
-    if (threadIdx.x != 0) return;
-    const int j = *jdev;
-    double* H = st;
-    double* g = st + gs_g(m);
-    double* cs = st + gs_c(m);
-    double* sn = st + gs_s(m);
-    double* col = H + (size_t)j * (m + 1);
-    for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-    }
+// Givens update of column j = *jdev; |g[j+1]| into hist[j]; then *jdev = j + 1.
+// The earlier rotations apply in sequence (each one mixes the rows the next
+// one reads); the column and the rotations are staged in LDS first, so the
+// sequential part runs from LDS. Bases too long for LDS read them in place.
+constexpr int GV_T = 256;
+__device__ __forceinline__ void givens_tail(double* __restrict__ col, double* __restrict__ g, double* __restrict__ cs,
+                                            double* __restrict__ sn, int j, double* __restrict__ hist) {
     const double a = col[j], b = col[j + 1];
     const double r = hypot(a, b);
     const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
@@ -494,10 +554,52 @@ __global__ void k_givens_j(double* __restrict__ st, int m, int* __restrict__ jde
     g[j + 1] = -s * g[j];
     g[j] = c * g[j];
     hist[j] = fabs(g[j + 1]);
-    *jdev = j + 1;
+}
+__global__ __launch_bounds__(GV_T) void k_givens_j(double* __restrict__ st, int m, int* __restrict__ jdev,
+                                                   double* __restrict__ hist, int staged) {
+    extern __shared__ double sh[];
+    const int j = *jdev;
+    double* g = st + gs_g(m);
+    double* cs = st + gs_c(m);
+    double* sn = st + gs_s(m);
+    double* col = st + (size_t)j * (m + 1);
+    if (!staged) {
+        if (threadIdx.x == 0) {
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            givens_tail(col, g, cs, sn, j, hist);
+            *jdev = j + 1;
+        }
+        return;
+    }
+    double* lc = sh;              // rows 0..j+1 of the column
+    double* lcs = sh + (m + 1);   // cs[0..j-1]
+    double* lsn = lcs + m;        // sn[0..j-1]
+    for (int i = threadIdx.x; i <= j + 1; i += GV_T) lc[i] = col[i];
+    for (int i = threadIdx.x; i < j; i += GV_T) {
+        lcs[i] = cs[i];
+        lsn[i] = sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < j; ++i) {
+            const double t = lcs[i] * lc[i] + lsn[i] * lc[i + 1];
+            lc[i + 1] = -lsn[i] * lc[i] + lcs[i] * lc[i + 1];
+            lc[i] = t;
+        }
+        givens_tail(lc, g, cs, sn, j, hist);
+        *jdev = j + 1;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += GV_T) col[i] = lc[i];
 }
 void givens_j(double* st, int m, int* jdev, double* hist, hipStream_t s) {
-    PQ_LAUNCH(k_givens_j, 1, 64, 0, s, st, m, jdev, hist);
+    const size_t lds = (size_t)(3 * m + 1) * sizeof(double);
+    const int staged = lds <= 65536 ? 1 : 0;
+    PQ_LAUNCH(k_givens_j, 1, GV_T, staged ? lds : 0, s, st, m, jdev, hist, staged);
 }
 __global__ void k_set_int(int* __restrict__ p, int v) {
     if (threadIdx.x == 0) *p = v;
