@@ -306,6 +306,35 @@ void coulomb_eval_ws(Ctx& c, const double* q, double* phi, double* force, double
     E.commit();
 }
 
+void ensure_bilinear(Ctx& c) {
+    PQ_REQUIRE(c.prm.method == PQ_METHOD_PME, PQ_ERR_STATE, "the bilinear force path needs PME");
+    c.qv.ensure((size_t)c.ncl * CL * rsz(c));
+    c.qbrick2.ensure((size_t)c.n * rsz(c));
+    c.grid2.ensure((size_t)c.K[0] * c.K[1] * c.K[2] * rsz(c));
+}
+
+void coulomb_bilinear_force(Ctx& c, const double* u, const double* v, bool have_psi_v, double* force,
+                            hipStream_t s) {
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    ensure_eval(c);
+    ensure_red(c);
+    ensure_bilinear(c);
+    stage_charges2(c, u, v, s);
+    // the pair kernel beside the reciprocal chains, as in coulomb_eval
+    hipStream_t ps = s;
+    if (!c.serial) {
+        ensure_side(c);
+        ps = c.side;
+        ev_record(c.ev_fork, s);
+        stream_wait(ps, c.ev_fork);
+    }
+    pair_sum_bilinear(c, ps);
+    if (ps != s) ev_record(c.ev_join, ps);
+    pme_bilinear(c, have_psi_v, s);
+    if (ps != s) stream_wait(s, c.ev_join);
+    combine_force(c, force, s);
+}
+
 }  // namespace pq
 
 using namespace pq;

@@ -490,18 +490,34 @@ pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, doub
     const int64_t n = c.n;
     Work W(c, n_krylov);
     c.kf.ensure((size_t)n * 3);
-    // v = A n ; q[n] and lambda in closed form
+    // v = A n ; q[n] and lambda in closed form. With PME and a force to
+    // compute, the evaluation keeps its convolved grid of n for the bilinear
+    // force below.
+    const bool bil = force && c.prm.method == PQ_METHOD_PME;
+    if (bil) ensure_bilinear(c);
     double* phin = W.w(W_PHI);
-    coulomb_eval(c, n_vec, phin, nullptr, nullptr, s);
+    c.save_psi = bil;
+    try {
+        coulomb_eval(c, n_vec, phin, nullptr, nullptr, s);
+    } catch (...) {
+        c.save_psi = false;
+        throw;
+    }
+    c.save_psi = false;
     shadow_sums(c, n, chi, phin, eta, W.sc(5), s);
     shadow_q(n, chi, phin, eta, W.sc(5), q_tot, q_n, W.sc(7), s);
-    // shadow force F[q] - F[q - n]
+    // shadow force F[q] - F[q - n] = -d/dR 1/2 (2q - n)^T A n
     if (force) {
         double* d = W.w(W_D);
-        coulomb_eval(c, q_n, nullptr, force, nullptr, s);
-        axpby(n, 1.0, q_n, -1.0, n_vec, d, s);
-        coulomb_eval(c, d, nullptr, c.kf.p, nullptr, s);
-        axpby(3 * n, 1.0, force, -1.0, c.kf.p, force, s);
+        if (bil) {
+            axpby(n, 2.0, q_n, -1.0, n_vec, d, s);
+            coulomb_bilinear_force(c, d, n_vec, true, force, s);
+        } else {
+            coulomb_eval(c, q_n, nullptr, force, nullptr, s);
+            axpby(n, 1.0, q_n, -1.0, n_vec, d, s);
+            coulomb_eval(c, d, nullptr, c.kf.p, nullptr, s);
+            axpby(3 * n, 1.0, force, -1.0, c.kf.p, force, s);
+        }
     }
     if (energy) {
         double* a = W.w(W_D);
@@ -558,13 +574,19 @@ pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const do
     if (d_chi) axpby(n, -1.0, a, 0.0, nullptr, d_chi, s);
     if (d_eta) vmul(n, a, q_star, -1.0, d_eta, s);
     if (d_pos) {
+        // dL/dR = F[a + q] - F[a] - F[q] = -d/dR (a^T A q)
         double* aq = W.w(W_PHI);
-        axpby(n, 1.0, a, 1.0, q_star, aq, s);
-        coulomb_eval(c, aq, nullptr, d_pos, nullptr, s);
-        coulomb_eval(c, a, nullptr, c.kf.p, nullptr, s);
-        axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
-        coulomb_eval(c, q_star, nullptr, c.kf.p, nullptr, s);
-        axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
+        if (c.prm.method == PQ_METHOD_PME) {
+            axpby(n, 2.0, a, 0.0, nullptr, aq, s);
+            coulomb_bilinear_force(c, aq, q_star, false, d_pos, s);
+        } else {
+            axpby(n, 1.0, a, 1.0, q_star, aq, s);
+            coulomb_eval(c, aq, nullptr, d_pos, nullptr, s);
+            coulomb_eval(c, a, nullptr, c.kf.p, nullptr, s);
+            axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
+            coulomb_eval(c, q_star, nullptr, c.kf.p, nullptr, s);
+            axpby(3 * n, 1.0, d_pos, -1.0, c.kf.p, d_pos, s);
+        }
     }
     PQ_HIP(hipStreamSynchronize(s));
     return o.converged ? PQ_OK : PQ_WARN_NOT_CONVERGED;

@@ -369,15 +369,20 @@ __global__ __launch_bounds__(64 * REDUCE_ROWS) void k_spread_reduce(PmeGeo G, co
 // region of the convolved grid (staged row by row); eight lanes per atom,
 // lane y < p walks the (z, x) plane of stencil row y with the atom's stored
 // B-spline weights and derivatives.
-template <int P, bool FORCE, class T>
+// BIL: the two-charge (bilinear) reciprocal force of u (qbrick, convolved
+// grid psi_u in `grid`) and v (qbrick2, psi_v in `grid2`):
+//   F_i = -1/2 (u_i grad_i(theta . psi_v) + v_i grad_i(theta . psi_u)), no potential.
+template <int P, bool FORCE, bool BIL, class T>
 __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
                                                 const int* __restrict__ pme_idx, const V4<T>* __restrict__ pme_frac,
                                                 const T* __restrict__ pme_w, const T* __restrict__ qbrick,
-                                                const T* __restrict__ grid, T* __restrict__ phi_out,
+                                                const T* __restrict__ grid, const T* __restrict__ qbrick2,
+                                                const T* __restrict__ grid2, T* __restrict__ phi_out,
                                                 V4<T>* __restrict__ f_out) {
     constexpr int R = PME_B + P - 1;
     static_assert(R <= 16, "a region row must fit 16 lanes");
     __shared__ T lds[R * R * R];
+    __shared__ T lds2[BIL ? R * R * R : 1];
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
@@ -396,7 +401,11 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
             Y -= (Y >= G.K1) ? G.K1 : 0;
             Z += (Z < 0) ? G.K2 : 0;
             Z -= (Z >= G.K2) ? G.K2 : 0;
-            if (lx < R) lds[r * R + lx] = grid[((size_t)Z * G.K1 + Y) * G.K0 + X];
+            if (lx < R) {
+                const size_t gi = ((size_t)Z * G.K1 + Y) * G.K0 + X;
+                lds[r * R + lx] = grid[gi];
+                if (BIL) lds2[r * R + lx] = grid2[gi];
+            }
         }
     }
     __syncthreads();
@@ -408,10 +417,12 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
         const int k = s0 + grp + 32 * it;
         const bool valid = k < s1;
         T phi = 0, gxs = 0, gys = 0, gzs = 0;
+        T hxs = 0, hys = 0, hzs = 0;   // BIL: gradient sums on psi_v
         int i = -1;
-        T qq = 0;
+        T qq = 0, qv = 0;
         if (valid) {
             qq = qbrick[k];
+            if (BIL) qv = qbrick2[k];
             i = pme_idx[k];
             const int pk = unpack_int(pme_frac[k].w);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
@@ -429,7 +440,8 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
                 const int ly = gy - sub - y0;
 #pragma unroll
                 for (int tz = 0; tz < P; ++tz) {
-                    const T* row = lds + ((gz - tz - z0) * R + ly) * R + (gx - x0);
+                    const int off = ((gz - tz - z0) * R + ly) * R + (gx - x0);
+                    const T* row = lds + off;
                     T s = 0, sdx = 0;
 #pragma unroll
                     for (int tx = 0; tx < P; ++tx) {
@@ -437,24 +449,54 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
                         s = fma(wx[tx], v, s);
                         if (FORCE) sdx = fma(dx[tx], v, sdx);
                     }
-                    phi = fma(wys * wz[tz], s, phi);
+                    if (!BIL) phi = fma(wys * wz[tz], s, phi);
                     if (FORCE) {
                         gxs = fma(wys * wz[tz], sdx, gxs);
                         gys = fma(dys * wz[tz], s, gys);
                         gzs = fma(wys * dz[tz], s, gzs);
                     }
+                    if (BIL) {
+                        const T* row2 = lds2 + off;
+                        T s2 = 0, sdx2 = 0;
+#pragma unroll
+                        for (int tx = 0; tx < P; ++tx) {
+                            const T v = row2[-tx];
+                            s2 = fma(wx[tx], v, s2);
+                            sdx2 = fma(dx[tx], v, sdx2);
+                        }
+                        hxs = fma(wys * wz[tz], sdx2, hxs);
+                        hys = fma(dys * wz[tz], s2, hys);
+                        hzs = fma(wys * dz[tz], s2, hzs);
+                    }
                 }
             }
         }
         for (int o = 1; o < 8; o <<= 1) {
-            phi += __shfl_xor(phi, o, 64);
+            if (!BIL) phi += __shfl_xor(phi, o, 64);
             if (FORCE) {
                 gxs += __shfl_xor(gxs, o, 64);
                 gys += __shfl_xor(gys, o, 64);
                 gzs += __shfl_xor(gzs, o, 64);
             }
+            if (BIL) {
+                hxs += __shfl_xor(hxs, o, 64);
+                hys += __shfl_xor(hys, o, 64);
+                hzs += __shfl_xor(hzs, o, 64);
+            }
         }
-        if (valid && sub == 0) {
+        if (BIL && valid && sub == 0) {
+            // u_i (grad on psi_v) + v_i (grad on psi_u), then the chain factors
+            const T cx = T(0.5) * fma(qq, hxs, qv * gxs);
+            const T cy = T(0.5) * fma(qq, hys, qv * gys);
+            const T cz = T(0.5) * fma(qq, hzs, qv * gzs);
+            if (G.tric) {
+                const T jyx = (T)G.jyx, jzx = (T)G.jzx, jzy = (T)G.jzy;
+                f_out[i] = mk4<T>(-(kx * cx), -(ky * cy + jyx * cx), -((kz * cz + jzy * cy) + jzx * cx), T(0));
+            } else {
+                f_out[i] = mk4<T>(-kx * cx, -ky * cy, -kz * cz, T(0));
+            }
+        }
+        if (!BIL && valid && sub == 0) {
             phi_out[i] = phi;
             if (FORCE) {
                 if (G.tric) {
@@ -564,6 +606,12 @@ void pme_setup(Ctx& c) {
     fft_setup(c);
 }
 
+template <class T>
+__global__ void k_copy_grid(size_t n, const T* __restrict__ a, T* __restrict__ b) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        b[i] = a[i];
+}
+
 template <int P, class T>
 static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
                        const std::function<void()>& at_fork) {
@@ -581,13 +629,70 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
     fft_convolve(c, s);
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_FFT + 1], s));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER], s));
+    if (c.save_psi) {
+        // keep the convolved grid for a bilinear force evaluation that follows
+        const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
+        PQ_LAUNCH((k_copy_grid<T>), std::min<size_t>(cdiv(ng, 256), 8192), 256, 0, s, ng, as<T>(c.grid),
+                  as<T>(c.grid2));
+    }
     if (force)
-        PQ_LAUNCH((k_gather<P, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+        PQ_LAUNCH((k_gather<P, true, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p,
+                  as<v4>(c.pme_frac), as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), (const T*)nullptr,
+                  (const T*)nullptr, as<T>(c.phi_k), as<v4>(c.f_k));
     else
-        PQ_LAUNCH((k_gather<P, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
-                  as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.phi_k), as<v4>(c.f_k));
+        PQ_LAUNCH((k_gather<P, false, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p,
+                  as<v4>(c.pme_frac), as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), (const T*)nullptr,
+                  (const T*)nullptr, as<T>(c.phi_k), as<v4>(c.f_k));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER + 1], s));
+}
+
+// Bilinear reciprocal force of u (qbrick) and v (qbrick2) into c.f_k: the
+// convolved grid of v from grid2 (have_psi_v: kept by the last potential
+// evaluation of v, c.save_psi) or computed here, that of u into grid.
+template <int P, class T>
+static void pme_bilinear_p(Ctx& c, bool have_psi_v, hipStream_t s) {
+    using v4 = V4<T>;
+    PmeGeo G = geo(c);
+    const size_t ng = (size_t)c.K[0] * c.K[1] * c.K[2];
+    auto chain = [&](const T* q) {
+        PQ_LAUNCH((k_spread_stage<P, T>), c.nbrick, 64 * SW, 0, s, G, c.brick_start.p, as<v4>(c.pme_frac),
+                  as<T>(c.pme_w), q, as<T>(c.stage));
+        PQ_LAUNCH((k_spread_reduce<P, T>), cdiv(c.K[1] * c.K[2], REDUCE_ROWS), 64 * REDUCE_ROWS, 0, s, G,
+                  as<T>(c.stage), as<T>(c.grid));
+        fft_convolve(c, s);
+    };
+    if (!have_psi_v) {
+        chain(as<T>(c.qbrick2));
+        PQ_LAUNCH((k_copy_grid<T>), std::min<size_t>(cdiv(ng, 256), 8192), 256, 0, s, ng, as<T>(c.grid),
+                  as<T>(c.grid2));
+    }
+    chain(as<T>(c.qbrick));
+    PQ_LAUNCH((k_gather<P, true, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
+              as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.qbrick2), as<T>(c.grid2), as<T>(c.phi_k),
+              as<v4>(c.f_k));
+}
+
+template <class T>
+static void pme_bilinear_t(Ctx& c, bool have_psi_v, hipStream_t s) {
+    switch (c.P) {
+        case 3: pme_bilinear_p<3, T>(c, have_psi_v, s); break;
+        case 4: pme_bilinear_p<4, T>(c, have_psi_v, s); break;
+        case 5: pme_bilinear_p<5, T>(c, have_psi_v, s); break;
+        case 6: pme_bilinear_p<6, T>(c, have_psi_v, s); break;
+        case 7: pme_bilinear_p<7, T>(c, have_psi_v, s); break;
+        case 8: pme_bilinear_p<8, T>(c, have_psi_v, s); break;
+        default: throw Error(PQ_ERR_INVALID, "spline order must be in 3..8");
+    }
+}
+
+void pme_bilinear(Ctx& c, bool have_psi_v, hipStream_t s) {
+    const bool we = c.want_energy;
+    c.want_energy = false;   // no reciprocal energy for these chains
+    if (c.fp64)
+        pme_bilinear_t<double>(c, have_psi_v, s);
+    else
+        pme_bilinear_t<float>(c, have_psi_v, s);
+    c.want_energy = we;
 }
 
 template <class T>

@@ -305,6 +305,12 @@ struct Ctx {
     DBuf<unsigned char> stage;    // T: per-brick spreading regions (B+p-1)^3
     DBuf<unsigned char> spec;     // V2<T>: half spectrum (K1/2+1)*K2*K3
     DBuf<unsigned char> twid;     // V2<T>: FFT twiddles of the three axes
+    // bilinear (two-charge) force: the second charge vector per slot and in
+    // brick order, and the second convolved grid
+    DBuf<unsigned char> qv;       // T per slot
+    DBuf<unsigned char> qbrick2;  // T in brick order
+    DBuf<unsigned char> grid2;    // T, like grid
+    bool save_psi = false;        // the next PME evaluation copies its convolved grid to grid2
     DBuf<double> inftab;     // T and S tables (FP64)
     Fft1D fft[3];
     InfTab inf{};
@@ -410,6 +416,10 @@ int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs);
 // pair.hip: outputs in original atom order, without KE; force includes q_i
 void stage_charges(Ctx& c, const double* q, hipStream_t s);
 void pair_sum(Ctx& c, bool force, hipStream_t s);   // into c.phi_r, c.f_r
+// two charge vectors u (slots, qbrick) and v (qv, qbrick2); the bilinear pair
+// force 1/2 sum_j (u_i v_j + v_i u_j) f_ij into c.f_r
+void stage_charges2(Ctx& c, const double* u, const double* v, hipStream_t s);
+void pair_sum_bilinear(Ctx& c, hipStream_t s);
 // pme.hip
 void pme_setup(Ctx& c);
 // ev: 2*PQ_NPHASE timing events or NULL (spread, FFT and gather phases are recorded)
@@ -417,6 +427,9 @@ void pme_setup(Ctx& c);
 // kernel c.fork_at names (1: pass 1, 2: pass 2)
 void pme_eval(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipStream_t s,
               const std::function<void()>& at_fork = {});
+// bilinear reciprocal force of the staged u and v into c.f_k (PME; psi_v
+// from grid2 when have_psi_v, else computed)
+void pme_bilinear(Ctx& c, bool have_psi_v, hipStream_t s);
 // fft.hip
 void fft_setup(Ctx& c);
 void fft_convolve(Ctx& c, hipStream_t s);   // grid -> psi in place; energy partials into c.ews.part
@@ -430,12 +443,21 @@ void sum_vector_into(const double* x, int64_t n, double* out, double* part, hipS
 void dot_vector(Ctx& c, const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 // after the total charge is in c.ews.scal[0]
 void combine(Ctx& c, const double* q, double* phi, double* force, double* energy, hipStream_t s);
+// force = KE (c.f_r + c.f_k), FP64 n x 3
+void combine_force(Ctx& c, double* force, hipStream_t s);
 
 // high-level evaluation used by the ABI and the Krylov solvers (abi.cpp)
 void ensure_side(Ctx& c);   // creates the pair kernel's stream and fork/join events
 void ensure_red(Ctx& c);    // reduction partials and device scalars (part, qpart, scal)
 void coulomb_eval(Ctx& c, const double* q, double* phi, double* force, double* energy,
                   hipStream_t s);
+// Bilinear force F = -d/dR (1/2 u^T A(R) v) into force (device n x 3 FP64),
+// one pass of the pair list with both charge vectors and the PME chains of u
+// (and of v unless have_psi_v: its convolved grid kept in grid2 by the last
+// evaluation, which ran with c.save_psi). PME only.
+void coulomb_bilinear_force(Ctx& c, const double* u, const double* v, bool have_psi_v, double* force,
+                            hipStream_t s);
+void ensure_bilinear(Ctx& c);   // qv, qbrick2, grid2
 // the same on the reduction workspace c.ews as it stands (allocates nothing
 // once pq_set_system has sized the per-atom buffers)
 void coulomb_eval_ws(Ctx& c, const double* q, double* phi, double* force, double* energy,

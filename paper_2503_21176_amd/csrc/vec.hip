@@ -188,6 +188,25 @@ void combine(Ctx& c, const double* q, double* phi, double* force, double* energy
     if (energy) PQ_LAUNCH(k_energy_final, 1, VB, 0, s, c.ews.part, nb, c.ews.scal + 1, energy);
 }
 
+template <class T>
+__global__ void k_combine_force(int64_t n, const V4<T>* __restrict__ fr, const V4<T>* __restrict__ fk,
+                                double* __restrict__ force) {
+    for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
+        const V4<T> x = fr[i], y = fk[i];
+        force[3 * i + 0] = KE * ((double)x.x + (double)y.x);
+        force[3 * i + 1] = KE * ((double)x.y + (double)y.y);
+        force[3 * i + 2] = KE * ((double)x.z + (double)y.z);
+    }
+}
+void combine_force(Ctx& c, double* force, hipStream_t s) {
+    const int64_t n = c.n;
+    const unsigned g = std::min<int64_t>(cdiv(n, VB), 4096);
+    if (c.fp64)
+        PQ_LAUNCH(k_combine_force<double>, g, VB, 0, s, n, as<double4>(c.f_r), as<double4>(c.f_k), force);
+    else
+        PQ_LAUNCH(k_combine_force<float>, g, VB, 0, s, n, as<float4>(c.f_r), as<float4>(c.f_k), force);
+}
+
 // ---- elementwise kernels ----------------------------------------------------
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
                         double* __restrict__ z) {

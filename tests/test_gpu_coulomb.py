@@ -2,7 +2,8 @@
 
 Tolerances (FP32 bulk arithmetic, FP64 reductions), against the oracle run
 with the same alpha, cutoff, grid and order, so only rounding differs:
-  ||dphi||_2 / ||phi||_2 <= 1e-5,  ||dF||_rms / ||F||_rms <= 1e-5,  |dE|/|E| <= 1e-6.
+  ||dphi||_2 / ||phi||_2 <= 1e-5,  ||dF||_rms / ||F||_rms <= 1e-5,  |dE|/|E| <= 1e-6,
+and per atom max_i |dphi_i| / rms(phi) <= 1e-5, max_i |dF_i| / rms(|F|) <= 1e-5.
 Neighbour pair sets must match exactly.
 """
 import math
@@ -14,12 +15,14 @@ import torch
 
 import oracle as O
 import workloads as W
+from _parity import elem_err
 
 pytestmark = pytest.mark.gpu
 
 TOL_PHI = 1e-5
 TOL_F = 1e-5
 TOL_E = 1e-6
+TOL_ELEM = 1e-5
 
 
 def say(*a):
@@ -62,9 +65,12 @@ def check(name, phi, F, E, ref, rows=None, e_tol=TOL_E, energies=True):
     if rows is not None:
         phi, F = phi[rows], F[rows]
     ephi, ef = rel2(phi, rp), rms_rel(F, rf)
-    say(f"[{name}] phi rel {ephi:.2e}  F rms rel {ef:.2e}  max|dphi| {np.abs(phi - rp).max():.2e}")
+    mphi, mf = elem_err(phi, rp), elem_err(F, rf)
+    say(f"[{name}] phi rel {ephi:.2e}  F rms rel {ef:.2e}  per atom: phi {mphi:.2e} F {mf:.2e}")
     assert ephi <= TOL_PHI
     assert ef <= TOL_F
+    assert mphi <= TOL_ELEM
+    assert mf <= TOL_ELEM
     if energies:
         # relative to the magnitude of the three parts: for non-neutral or
         # strongly screened systems the total is a difference of large terms

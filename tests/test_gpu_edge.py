@@ -10,6 +10,7 @@ import torch
 
 import oracle as O
 import workloads as W
+from _parity import elem_err
 
 pytestmark = pytest.mark.gpu
 
@@ -66,10 +67,12 @@ def test_fft_paths(P, grid):
     phi, F, E = run(P, s.pos, s.q, box, P.make_params(box, rc, a, grid=grid, order=p))
     ref = O.spme_full(s.pos, s.q, box, a, rc, grid, p)
     ep, ef = rel2(phi, ref["phi"]), rms_rel(F, ref["F"])
+    mp, mf = elem_err(phi, ref["phi"]), elem_err(F, ref["F"])
     scale = abs(ref["E_real"]) + abs(ref["E_rec"]) + abs(ref["E_selfbg"])
     ee = abs(E[0] - ref["E"]) / scale
-    say(f"[fft {grid}] phi {ep:.2e} F {ef:.2e} E {ee:.2e}")
+    say(f"[fft {grid}] phi {ep:.2e} F {ef:.2e} E {ee:.2e} per atom: phi {mp:.2e} F {mf:.2e}")
     assert ep < TOL and ef < TOL and ee < 1e-6
+    assert mp < TOL and mf < TOL
     assert abs(E[2] - ref["E_rec"]) < 1e-6 * scale
 
 

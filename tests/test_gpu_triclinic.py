@@ -14,6 +14,7 @@ import torch
 
 import oracle as O
 import workloads as W
+from _parity import elem_err
 
 pytestmark = pytest.mark.gpu
 
@@ -58,10 +59,13 @@ def run(P, s, params):
 def check(name, got, ref, tol_phi=TOL_PHI, tol_f=TOL_F, tol_e=TOL_E):
     phi, F, E = got
     ephi, ef = rel2(phi, ref["phi"]), rms_rel(F, ref["F"])
+    mphi, mf = elem_err(phi, ref["phi"]), elem_err(F, ref["F"])
     scale = abs(ref["E_real"]) + abs(ref["E_rec"]) + abs(ref["E_selfbg"])
     eE = abs(E[0] - ref["E"]) / scale
-    say(f"[{name}] phi rel {ephi:.2e}  F rms rel {ef:.2e}  E {E[0]:.12g} vs {ref['E']:.12g} rel(parts) {eE:.2e}")
+    say(f"[{name}] phi rel {ephi:.2e}  F rms rel {ef:.2e}  per atom: phi {mphi:.2e} F {mf:.2e}  "
+        f"E {E[0]:.12g} vs {ref['E']:.12g} rel(parts) {eE:.2e}")
     assert ephi <= tol_phi and ef <= tol_f and eE <= tol_e
+    assert mphi <= 10 * tol_phi and mf <= 10 * tol_f
     for k, key in ((1, "E_real"), (2, "E_rec"), (3, "E_selfbg")):
         assert abs(E[k] - ref[key]) <= tol_e * scale
 
@@ -188,7 +192,10 @@ def test_triclinic_300k_sampled(P):
     rows = np.random.default_rng(2).choice(s.n, 48, replace=False)
     ref = O.spme_full(s.pos, s.q, s.box, a, 10.0, 144, 6, rows=rows)
     ephi, ef = rel2(phi[rows], ref["phi"]), rms_rel(F[rows], ref["F"])
-    say(f"[tric-300k] phi rel {ephi:.2e}  F rms rel {ef:.2e}  E_rec {E[2]:.10g} vs {ref['E_rec']:.10g}")
+    mphi, mf = elem_err(phi[rows], ref["phi"]), elem_err(F[rows], ref["F"])
+    say(f"[tric-300k] phi rel {ephi:.2e}  F rms rel {ef:.2e}  per atom: phi {mphi:.2e} F {mf:.2e}  "
+        f"E_rec {E[2]:.10g} vs {ref['E_rec']:.10g}")
     assert ephi <= TOL_PHI and ef <= TOL_F
+    assert mphi <= 10 * TOL_PHI and mf <= 10 * TOL_F
     assert abs(E[2] - ref["E_rec"]) <= 1e-5 * abs(ref["E_rec"])
     assert abs(E[0] - E[1:].sum()) <= 1e-12 * abs(E[0])
