@@ -164,8 +164,10 @@ def md_bench(n=3000, steps=200, dt=0.5, n_krylov=6, seed=41):
     """Shadow XL-BOMD (pq_md_run) on a random ionic system at 0.1 atoms/A^3:
     masses 16/23/35.5 amu, hardness U(20, 25) eV, 300 K start, the repulsive
     V_short stand-in (400 exp(-r/0.25 A) eV), K = 5 dissipation, PME at the
-    parameters for delta = 5e-4 and rc = 9 A, rebuild every step. Prints one
-    JSON line: ms per MD step and the total-energy statistics."""
+    parameters for delta = 5e-4 and rc = 9 A; once with a rebuild every step
+    (skin 0) and once with the paper's 1 A skin (list kept while every atom is
+    within 0.5 A of its build position). One JSON line per run: ms per MD
+    step, rebuilt steps and the total-energy statistics."""
     import torch
 
     import paper_2503_21176_amd as P
@@ -177,28 +179,33 @@ def md_bench(n=3000, steps=200, dt=0.5, n_krylov=6, seed=41):
     eta = rng.uniform(20.0, 25.0, n)
     mass = rng.choice([16.0, 23.0, 35.5], n)
     vel = rng.normal(0.0, 1.0, (n, 3)) * np.sqrt(0.02585 * 9.648533212331e-3 / mass)[:, None]
-    prm = P.choose_params(s.box, n, 9.0, 5e-4, 6, "pme")
-    ctx = P.Context(0)
-    pos = t(s.pos)
-    ctx.set_system(pos, prm)
-    r = ctx.qeq_solve(t(s.chi), t(eta), tol=1e-10, max_it=400, restart=100)
-    H = P.md_history(5)
-    hist = r.q.reshape(1, n).repeat(H, 1).contiguous()
-    v, m, chi, et = t(vel), t(mass), t(s.chi), t(eta)
-    ctx.md_run(pos, v, m, chi, et, hist, 5, dt_fs=dt, n_krylov=n_krylov, dissipation=5, rep_a=400.0, rep_rho=0.25)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e = ctx.md_run(pos, v, m, chi, et, hist, steps, dt_fs=dt, n_krylov=n_krylov, dissipation=5, rep_a=400.0,
-                   rep_rho=0.25)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    ctx.close()
-    tot, ke = e[:, 3], e[:, 0]
-    slope = float(np.polyfit(np.arange(len(tot)) * dt * 1e-3, tot, 1)[0])
-    print(json.dumps({"md": "shadow XL-BOMD", "n_atoms": n, "steps": steps, "dt_fs": dt, "n_krylov": n_krylov,
-                      "grid": list(prm.grid), "ms_per_md_step": round(ms, 4), "md_steps_per_s": round(1e3 / ms, 1),
-                      "e_tot_std_eV": float(tot.std()), "e_tot_drift_eV_per_ps": slope, "ke_std_eV": float(ke.std()),
-                      "ke_mean_eV": float(ke.mean())}), flush=True)
+    for skin in (0.0, 1.0):
+        prm = P.choose_params(s.box, n, 9.0, 5e-4, 6, "pme")
+        prm.skin = skin
+        ctx = P.Context(0)
+        pos = t(s.pos)
+        ctx.set_system(pos, prm)
+        r = ctx.qeq_solve(t(s.chi), t(eta), tol=1e-10, max_it=400, restart=100)
+        H = P.md_history(5)
+        hist = r.q.reshape(1, n).repeat(H, 1).contiguous()
+        v, m, chi, et = t(vel), t(mass), t(s.chi), t(eta)
+        ref = pos.clone()
+        kw = dict(dt_fs=dt, n_krylov=n_krylov, dissipation=5, rep_a=400.0, rep_rho=0.25, pos_ref=ref)
+        ctx.md_run(pos, v, m, chi, et, hist, 5, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e = ctx.md_run(pos, v, m, chi, et, hist, steps, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ctx.close()
+        tot, ke = e[:, 3], e[:, 0]
+        slope = float(np.polyfit(np.arange(len(tot)) * dt * 1e-3, tot, 1)[0])
+        print(json.dumps({"md": "shadow XL-BOMD", "n_atoms": n, "steps": steps, "dt_fs": dt, "n_krylov": n_krylov,
+                          "skin_A": skin, "rebuilt_steps": int(e[1:, 5].sum()),
+                          "grid": list(prm.grid), "ms_per_md_step": round(ms, 4),
+                          "md_steps_per_s": round(1e3 / ms, 1), "e_tot_std_eV": float(tot.std()),
+                          "e_tot_drift_eV_per_ps": slope, "ke_std_eV": float(ke.std()),
+                          "ke_mean_eV": float(ke.mean())}), flush=True)
 
 
 def md_sweep(n=300, steps=1000, dt=0.5, seed=51):

@@ -166,12 +166,28 @@ pq_status pq_destroy(pq_ctx* ctx);
  * x-y column) must stay below 2^24, else PQ_ERR_TOO_LARGE. */
 pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm);
 
+/* Moves the system's atoms to pos (device n x 3 FP64, the same atoms in the
+ * same order) and keeps the neighbour list when every atom is within skin/2
+ * of its position at the last full build: the list, built with radius
+ * rc + skin, then still holds every pair closer than rc (the paper's skin
+ * rule for re-neighbouring, Section "Performance"). The cluster-pair search
+ * is skipped; the atoms' list positions, the pair decisions (the canonical
+ * FP64 predicate at rc on the current positions, with image vectors that
+ * follow atoms across the cell faces) and the PME stencils are redone.
+ * Otherwise (an atom moved further, skin == 0, a triclinic cell) it is
+ * pq_set_system(pos) with the current parameters. *rebuilt (host, may be
+ * NULL) = 1 if a full build ran. Host-synchronising (the largest
+ * displacement is read back). */
+pq_status pq_update_positions(pq_ctx* ctx, const double* pos, int32_t* rebuilt);
+
 /* Number of neighbour pairs (i, j, n) with |w_j - w_i + n L| < rc + skin,
  * each unordered pair once (i < j, or i == j with the image vector n
  * lexicographically positive), evaluated with the canonical FP64 predicate
  * d.d < (rc+skin)^2 on the wrapped positions. Host-synchronising.
- * `pairs` (device int32, 5 x cap, row-major rows i, j, n0, n1, n2, in no
- * particular order) may be NULL to query the count only; if cap is too small
+ * After pq_update_positions kept the list, the pairs closer than rc (the
+ * kept list covers those), with the image vectors of the current wrapped
+ * positions. `pairs` (device int32, 5 x cap, row-major rows i, j, n0, n1,
+ * n2, in no particular order) may be NULL to query the count only; if cap is too small
  * the call returns PQ_ERR_CAPACITY with *n_pairs (host) set to the count. */
 pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs);
 
@@ -347,8 +363,11 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t);
  * (kappa = dt^2 omega^2). dissipation = 5 takes the weak-dissipation scheme
  * of extended-Lagrangian BOMD with K = 5 (kappa 1.82, alpha 0.018,
  * c = -6, 14, -8, -3, 4, -1); dissipation = 0 uses alpha = 0 and the given
- * kappa. The system is rebuilt (pq_set_system, the context's parameters) at
- * every step. V_short, the paper's trained short-range model, is not part of
+ * kappa. After each position update the system is moved with
+ * pq_update_positions: the neighbour list is kept while every atom stays
+ * within skin/2 of its position at the last full build (the context's
+ * pq_params.skin; skin 0 rebuilds every step) and rebuilt otherwise (the
+ * paper's skin rule, Section "Performance"). V_short, the paper's trained short-range model, is not part of
  * this library: a repulsive pair term rep_a exp(-r/rep_rho) over every pair
  * and image closer than the cutoff stands in for it (rep_a = 0: none; brute
  * force over all pairs, FP64, meant for test systems of a few thousand atoms).
@@ -374,17 +393,24 @@ typedef struct pq_md_cfg {
 } pq_md_cfg;
 
 /* Runs `steps` steps from the state in pos, vel (device n x 3 FP64, updated
- * in place; pos as accepted by pq_set_system, which the context must already
- * have received for these positions) and n_hist (device, pq_md_history()
- * vectors of n, newest first: n(t), n(t - dt), ...; updated in place).
- * mass (amu), chi, eta (= u): device n FP64. energies: host (steps + 1) x 5
- * FP64 or NULL, row t = {kinetic, potential (shadow energy E(R, q[n], n), or
- * the QEQ energy E(R, q) in regular mode), V_short, total, Coulomb
- * evaluations of that step's force evaluation} at step t (row 0: the initial
- * state). Host-synchronising. */
+ * in place; the context must already hold a system of n atoms and the
+ * parameters to run with, from pq_set_system) and n_hist (device,
+ * pq_md_history() vectors of n, newest first: n(t), n(t - dt), ...; updated
+ * in place). pos_ref (device n x 3 FP64, or NULL): the positions of the last
+ * full neighbour build; on entry the list is built there and moved to pos,
+ * on return it holds the positions of the run's last full build. NULL: the
+ * list is built at pos. (pos, vel, n_hist, pos_ref) is the whole state of
+ * a run: a run continued from a saved copy of it, in a fresh context with the
+ * same parameters, repeats the uninterrupted run bit for bit (for a fresh
+ * start pass a copy of pos as pos_ref). mass (amu), chi, eta (= u): device n
+ * FP64. energies: host (steps + 1) x 6 FP64 or NULL, row t = {kinetic,
+ * potential (shadow energy E(R, q[n], n), or the QEQ energy E(R, q) in
+ * regular mode), V_short, total, Coulomb evaluations of that step's force
+ * evaluation, 1 if the neighbour list was rebuilt for it (else 0)} at step t
+ * (row 0: the initial state). Host-synchronising. */
 pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const double* mass, const double* chi,
-                    const double* eta, double q_tot, double* n_hist, int32_t steps, const pq_md_cfg* cfg,
-                    double* energies);
+                    const double* eta, double q_tot, double* n_hist, double* pos_ref, int32_t steps,
+                    const pq_md_cfg* cfg, double* energies);
 /* Number of n vectors pq_md_run keeps for a dissipation setting (2 or 6). */
 int32_t pq_md_history(int32_t dissipation);
 

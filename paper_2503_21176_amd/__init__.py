@@ -33,7 +33,7 @@ EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create"
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
            "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history", "pq_coulomb_noalloc",
-           "pq_set_solver"]
+           "pq_set_solver", "pq_update_positions"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -109,6 +109,7 @@ def load() -> ctypes.CDLL:
         "pq_coulomb": (i32, [vp, vp, vp, vp, vp]),
         "pq_coulomb_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "pq_set_solver": (i32, [vp, i32, i32]),
+        "pq_update_positions": (i32, [vp, vp, ctypes.POINTER(i32)]),
         "pq_set_timing": (i32, [vp, i32]),
         "pq_timings": (i32, [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
         "pq_qeq_solve": (i32, [vp, vp, vp, dbl, dbl, i32, i32, vp, vp, vp, vp, ctypes.POINTER(SolveInfo)]),
@@ -123,7 +124,7 @@ def load() -> ctypes.CDLL:
         "pq_set_tuning": (i32, [vp, ctypes.POINTER(TuneResult)]),
         "pq_choose_params": (i32, [ctypes.POINTER(dbl), i64, dbl, dbl, i32, i32, ctypes.POINTER(Params)]),
         "pq_auto_pme_min_atoms": (i64, []),
-        "pq_md_run": (i32, [vp, vp, vp, vp, vp, vp, dbl, vp, i32, ctypes.POINTER(MdCfg), vp]),
+        "pq_md_run": (i32, [vp, vp, vp, vp, vp, vp, dbl, vp, vp, i32, ctypes.POINTER(MdCfg), vp]),
         "pq_md_history": (i32, [i32]),
     }
     for name, (res, args) in sig.items():
@@ -191,6 +192,24 @@ MD_SHADOW, MD_REGULAR = 0, 1
 def md_history(dissipation: int) -> int:
     """Number of n vectors the shadow-MD driver keeps (newest first)."""
     return int(load().pq_md_history(int(dissipation)))
+
+
+def md_state_save(path, pos, vel, n_hist, pos_ref):
+    """Writes the state of an MD run (positions, velocities, extended-charge
+    history, positions of the last full neighbour build) to a .npz file; a
+    run continued from md_state_load in a fresh context with the same
+    parameters repeats the uninterrupted run bit for bit."""
+    np.savez(path, pos=pos.detach().cpu().numpy(), vel=vel.detach().cpu().numpy(),
+             n_hist=n_hist.detach().cpu().numpy(), pos_ref=pos_ref.detach().cpu().numpy())
+
+
+def md_state_load(path, device=0):
+    """The state md_state_save wrote, as FP64 tensors on `device`:
+    (pos, vel, n_hist, pos_ref)."""
+    with np.load(path, allow_pickle=False) as z:
+        dev = torch.device("cuda", device)
+        return tuple(torch.as_tensor(np.ascontiguousarray(z[k]), dtype=torch.float64, device=dev)
+                     for k in ("pos", "vel", "n_hist", "pos_ref"))
 
 
 def choose_params(box, n, cutoff, delta=5e-4, order=6, method="auto", fp64=False) -> Params:
@@ -294,6 +313,15 @@ class Context:
         _check(self.lib.pq_set_system(self.h, n, _ptr(pos), ctypes.byref(params)))
         self.n, self.params = n, params
 
+    def update_positions(self, pos: torch.Tensor) -> bool:
+        """Moves the atoms, keeping the neighbour list while every atom is
+        within skin/2 of its last build position; returns True if it rebuilt."""
+        pos = self._vec(pos, self.n, "pos", 3)
+        r = ctypes.c_int32()
+        self._sync_stream()
+        _check(self.lib.pq_update_positions(self.h, _ptr(pos), ctypes.byref(r)))
+        return bool(r.value)
+
     def neighbor_count(self) -> int:
         cnt = ctypes.c_int64()
         self._sync_stream()
@@ -387,16 +415,21 @@ class Context:
         return q, f, x, e
 
     def md_run(self, pos, vel, mass, chi, eta, n_hist, steps, dt_fs=0.5, n_krylov=8, dissipation=5, kappa=1.82,
-               rep_a=0.0, rep_rho=0.3, q_tot=0.0, regular=False, tol=1e-6, max_it=200, restart=50):
+               rep_a=0.0, rep_rho=0.3, q_tot=0.0, regular=False, tol=1e-6, max_it=200, restart=50, pos_ref=None):
         """Shadow XL-BOMD steps, or regular BO-MD steps with QEQ solves to
         ``tol`` (pq_md_run). pos, vel (n x 3), n_hist (md_history(dissipation)
-        x n, newest first; regular mode: row 0 the start charges) are FP64
-        device tensors updated in place; the context must hold the system at
-        pos. Returns the (steps + 1) x 5 rows {kinetic, potential, V_short,
-        total (eV), Coulomb evaluations of the step}."""
+        x n, newest first; regular mode: row 0 the start charges) and pos_ref
+        (n x 3 or None: positions of the last full neighbour build, see
+        md_state) are FP64 device tensors updated in place; the context holds
+        the run's parameters (pq_set_system). Returns the (steps + 1) x 6 rows
+        {kinetic, potential, V_short, total (eV), Coulomb evaluations of the
+        step, 1 if the neighbour list was rebuilt for the step}."""
         N = self.n
         H = md_history(dissipation)
-        for t, shape, name in ((pos, (N, 3), "pos"), (vel, (N, 3), "vel"), (n_hist, (H, N), "n_hist")):
+        shapes = [(pos, (N, 3), "pos"), (vel, (N, 3), "vel"), (n_hist, (H, N), "n_hist")]
+        if pos_ref is not None:
+            shapes.append((pos_ref, (N, 3), "pos_ref"))
+        for t, shape, name in shapes:
             if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous()
                     and tuple(t.shape) == shape and t.device == self.device):
                 raise ValueError(f"{name} must be a contiguous FP64 tensor of shape {shape} on {self.device}")
@@ -404,10 +437,11 @@ class Context:
         chi, eta = self._vec(chi, N, "chi"), self._vec(eta, N, "eta")
         cfg = MdCfg(float(dt_fs), int(n_krylov), int(dissipation), float(kappa), float(rep_a), float(rep_rho),
                     MD_REGULAR if regular else MD_SHADOW, int(max_it), int(restart), 0, float(tol))
-        e = np.zeros((int(steps) + 1, 5), dtype=np.float64)
+        e = np.zeros((int(steps) + 1, 6), dtype=np.float64)
         self._sync_stream()
         _check(self.lib.pq_md_run(self.h, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(chi), _ptr(eta), float(q_tot),
-                                  _ptr(n_hist), int(steps), ctypes.byref(cfg), e.ctypes.data_as(ctypes.c_void_p)))
+                                  _ptr(n_hist), _ptr(pos_ref), int(steps), ctypes.byref(cfg),
+                                  e.ctypes.data_as(ctypes.c_void_p)))
         return e
 
     def qeq_vjp(self, chi, eta, q_star, gbar=None, tol=1e-8, max_it=1000, with_status=False):

@@ -442,6 +442,37 @@ pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_para
     PQ_API_END
 }
 
+pq_status pq_update_positions(pq_ctx* ctx, const double* pos, int32_t* rebuilt) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && pos != nullptr, PQ_ERR_INVALID, "ctx or pos is NULL");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    // the list radius rc + skin covers every pair closer than rc while no
+    // atom has moved more than skin/2 since the build
+    bool keep = c.prm.skin > 0.0 && !is_tric(c.prm) && c.pos_build.n >= (size_t)c.n * 3;
+    if (keep) {
+        const double d2 = nbr_max_disp2(c, pos);
+        const double h = 0.5 * c.prm.skin;
+        keep = d2 <= h * h;   // false for a NaN displacement
+    }
+    if (rebuilt) *rebuilt = keep ? 0 : 1;
+    const pq_params prm = c.prm;
+    if (!keep) return pq_set_system(ctx, c.n, pos, &prm);
+    c.have_system = false;
+    ++c.gen;
+    nbr_refresh(c, pos);
+    if (c.prm.method == PQ_METHOD_PME)
+        pme_setup(c);
+    else
+        ewald_setup(c);
+    ensure_eval(c);
+    c.have_system = true;
+    return PQ_OK;
+    PQ_API_END
+}
+
 pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && n_pairs != nullptr, PQ_ERR_INVALID, "ctx or n_pairs is NULL");

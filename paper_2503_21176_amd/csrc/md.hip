@@ -8,7 +8,8 @@
 //   v += dt/2 F/m ;  R += dt v                      (velocity Verlet)
 //   n(t+dt) = 2 n(t) - n(t-dt) + kappa x(t) + alpha sum_k c_k n(t-k dt)
 //                                                   (kappa = dt^2 omega^2)
-//   rebuild at R(t+dt); shadow step at (R, n)(t+dt) -> F, x, E_shadow
+//   move the system to R(t+dt) (neighbour list kept within the skin rule);
+//   shadow step at (R, n)(t+dt) -> F, x, E_shadow
 //   v += dt/2 F/m
 // The n update is the time-reversible Verlet step of extended-Lagrangian
 // BOMD with the weak dissipation of Niklasson et al. (J. Chem. Phys. 130,
@@ -40,7 +41,7 @@ namespace pq {
 
 constexpr double ACC_PER_EV_A_AMU = 9.648533212331e-3;   // (eV/A)/amu in A/fs^2
 constexpr int MD_TILE = 256;
-constexpr int MD_COLS = 5;   // kinetic, potential, V_short, total, Coulomb evaluations
+constexpr int MD_COLS = 6;   // kinetic, potential, V_short, total, Coulomb evaluations, list rebuilt
 
 __global__ void k_md_kick(int64_t n3, double* __restrict__ v, const double* __restrict__ f,
                           const double* __restrict__ m, double c) {
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(MD_TILE) void k_md_short(int n, const double* __res
 }
 
 __global__ void k_md_record(const double* __restrict__ kin_part, int nk, const double* __restrict__ sr_part, int ns,
-                            const double* __restrict__ e_pot, double evals, double* __restrict__ row) {
+                            const double* __restrict__ e_pot, double evals, double rebuilt, double* __restrict__ row) {
     // one wavefront: lane-strided partial sums, then a fixed butterfly
     if (blockIdx.x != 0 || threadIdx.x >= 64) return;
     double ke = 0.0, es = 0.0;
@@ -166,6 +167,7 @@ __global__ void k_md_record(const double* __restrict__ kin_part, int nk, const d
     row[2] = es;
     row[3] = (ke + e_pot[0]) + es;
     row[4] = evals;
+    row[5] = rebuilt;
 }
 
 void set_error(const std::string& m);
@@ -178,7 +180,7 @@ static void check(pq_status st) {
 static int md_history(int dissipation) { return dissipation == 5 ? 6 : 2; }
 
 void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* chi, const double* eta,
-            double q_tot, double* n_hist, int steps, const pq_md_cfg& cfg, double* energies) {
+            double q_tot, double* n_hist, double* pos_ref, int steps, const pq_md_cfg& cfg, double* energies) {
     PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
     PQ_REQUIRE(!is_tric(c.prm), PQ_ERR_BOX, "the MD driver takes orthorhombic boxes (zero tilts)");
     PQ_REQUIRE(std::isfinite(cfg.dt_fs) && cfg.dt_fs > 0.0, PQ_ERR_INVALID, "dt_fs must be > 0");
@@ -225,9 +227,21 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
         PQ_HIP(hipMemcpyAsync(qprev.p, n_hist, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
     }
     double evals = 0.0;   // Coulomb evaluations of the current force evaluation
+    double rebuilt = 0.0;
     int head = 0;   // n_hist is newest first on entry
+    pq_ctx* h = reinterpret_cast<pq_ctx*>(&c);
     auto forces = [&](int row) {
-        check(pq_set_system(reinterpret_cast<pq_ctx*>(&c), n, pos, &prm));
+        int32_t rb = 1;
+        if (row == 0 && pos_ref) {
+            // the list of the interrupted run: built at pos_ref, moved to pos
+            check(pq_set_system(h, n, pos_ref, &prm));
+            check(pq_update_positions(h, pos, &rb));
+        } else if (row == 0) {
+            check(pq_set_system(h, n, pos, &prm));
+        } else {
+            check(pq_update_positions(h, pos, &rb));
+        }
+        rebuilt = rb ? 1.0 : 0.0;
         if (regular) {
             pq_solve_info info{};
             const pq_status st = pq_qeq_solve(reinterpret_cast<pq_ctx*>(&c), chi, eta, q_tot, cfg.tol, cfg.max_it,
@@ -238,7 +252,9 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
         } else {
             check(pq_shadow_step(reinterpret_cast<pq_ctx*>(&c), chi, eta, q_tot, n_hist + (size_t)head * n,
                                  cfg.n_krylov, qn.p, f.p, x.p, esh.p));
-            evals = 3.0 + cfg.n_krylov;      // potential of n, two force evaluations, Krylov products
+            // potential of n, the shadow force (PME: one bilinear evaluation,
+            // counted as two), Krylov products
+            evals = 3.0 + cfg.n_krylov;
         }
         if (cfg.rep_a > 0.0)
             PQ_LAUNCH(k_md_short, sb, MD_TILE, 0, s, (int)n, c.w64.p, prm.box[0], prm.box[1], prm.box[2],
@@ -248,7 +264,7 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
     auto record = [&](int row) {
         PQ_LAUNCH(k_md_kinetic, kb, MD_TILE, 0, s, n, (const double*)vel, mass, kin.p);
         PQ_LAUNCH(k_md_record, 1, 64, 0, s, (const double*)kin.p, kb, (const double*)srp.p,
-                  cfg.rep_a > 0.0 ? sb : 0, (const double*)esh.p, evals, rows.p + (size_t)MD_COLS * row);
+                  cfg.rep_a > 0.0 ? sb : 0, (const double*)esh.p, evals, rebuilt, rows.p + (size_t)MD_COLS * row);
     };
     try {
         forces(0);
@@ -273,6 +289,11 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
             PQ_HIP(hipMemcpyAsync(n_hist, hist2.p, sizeof(double) * H * n, hipMemcpyDeviceToDevice, s));
         }
         if (regular) PQ_HIP(hipMemcpyAsync(n_hist, qprev.p, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        // positions of the last full build (with skin 0 every step rebuilt)
+        if (pos_ref) {
+            const double* last = (prm.skin > 0.0 && c.pos_build.n >= (size_t)n * 3) ? c.pos_build.p : pos;
+            PQ_HIP(hipMemcpyAsync(pos_ref, last, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        }
         if (energies)
             PQ_HIP(hipMemcpyAsync(energies, rows.p, sizeof(double) * MD_COLS * (steps + 1), hipMemcpyDeviceToHost, s));
         PQ_HIP(hipStreamSynchronize(s));
@@ -288,15 +309,15 @@ void md_run(Ctx& c, double* pos, double* vel, const double* mass, const double* 
 using namespace pq;
 
 extern "C" pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const double* mass, const double* chi,
-                               const double* eta, double q_tot, double* n_hist, int32_t steps, const pq_md_cfg* cfg,
-                               double* energies) {
+                               const double* eta, double q_tot, double* n_hist, double* pos_ref, int32_t steps,
+                               const pq_md_cfg* cfg, double* energies) {
     try {
         PQ_REQUIRE(ctx && pos && vel && mass && chi && eta && n_hist && cfg, PQ_ERR_INVALID,
                    "ctx, pos, vel, mass, chi, eta, n_hist and cfg must not be NULL");
         Ctx& c = *reinterpret_cast<Ctx*>(ctx);
         AllocScope alloc_scope(c);
         PQ_HIP(hipSetDevice(c.device));
-        md_run(c, pos, vel, mass, chi, eta, q_tot, n_hist, steps, *cfg, energies);
+        md_run(c, pos, vel, mass, chi, eta, q_tot, n_hist, pos_ref, steps, *cfg, energies);
         return PQ_OK;
     } catch (const Error& e) {
         set_error(e.what());

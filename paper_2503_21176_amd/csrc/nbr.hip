@@ -540,9 +540,16 @@ __device__ __forceinline__ long long inv_mod(long long s, long long n) {
     return t0 < 0 ? t0 + n : t0;
 }
 
+// cw, kimg (both NULL after a full build): a list kept across moves
+// (nbr_refresh). Then cpos holds the continuous positions x = w + k L since
+// the build (entry positions), cw the canonical wrap w of the current
+// positions and kimg the lattice steps k between the two, and the pair
+// (i, j) of a cluster pair with image n has the canonical image
+// n + k_j - k_i, on which the FP64 predicate decides.
 template <bool FILL, class T>
 __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                const int2* __restrict__ lj, const double4* __restrict__ cpos,
+                                               const double4* __restrict__ cw, const int4* __restrict__ kimg,
                                                const double* __restrict__ ref, unsigned char* __restrict__ jmask,
                                                int* __restrict__ jcount, const int* __restrict__ jstart,
                                                V4<T>* __restrict__ jl) {
@@ -550,17 +557,23 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
     const int ic = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (ic >= ncl) return;
     const double rc2 = g.rc * g.rc;
+    const bool moved = kimg != nullptr;
     // the i-cluster's atoms (the same in every lane)
     bool ireal[CL];
     double wi[CL][3];
+    int ki[CL][3];
     if (!FILL) {
 #pragma unroll
         for (int a = 0; a < CL; ++a) {
-            const double4 p = cpos[(size_t)ic * CL + a];
+            const double4 p = (moved ? cw : cpos)[(size_t)ic * CL + a];
             ireal[a] = p.w != 0.0;
             wi[a][0] = p.x;
             wi[a][1] = p.y;
             wi[a][2] = p.z;
+            const int4 k = moved ? kimg[(size_t)ic * CL + a] : make_int4(0, 0, 0, 0);
+            ki[a][0] = k.x;
+            ki[a][1] = k.y;
+            ki[a][2] = k.z;
         }
     }
     const double r0 = ref[3 * ic], r1 = ref[3 * ic + 1], r2 = ref[3 * ic + 2];
@@ -611,11 +624,26 @@ __global__ __launch_bounds__(256) void k_jlist(int ncl, Geom g, const int* __res
             double sx, sy, sz;
             lattice_vec(n0, n1, n2, g.L, g.t, sx, sy, sz);
             if (!FILL) {
-                const double wj[3] = {pj.x, pj.y, pj.z};
+                if (moved) {
+                    const size_t js = (size_t)je.x * CL + b;
+                    const double4 w4 = cw[js];
+                    const int4 kj = kimg[js];
+                    const double wj[3] = {w4.x, w4.y, w4.z};
 #pragma unroll
-                for (int a = 0; a < CL; ++a) {
-                    const double d2 = canon_d2s(wi[a], wj, sx, sy, sz);
-                    if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                    for (int a = 0; a < CL; ++a) {
+                        double tx, ty, tz;
+                        lattice_vec(n0 + kj.x - ki[a][0], n1 + kj.y - ki[a][1], n2 + kj.z - ki[a][2], g.L, g.t, tx,
+                                    ty, tz);
+                        const double d2 = canon_d2s(wi[a], wj, tx, ty, tz);
+                        if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                    }
+                } else {
+                    const double wj[3] = {pj.x, pj.y, pj.z};
+#pragma unroll
+                    for (int a = 0; a < CL; ++a) {
+                        const double d2 = canon_d2s(wi[a], wj, sx, sy, sz);
+                        if (ireal[a] && d2 > 0.0 && d2 < rc2) col |= 1 << a;
+                    }
                 }
             }
             p0 = pj.x + sx;
@@ -650,18 +678,24 @@ __global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
 // pairs, reserves that many rows with one atomic on the global counter and,
 // when `out` is given, walks the list again to write them; rows beyond `cap`
 // are not written but still counted.
+// With kimg (a list kept across moves, see k_jlist) the positions are the
+// canonical wraps cw, the image of a pair is n + k_j - k_i, and the radius is
+// the cutoff (the kept list covers the pairs closer than rc, not rc + skin).
 __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                 const int2* __restrict__ lj, const int* __restrict__ orig,
-                                                const double4* __restrict__ cpos, int64_t cap,
-                                                int32_t* __restrict__ out, unsigned long long* __restrict__ counter) {
+                                                const double4* __restrict__ cpos, const int4* __restrict__ kimg,
+                                                int64_t cap, int32_t* __restrict__ out,
+                                                unsigned long long* __restrict__ counter) {
     const int lane = lane_id();
     const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ic >= ncl) return;
     const int a = lane >> 3, b = lane & 7;
     const int i = orig[(size_t)ic * CL + a];
     const double4 pi4 = cpos[(size_t)ic * CL + a];
+    const int4 ki = kimg ? kimg[(size_t)ic * CL + a] : make_int4(0, 0, 0, 0);
     const double wi[3] = {pi4.x, pi4.y, pi4.z};
-    const double rl2 = g.rlist * g.rlist;
+    const double rl = kimg ? g.rc : g.rlist;
+    const double rl2 = rl * rl;
     const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
     auto pair_at = [&](size_t e, int& j, int& n0, int& n1, int& n2) -> bool {
         const int2 je = lj[e];
@@ -669,6 +703,12 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
         j = orig[slot];
         const double4 pj = cpos[slot];
         unpack_img(je.y, n0, n1, n2);
+        if (kimg) {
+            const int4 kj = kimg[slot];
+            n0 += kj.x - ki.x;
+            n1 += kj.y - ki.y;
+            n2 += kj.z - ki.z;
+        }
         bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
         if (ok) {
             const double wj[3] = {pj.x, pj.y, pj.z};
@@ -857,10 +897,12 @@ void nbr_build(Ctx& c, const double* pos) {
         // atom-level j lists for the pair kernel: count pass
         if (c.fp64)
             PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p,
-                      c.cl_pos.p, c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (double4*)nullptr);
+                      c.cl_pos.p, (const double4*)nullptr, (const int4*)nullptr, c.cl_ref.p, c.jmask.p, c.jcount.p,
+                      (const int*)nullptr, (double4*)nullptr);
         else
             PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p,
-                      c.cl_pos.p, c.cl_ref.p, c.jmask.p, c.jcount.p, (const int*)nullptr, (float4*)nullptr);
+                      c.cl_pos.p, (const double4*)nullptr, (const int4*)nullptr, c.cl_ref.p, c.jmask.p, c.jcount.p,
+                      (const int*)nullptr, (float4*)nullptr);
         scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
         PQ_HIP(hipMemcpyAsync(&hv[2], c.flag.p + 2, sizeof(int), hipMemcpyDeviceToHost, s));
         PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -871,27 +913,162 @@ void nbr_build(Ctx& c, const double* pos) {
         c.lcap = mx + mx / 8 + 8;
     }
     const int rows = hv[3];
+    c.moved = false;
+    jlist_fill(c, rows);
+    // positions of this build, for the moves that keep the list
+    if (p.skin > 0.0) {
+        c.pos_build.ensure((size_t)n * 3);
+        c.cl_pos0.ensure(nslot);
+        PQ_HIP(hipMemcpyAsync(c.pos_build.p, pos, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        PQ_HIP(hipMemcpyAsync(c.cl_pos0.p, c.cl_pos.p, sizeof(double4) * nslot, hipMemcpyDeviceToDevice, s));
+    }
+}
+
+// The atom-level j lists from the counted rows: the far-away tail, then the
+// fill pass (canonical images of a kept list when c.moved).
+void jlist_fill(Ctx& c, int rows) {
+    hipStream_t s = c.stream;
+    const int ncl = c.ncl;
+    const Geom& g = c.g;
     PQ_REQUIRE(rows >= 0, PQ_ERR_BOX, "atom list overflow");
     c.njrows = rows;
     // JL_TAIL far-away entries after the last row keep the pair kernel's
     // look-ahead loads in bounds
     c.jl.ensure(((size_t)rows * CL + JL_TAIL) * 4 * rsz(c));
+    const double4* cw = c.moved ? c.cl_w.p : nullptr;
+    const int4* kimg = c.moved ? c.cl_k.p : nullptr;
     if (c.fp64)
         PQ_LAUNCH(k_far_entries<double>, 1, 256, 0, s, as<double4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     else
         PQ_LAUNCH(k_far_entries<float>, 1, 256, 0, s, as<float4>(c.jl) + (size_t)rows * CL, JL_TAIL);
     if (c.fp64)
         PQ_LAUNCH((k_jlist<true, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
+                  cw, kimg, c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<double4>(c.jl));
     else
         PQ_LAUNCH((k_jlist<true, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
-                  c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
+                  cw, kimg, c.cl_ref.p, c.jmask.p, c.jcount.p, c.jstart.p, as<float4>(c.jl));
+}
+
+// ---- moves that keep the list ------------------------------------------------
+// Largest squared displacement of an atom since the build (block partials).
+__global__ __launch_bounds__(256) void k_disp2(int n, const double* __restrict__ pos, const double* __restrict__ pos0,
+                                               double* __restrict__ part) {
+    __shared__ double red[4];
+    double m = 0.0;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double dx = pos[3 * (size_t)i] - pos0[3 * (size_t)i];
+        const double dy = pos[3 * (size_t)i + 1] - pos0[3 * (size_t)i + 1];
+        const double dz = pos[3 * (size_t)i + 2] - pos0[3 * (size_t)i + 2];
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        m = (d2 > m || d2 != d2) ? d2 : m;   // a NaN displacement wins (forces a rebuild)
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(m, o, 64);
+        m = (t > m || t != t) ? t : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r = red[0];
+        for (int k = 1; k < 4; ++k) r = (red[k] > r || red[k] != red[k]) ? red[k] : r;
+        part[blockIdx.x] = r;
+    }
+}
+__global__ void k_max_part(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double r = 0.0;
+    for (int k = 0; k < nb; ++k) r = (part[k] > r || part[k] != part[k]) ? part[k] : r;
+    *out = r;
+}
+
+// Per slot: continuous position x = (build wrap) + (pos - pos at build), the
+// canonical wrap w of pos, the lattice steps k = (x - w)/L, the pair kernel's
+// position x - ref, and w into w64 (original order). Orthorhombic cells.
+template <class T>
+__global__ void k_refresh(int nslot, const int* __restrict__ orig, const double* __restrict__ pos,
+                          const double* __restrict__ pos0, const double4* __restrict__ cpos0, Geom g,
+                          const double* __restrict__ ref, double4* __restrict__ cpos, double4* __restrict__ cw,
+                          int4* __restrict__ kimg, V4<T>* __restrict__ xyzq, double* __restrict__ w64) {
+    const int sl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= nslot) return;
+    const int i = orig[sl];
+    if (i < 0) {
+        cw[sl] = make_double4(0.0, 0.0, 0.0, 0.0);
+        kimg[sl] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    const double4 p0 = cpos0[sl];
+    double x[3], w[3];
+    int k[3];
+    const double b0[3] = {p0.x, p0.y, p0.z};
+    for (int d = 0; d < 3; ++d) {
+        const double pd = pos[3 * (size_t)i + d];
+        x[d] = b0[d] + (pd - pos0[3 * (size_t)i + d]);
+        w[d] = canon_wrap(pd, g.L[d], g.invL[d]);
+        k[d] = (int)rint((x[d] - w[d]) * g.invL[d]);
+        w64[3 * (size_t)i + d] = w[d];
+    }
+    const int c = sl / CL;
+    cpos[sl] = make_double4(x[0], x[1], x[2], 1.0);
+    cw[sl] = make_double4(w[0], w[1], w[2], 1.0);
+    kimg[sl] = make_int4(k[0], k[1], k[2], 0);
+    V4<T> v = xyzq[sl];
+    v.x = (T)(x[0] - ref[3 * (size_t)c + 0]);
+    v.y = (T)(x[1] - ref[3 * (size_t)c + 1]);
+    v.z = (T)(x[2] - ref[3 * (size_t)c + 2]);
+    xyzq[sl] = v;
+}
+
+double nbr_max_disp2(Ctx& c, const double* pos) {
+    hipStream_t s = c.stream;
+    const int n = (int)c.n;
+    const int nb = std::max(1, std::min(256, (int)cdiv(n, 256)));
+    c.disp_part.ensure(nb + 1);
+    PQ_LAUNCH(k_disp2, nb, 256, 0, s, n, pos, (const double*)c.pos_build.p, c.disp_part.p);
+    PQ_LAUNCH(k_max_part, 1, 64, 0, s, (const double*)c.disp_part.p, nb, c.disp_part.p + nb);
+    double* h = c.pinned + 40;
+    PQ_HIP(hipMemcpyAsync(h, c.disp_part.p + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    return *h;
+}
+
+void nbr_refresh(Ctx& c, const double* pos) {
+    hipStream_t s = c.stream;
+    const int ncl = c.ncl;
+    const int nslot = ncl * CL;
+    Geom& g = c.g;
+    c.cl_w.ensure(nslot);
+    c.cl_k.ensure(nslot);
+    c.moved = true;
+    if (c.fp64)
+        PQ_LAUNCH(k_refresh<double>, cdiv(nslot, 256), 256, 0, s, nslot, c.orig.p, pos, (const double*)c.pos_build.p,
+                  (const double4*)c.cl_pos0.p, g, (const double*)c.cl_ref.p, c.cl_pos.p, c.cl_w.p, c.cl_k.p,
+                  as<double4>(c.xyzq), c.w64.p);
+    else
+        PQ_LAUNCH(k_refresh<float>, cdiv(nslot, 256), 256, 0, s, nslot, c.orig.p, pos, (const double*)c.pos_build.p,
+                  (const double4*)c.cl_pos0.p, g, (const double*)c.cl_ref.p, c.cl_pos.p, c.cl_w.p, c.cl_k.p,
+                  as<float4>(c.xyzq), c.w64.p);
+    // count pass with the canonical images, then the fill pass
+    if (c.fp64)
+        PQ_LAUNCH((k_jlist<false, double>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  (const double4*)c.cl_w.p, (const int4*)c.cl_k.p, c.cl_ref.p, c.jmask.p, c.jcount.p,
+                  (const int*)nullptr, (double4*)nullptr);
+    else
+        PQ_LAUNCH((k_jlist<false, float>), cdiv(ncl, 4), 256, 0, s, ncl, g, c.lcount.p, c.lcap, c.lj.p, c.cl_pos.p,
+                  (const double4*)c.cl_w.p, (const int4*)c.cl_k.p, c.cl_ref.p, c.jmask.p, c.jcount.p,
+                  (const int*)nullptr, (float4*)nullptr);
+    scan_ints(c, c.jcount.p, c.jstart.p, ncl, false, s);
+    int* hv = reinterpret_cast<int*>(c.pinned + 48);
+    PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    jlist_fill(c, hv[3]);
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {
     hipStream_t s = c.stream;
     PQ_HIP(hipMemsetAsync(c.counter.p, 0, sizeof(unsigned long long), s));
-    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, c.cl_pos.p,
+    PQ_LAUNCH(k_export, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p,
+              (const double4*)(c.moved ? c.cl_w.p : c.cl_pos.p), (const int4*)(c.moved ? c.cl_k.p : nullptr),
               pairs ? cap : (int64_t)0, pairs, c.counter.p);
     unsigned long long tot = 0;
     PQ_HIP(hipMemcpyAsync(&tot, c.counter.p, sizeof(tot), hipMemcpyDeviceToHost, s));

@@ -292,6 +292,13 @@ struct Ctx {
     DBuf<int> flag;          // device error flags
     DBuf<unsigned long long> counter;
     DBuf<int> scan_part;     // block sums of the multi-workgroup scan
+    // moves that keep the list (skin > 0, nbr_refresh)
+    bool moved = false;      // the list was kept across a move: cl_w and cl_k are valid
+    DBuf<double> pos_build;  // positions of the last full build, n*3
+    DBuf<double4> cl_pos0;   // slot-ordered wrapped positions of that build
+    DBuf<double4> cl_w;      // slot-ordered canonical wraps of the current positions
+    DBuf<int4> cl_k;         // lattice steps between continuous and wrapped positions
+    DBuf<double> disp_part;  // partial maxima of the displacement
 
     // --- PME ---
     int K[3] = {0, 0, 0}, P = 0, B = 8;
@@ -412,6 +419,12 @@ inline size_t rsz(const Ctx& c) { return c.fp64 ? 8 : 4; }
 // nbr.hip
 void scan_ints(Ctx& c, const int* in, int* out, int n, bool ceil8, hipStream_t s);  // exclusive; out[n] = total
 void nbr_build(Ctx& c, const double* pos);
+void jlist_fill(Ctx& c, int rows);
+// largest squared displacement since the last build (host-synchronising)
+double nbr_max_disp2(Ctx& c, const double* pos);
+// moves the atoms to pos keeping the cluster-pair list (orthorhombic, skin > 0,
+// every atom within skin/2 of its build position)
+void nbr_refresh(Ctx& c, const double* pos);
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs);
 // pair.hip: outputs in original atom order, without KE; force includes q_i
 void stage_charges(Ctx& c, const double* q, hipStream_t s);
