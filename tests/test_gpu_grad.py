@@ -38,13 +38,22 @@ def P():
     return P
 
 
+_MEMBERS = {}
+
+
+def build_member(k):
+    """System k of the gradient batch with its dense oracle matrix (cached)."""
+    if k not in _MEMBERS:
+        s = W.diff_batch(n_sys=k + 1)[k]
+        coul = dict(method="pme", alpha=W.ALPHA_RC9, rc=9.0, grid=48, order=5)
+        say(f"[grad] building the dense oracle matrix of batch system {k} (2000 atoms)")
+        _MEMBERS[k] = (s, coul, Q.coulomb_matrix_blocked(s.pos, s.box, coul))
+    return _MEMBERS[k]
+
+
 @pytest.fixture(scope="module")
 def member():
-    s = W.diff_batch(n_sys=1)[0]
-    coul = dict(method="pme", alpha=W.ALPHA_RC9, rc=9.0, grid=48, order=5)
-    say("[grad] building the dense oracle matrix for 2000 atoms")
-    A = Q.coulomb_matrix_blocked(s.pos, s.box, coul)
-    return s, coul, A
+    return build_member(0)
 
 
 def gpu(x):
@@ -77,8 +86,9 @@ def test_envelope_gradient_workload_hardness(P, member):
     ctx.close()
 
 
-def test_full_gmres_at_workload_hardness(P, member):
-    s, coul, A = member
+@pytest.mark.parametrize("k", [0, 63])
+def test_full_gmres_at_workload_hardness(P, k):
+    s, coul, A = build_member(k)
     M = Q.bordered(A, s.eta)
     kappa = np.linalg.cond(M)
     z = np.linalg.solve(M, np.concatenate([-s.chi, [0.0]]))
@@ -101,6 +111,10 @@ def test_full_gmres_at_workload_hardness(P, member):
     e = rel(dpos.cpu().numpy(), dR)
     say(f"[grad-workload-full] dE/dR rel err {e:.2e}")
     assert e < 1.01 * kappa * back + 1e-5
+    # the whole envelope gradient: dE/dchi = q*, dE/du = q*^2/2 at the device solution
+    dchi, deta = ctx.qeq_vjp(gpu(s.chi), gpu(s.eta), r.q)[1:]
+    assert rel(dchi.cpu().numpy(), qd) <= 1.01 * kappa * back
+    assert rel(deta.cpu().numpy(), 0.5 * qd * qd) <= 3 * kappa * back
     ctx.close()
 
 
@@ -143,3 +157,49 @@ def test_full_pipeline_well_posed(P, member):
     say(f"[grad-posdef] VJP dR {eR:.2e}")
     assert eR < 1e-5
     ctx.close()
+
+
+@pytest.mark.parametrize("k", [0, 63])
+def test_central_differences_fp64_workload_hardness(P, k):
+    """dE/dR of the QEQ energy at the workload's hardness (FP64 form, full
+    GMRES to 1e-10) against central differences of the device energy with
+    h = 1e-4 A, on the first and the last system of the gradient batch. The
+    probed atoms have no pair within 1e-3 A of the cutoff, so the pair set is
+    the same at every probe (the real-space sum is truncated, not shifted)."""
+    s = W.diff_batch(n_sys=k + 1)[k]
+    rc, h = 9.0, 1e-4
+    prm = P.make_params(s.box, rc, W.ALPHA_RC9, grid=48, order=5, fp64=True)
+    ctx = P.Context(0)
+    chi, eta = gpu(s.chi), gpu(s.eta)
+
+    def energy(pos):
+        ctx.set_system(gpu(pos), prm)
+        r = ctx.qeq_solve(chi, eta, tol=1e-10, max_it=3000, restart=3000)
+        assert r.status == 0, (r.iterations, r.rel_residual)
+        return float(r.energy.cpu()[0]), r
+
+    E0, r0 = energy(s.pos)
+    dpos, _, _ = ctx.qeq_vjp(chi, eta, r0.q)
+    g = dpos.cpu().numpy()
+    # atoms whose pair distances all stay clear of the cutoff under the probes
+    w = np.mod(s.pos, s.box)
+    d = w[None, :, :] - w[:, None, :]
+    d -= s.box * np.round(d / s.box)
+    r = np.sqrt((d * d).sum(-1))
+    np.fill_diagonal(r, 1e9)
+    clear = np.where(np.abs(r - rc).min(1) > 1e-3)[0][:2]
+    worst = 0.0
+    for i in clear:
+        for dim in range(3):
+            pp, pm = s.pos.copy(), s.pos.copy()
+            pp[i, dim] += h
+            pm[i, dim] -= h
+            fd = (energy(pp)[0] - energy(pm)[0]) / (2 * h)
+            worst = max(worst, abs(fd - g[i, dim]))
+            say(f"[fd-fp64 sys {k}] atom {i} dim {dim}: FD {fd:.10f} device {g[i, dim]:.10f} "
+                f"({r0.iterations} products for E0)")
+    ctx.close()
+    scale = np.abs(g).max()
+    say(f"[fd-fp64 sys {k}] worst |FD - dE/dR| {worst:.2e} eV/A (max |dE/dR| {scale:.3f})")
+    assert len(clear) == 2
+    assert worst < 1e-6 * scale
