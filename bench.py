@@ -542,6 +542,32 @@ def main():
                  "fp32_vs_fp64_phi_rel": dphi, "fp32_vs_fp64_F_rms_rel": dF}
     log(f"[bench] FP64 form {ms64:.3f} ms/eval ({ms64 / ms_step:.2f}x the FP32 form); FP32 vs FP64: "
         f"phi {dphi:.2e}, F {dF:.2e}")
+    # the FP32 form with compensated pair sums (PQ_FLAG_COMPENSATED): its
+    # cost in the pair kernel and the step, and its distance from the FP64 form
+    prmc = P.make_params(s.box, rc, a, grid=K, order=p, compensated=True)
+    ctx.set_system(pos, prmc)
+    ctx.set_tuning(tune["pair_wg_per_cu"], tune["fft_lds_bytes"], tune["pair_fork"])
+    for _ in range(2):
+        ctx.coulomb(q)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        phic, Fc, _ = ctx.coulomb(q)
+    e1.record()
+    torch.cuda.synchronize()
+    msc = e0.elapsed_time(e1) / args.steps
+    ctx.set_timing(2)
+    ctx.timings()
+    for _ in range(args.steps):
+        ctx.coulomb(q)
+    ph_c, cnt_c = ctx.timings()
+    ctx.set_timing(0)
+    dphic = float(torch.linalg.norm(phic - phi64) / torch.linalg.norm(phi64))
+    dFc = float(torch.sqrt(((Fc - F64) ** 2).sum(1).mean()) / torch.sqrt((F64 ** 2).sum(1).mean()))
+    compensated = {"ms_per_eval": msc, "pair_ms": ph_c["pair"] / max(1, cnt_c), "pair_ms_plain": phase_ms["pair"],
+                   "vs_fp64_phi_rel": dphic, "vs_fp64_F_rms_rel": dFc}
+    log(f"[bench] compensated pair sums: {msc:.3f} ms/eval, pair {compensated['pair_ms']:.4f} ms "
+        f"(plain {phase_ms['pair']:.4f}); vs FP64: phi {dphic:.2e}, F {dFc:.2e}")
     ctx.close()
 
     out = {
@@ -561,6 +587,7 @@ def main():
         "shadow_step_resident_ms": shadow_res_ms,
         "energy_eV": float(E[0]),
         "fp64_form": fp64_form,
+        "compensated_form": compensated,
         "autotune": tune,
     }
 

@@ -61,6 +61,12 @@ enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1, PQ_METHOD_AUTO = 2 /* pq_choose_p
  *   "Performance"); this flag gives that form on the same kernels, for
  *   callers that need relative accuracy well below 1e-6. */
 #define PQ_FLAG_FP64 1
+/* PQ_FLAG_COMPENSATED (FP32 form): the real-space pair sums accumulate in
+ *   FP32 blocks of 8 rounds that are folded into a running sum with an error
+ *   term (TwoSum), and the lanes' partial sums are combined the same way, so
+ *   the long per-atom sums lose no more than one FP32 rounding per block
+ *   (compensated per-cell partial sums). Ignored with PQ_FLAG_FP64. */
+#define PQ_FLAG_COMPENSATED 2
 
 /* Parameters of one periodic system. The names follow the paper's problem
  * statement for smooth PME (Algorithm "Smooth PME", input line: positions,
@@ -75,7 +81,7 @@ typedef struct pq_params {
     int32_t order;    /* PME B-spline order p, 3 <= p <= 8                             */
     int32_t kmax[3];  /* direct Ewald: k = 2 pi n / L over |n_d| <= kmax_d, 0..64     */
     int32_t method;   /* PQ_METHOD_PME (grid, order used) or PQ_METHOD_EWALD (kmax)   */
-    int32_t flags;    /* 0 or PQ_FLAG_FP64; other bits are rejected (PQ_ERR_INVALID)  */
+    int32_t flags;    /* PQ_FLAG_FP64 | PQ_FLAG_COMPENSATED; other bits are rejected   */
     double tilt[3];   /* triclinic tilt factors (t_xy, t_xz, t_yz) in A; all 0 for an
                        * orthorhombic box. The lattice vectors are the rows of
                        *   a = (L0, 0, 0), b = (t_xy, L1, 0), c = (t_xz, t_yz, L2)

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpmeqeq.so")
 ABI_VERSION = 5
 PQ_OK = 0
 FLAG_FP64 = 1
+FLAG_COMPENSATED = 2
 PQ_WARN_NOT_CONVERGED = 1
 STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_ERR_BOX",
           -3: "PQ_ERR_CAPACITY", -4: "PQ_ERR_NOMEM", -5: "PQ_ERR_HIP", -6: "PQ_ERR_TOO_LARGE",
@@ -147,12 +148,13 @@ def coulomb_constant() -> float:
 
 
 def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, method="pme",
-                fp64=False) -> Params:
+                fp64=False, compensated=False) -> Params:
     """Parameters of one periodic system. ``box``: an edge, three edges, or a
     3x3 lower triangular matrix whose rows are the lattice vectors
     a = (L0, 0, 0), b = (t_xy, L1, 0), c = (t_xz, t_yz, L2) (triclinic).
     ``fp64`` selects FP64 bulk arithmetic (PQ_FLAG_FP64) instead of the
-    default FP32 bulk with FP64 reductions."""
+    default FP32 bulk with FP64 reductions; ``compensated`` the compensated
+    FP32 pair sums (PQ_FLAG_COMPENSATED)."""
     p = Params()
     H = np.asarray(box, np.float64)
     if H.shape == (3, 3):
@@ -175,7 +177,7 @@ def make_params(box, cutoff, alpha, skin=0.0, grid=None, order=6, kmax=None, met
         p.method = METHOD_EWALD
     else:
         raise ValueError(method)
-    p.flags = FLAG_FP64 if fp64 else 0
+    p.flags = (FLAG_FP64 if fp64 else 0) | (FLAG_COMPENSATED if compensated else 0)
     return p
 
 

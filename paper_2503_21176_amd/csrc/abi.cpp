@@ -111,7 +111,7 @@ static void validate(int64_t n, const pq_params* p) {
                    std::fabs(p->tilt[1]) <= 0.5 * p->box[0] * (1 + 1e-12) &&
                    std::fabs(p->tilt[2]) <= 0.5 * p->box[1] * (1 + 1e-12),
                PQ_ERR_BOX, "tilt factors must satisfy |t_xy|, |t_xz| <= L0/2 and |t_yz| <= L1/2");
-    PQ_REQUIRE((p->flags & ~PQ_FLAG_FP64) == 0, PQ_ERR_INVALID, "unknown bits in flags");
+    PQ_REQUIRE((p->flags & ~(PQ_FLAG_FP64 | PQ_FLAG_COMPENSATED)) == 0, PQ_ERR_INVALID, "unknown bits in flags");
     PQ_REQUIRE(p->method == PQ_METHOD_PME || p->method == PQ_METHOD_EWALD, PQ_ERR_INVALID, "unknown method");
     if (p->method == PQ_METHOD_PME) {
         PQ_REQUIRE(p->order >= 3 && p->order <= 8, PQ_ERR_INVALID, "order must be in 3..8");

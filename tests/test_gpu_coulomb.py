@@ -156,6 +156,22 @@ def test_random_ionic_3000(P):
     check("ionic-3000", phi, F, E, ref)
 
 
+def test_compensated_pair_sums(P):
+    """PQ_FLAG_COMPENSATED: the pair sums in FP32 blocks folded by TwoSum;
+    the same tolerances, and the real-space part within FP32 rounding of the
+    plain form's."""
+    s = W.random_ionic(n=3000, seed=9, grid=None, order=6)
+    K = 32
+    prm = P.make_params(s.box, 10.0, W.ALPHA_RC10, grid=K, order=6, compensated=True)
+    phi, F, E = run(P, s, prm)
+    ref = O.spme_full(s.pos, s.q, s.box, W.ALPHA_RC10, 10.0, K, 6)
+    check("ionic-3000-compensated", phi, F, E, ref)
+    phi0, F0, _ = run(P, s, P.make_params(s.box, 10.0, W.ALPHA_RC10, grid=K, order=6))
+    say(f"[compensated] phi vs plain {rel2(phi, phi0):.2e}, F {rms_rel(F, F0):.2e}; vs oracle: "
+        f"compensated {rel2(phi, ref['phi']):.2e} plain {rel2(phi0, ref['phi']):.2e}")
+    assert rel2(phi, phi0) < 1e-6 and rms_rel(F, F0) < 1e-6
+
+
 def test_water_box_sampled(P):
     s = W.water_box()
     a = W.ALPHA_RC10
