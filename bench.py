@@ -45,7 +45,7 @@ def measured_traffic():
     summ = os.path.join(ROOT, "profiles", "coulomb_300k_hbm_counters.md")
     if not os.path.exists(summ):
         return None
-    m = re.search(r"TRAFFIC k_pair<true> pair_hip_sha256_16=(\w+) bytes_per_launch=(\d+)", open(summ).read())
+    m = re.search(r"TRAFFIC k_pair<true, false, false, float> pair_hip_sha256_16=(\w+) bytes_per_launch=(\d+)", open(summ).read())
     if not m:
         return None
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
