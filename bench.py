@@ -486,6 +486,22 @@ def main():
     log(f"[bench] pair kernel {phase_ms['pair']:.3f} ms, {npairs} half pairs, "
         f"{achieved / 1e12:.2f} TFLOP/s ({100 * achieved / PEAK_FP32:.1f}% of FP32 peak)")
 
+    # the neighbour list's two output formats (Section "Cell based Neighbor
+    # List"): COO rows (i, j, image) of the half pairs and the n x K ELLPACK
+    # matrix of both directions, exported from the resident list
+    nl_out = {}
+    for name, fn in (("coo", ctx.neighbor_pairs), ("ellpack", ctx.neighbor_ell)):
+        r = fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        nl_out[name + "_ms"] = (time.perf_counter() - t0) * 1e3
+    nl_out["ellpack_K"] = int(r[0].shape[1])
+    nl_out["coo_pairs"] = int(npairs)
+    del r
+    log(f"[bench] neighbour-list export: {nl_out}")
+
     # PME phases against HBM: algorithmic bytes (grid read/write per pass, atoms in/out)
     ng = K ** 3
     nspec = (K // 2 + 1) * K * K
@@ -584,6 +600,7 @@ def main():
         "phase_ms": phase_ms,
         "cold_eval_ms": cold_ms,
         "neighbor_build_ms": build_ms,
+        "neighbor_export": nl_out,
         "shadow_step_ms": shadow_ms,
         "shadow_step_resident_ms": shadow_res_ms,
         "energy_eV": float(E[0]),

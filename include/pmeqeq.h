@@ -197,6 +197,22 @@ pq_status pq_update_positions(pq_ctx* ctx, const double* pos, int32_t* rebuilt);
  * the call returns PQ_ERR_CAPACITY with *n_pairs (host) set to the count. */
 pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs);
 
+/* The same neighbour set in the ELLPACK form of Section "Cell based Neighbor
+ * List" (an n x K matrix, K the largest neighbour count). Row i lists every
+ * neighbour (j, n) of atom i: both directions of each pair of
+ * pq_neighbor_pairs ((i, j, n) gives (j, n) in row i and (i, -n) in row j; an
+ * atom's own images appear as (i, n) and (i, -n)), in ascending order of
+ * (j, n0, n1, n2), then padding. Outputs (device, each may be NULL):
+ *   nbr[n*K]    int32 row-major neighbour indices, -1 in the padding;
+ *   img[n*K*3]  int32 image vectors of the entries, 0 in the padding;
+ *   count[n]    int32 neighbours per row.
+ * *k_max (host, required) = the largest row count. With nbr or img given,
+ * K < *k_max returns PQ_ERR_CAPACITY (nothing written to nbr or img, count
+ * written), and *k_max > PQ_ELL_MAX_K returns PQ_ERR_TOO_LARGE. Uses a
+ * temporary device buffer of n*K*8 bytes. Host-synchronising. */
+#define PQ_ELL_MAX_K 8192
+pq_status pq_neighbor_ell(pq_ctx* ctx, int32_t K, int32_t* nbr, int32_t* img, int32_t* count, int32_t* k_max);
+
 /* ---- Coulomb evaluation ------------------------------------------------- */
 /* Periodic Coulomb potential, force and energy of the charge vector q
  * (device, n FP64; need not be neutral):

@@ -34,7 +34,7 @@ EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create"
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
            "pq_choose_params", "pq_auto_pme_min_atoms", "pq_md_run", "pq_md_history", "pq_coulomb_noalloc",
-           "pq_set_solver", "pq_update_positions"]
+           "pq_set_solver", "pq_update_positions", "pq_neighbor_ell"]
 PHASES = ["stage", "pair", "spread", "fft", "gather", "combine", "total"]
 
 
@@ -107,6 +107,7 @@ def load() -> ctypes.CDLL:
         "pq_destroy": (i32, [vp]),
         "pq_set_system": (i32, [vp, i64, vp, ctypes.POINTER(Params)]),
         "pq_neighbor_pairs": (i32, [vp, i64, vp, ctypes.POINTER(i64)]),
+        "pq_neighbor_ell": (i32, [vp, i32, vp, vp, vp, ctypes.POINTER(i32)]),
         "pq_coulomb": (i32, [vp, vp, vp, vp, vp]),
         "pq_coulomb_noalloc": (i32, [vp, vp, vp, vp, vp]),
         "pq_set_solver": (i32, [vp, i32, i32]),
@@ -337,6 +338,22 @@ class Context:
         out = torch.empty((max(1, cnt.value), 5), dtype=torch.int32, device=self.device)
         _check(self.lib.pq_neighbor_pairs(self.h, cnt.value, _ptr(out), ctypes.byref(cnt)))
         return out[:cnt.value]
+
+    def neighbor_ell(self, images: bool = True):
+        """ELLPACK neighbour matrix (n x K, K the largest row count): rows of
+        neighbour indices in ascending (j, image) order padded with -1, their
+        image vectors (n x K x 3, or None) and the row counts."""
+        km = ctypes.c_int32()
+        cnt = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        _check(self.lib.pq_neighbor_ell(self.h, 0, None, None, _ptr(cnt), ctypes.byref(km)))
+        K = int(km.value)
+        nbr = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
+        img = torch.empty((self.n, K, 3), dtype=torch.int32, device=self.device) if images else None
+        if K:
+            _check(self.lib.pq_neighbor_ell(self.h, K, _ptr(nbr), _ptr(img) if images else None, None,
+                                            ctypes.byref(km)))
+        return nbr, img, cnt
 
     def autotune(self, q, reps: int = 5) -> dict:
         """Times the pair kernel's launch shapes on phi+F evaluations with

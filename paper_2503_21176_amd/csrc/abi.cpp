@@ -491,6 +491,24 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
     PQ_API_END
 }
 
+pq_status pq_neighbor_ell(pq_ctx* ctx, int32_t K, int32_t* nbr, int32_t* img, int32_t* count, int32_t* k_max) {
+    PQ_API_BEGIN
+    PQ_REQUIRE(ctx != nullptr && k_max != nullptr, PQ_ERR_INVALID, "ctx or k_max is NULL");
+    PQ_REQUIRE(K >= 0, PQ_ERR_INVALID, "K must be >= 0");
+    Ctx& c = *reinterpret_cast<Ctx*>(ctx);
+    AllocScope alloc_scope(c);
+    PQ_REQUIRE(c.have_system, PQ_ERR_STATE, "pq_set_system has not been called");
+    PQ_HIP(hipSetDevice(c.device));
+    const int km = nbr_export_ell(c, K, nbr, img, count);
+    *k_max = km;
+    if ((nbr || img) && km > K) {
+        set_error("ELLPACK width " + std::to_string(K) + " below the largest row count " + std::to_string(km));
+        return PQ_ERR_CAPACITY;
+    }
+    return PQ_OK;
+    PQ_API_END
+}
+
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out) {
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx and q must not be NULL");

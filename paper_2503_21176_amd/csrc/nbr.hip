@@ -673,14 +673,43 @@ __global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
     for (int k = threadIdx.x; k < n; k += blockDim.x) out[k] = mk4<T>((T)-1.0e4, (T)-1.0e4, (T)-1.0e4, pack_int(0, T(0)));
 }
 
+// Entry e of an i-cluster's list seen from lane (a, b): the pair (i, j, n) of
+// i-atom i (canonical position wi, lattice steps ki) and the entry's atom b.
+// True when it is a pair closer than sqrt(rl2) by the canonical FP64
+// predicate, listed once (i < j, or i == j with n lexicographically positive).
+// With kimg (a list kept across moves, see k_jlist) the positions are the
+// canonical wraps and the image of a pair is n + k_j - k_i.
+__device__ __forceinline__ bool export_pair(const Geom& g, const int2* __restrict__ lj, const int* __restrict__ orig,
+                                            const double4* __restrict__ cpos, const int4* __restrict__ kimg, int i,
+                                            const double wi[3], int4 ki, double rl2, int b, size_t e, int& j, int& n0,
+                                            int& n1, int& n2) {
+    const int2 je = lj[e];
+    const size_t slot = (size_t)je.x * CL + b;
+    j = orig[slot];
+    const double4 pj = cpos[slot];
+    unpack_img(je.y, n0, n1, n2);
+    if (kimg) {
+        const int4 kj = kimg[slot];
+        n0 += kj.x - ki.x;
+        n1 += kj.y - ki.y;
+        n2 += kj.z - ki.z;
+    }
+    bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
+    if (ok) {
+        const double wj[3] = {pj.x, pj.y, pj.z};
+        double sx, sy, sz;
+        lattice_vec(n0, n1, n2, g.L, g.t, sx, sy, sz);
+        ok = canon_d2s(wi, wj, sx, sy, sz) < rl2;
+    }
+    return ok;
+}
+
 // Export of the atom pairs closer than the list radius, by the canonical FP64
 // predicate; each unordered pair once. A wavefront counts its i-cluster's
 // pairs, reserves that many rows with one atomic on the global counter and,
 // when `out` is given, walks the list again to write them; rows beyond `cap`
-// are not written but still counted.
-// With kimg (a list kept across moves, see k_jlist) the positions are the
-// canonical wraps cw, the image of a pair is n + k_j - k_i, and the radius is
-// the cutoff (the kept list covers the pairs closer than rc, not rc + skin).
+// are not written but still counted. With kimg the radius is the cutoff (the
+// kept list covers the pairs closer than rc, not rc + skin).
 __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                                 const int2* __restrict__ lj, const int* __restrict__ orig,
                                                 const double4* __restrict__ cpos, const int4* __restrict__ kimg,
@@ -697,31 +726,10 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
     const double rl = kimg ? g.rc : g.rlist;
     const double rl2 = rl * rl;
     const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
-    auto pair_at = [&](size_t e, int& j, int& n0, int& n1, int& n2) -> bool {
-        const int2 je = lj[e];
-        const size_t slot = (size_t)je.x * CL + b;
-        j = orig[slot];
-        const double4 pj = cpos[slot];
-        unpack_img(je.y, n0, n1, n2);
-        if (kimg) {
-            const int4 kj = kimg[slot];
-            n0 += kj.x - ki.x;
-            n1 += kj.y - ki.y;
-            n2 += kj.z - ki.z;
-        }
-        bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
-        if (ok) {
-            const double wj[3] = {pj.x, pj.y, pj.z};
-            double sx, sy, sz;
-            lattice_vec(n0, n1, n2, g.L, g.t, sx, sy, sz);
-            ok = canon_d2s(wi, wj, sx, sy, sz) < rl2;
-        }
-        return ok;
-    };
     unsigned long long cnt = 0;
     for (size_t e = e0; e < e1; ++e) {
         int j, n0, n1, n2;
-        cnt += __popcll(__ballot(pair_at(e, j, n0, n1, n2)));
+        cnt += __popcll(__ballot(export_pair(g, lj, orig, cpos, kimg, i, wi, ki, rl2, b, e, j, n0, n1, n2)));
     }
     if (cnt == 0) return;
     unsigned long long pos = 0;
@@ -730,7 +738,7 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
     if (!out) return;
     for (size_t e = e0; e < e1; ++e) {
         int j, n0, n1, n2;
-        const bool ok = pair_at(e, j, n0, n1, n2);
+        const bool ok = export_pair(g, lj, orig, cpos, kimg, i, wi, ki, rl2, b, e, j, n0, n1, n2);
         const unsigned long long m = __ballot(ok);
         if (ok) {
             const unsigned long long k = pos + lanes_below(m);
@@ -744,6 +752,97 @@ __global__ __launch_bounds__(256) void k_export(int ncl, Geom g, const int* __re
             }
         }
         pos += __popcll(m);
+    }
+}
+
+// ELLPACK key of neighbour (j, n) in a row: j in the high word, the image
+// components biased by 512 in three 10-bit fields below, so that ascending
+// keys are ascending (j, n0, n1, n2).
+__device__ __forceinline__ unsigned long long ell_key(int j, int n0, int n1, int n2) {
+    return ((unsigned long long)(unsigned)j << 32) |
+           (unsigned long long)(((unsigned)(n0 + 512) << 20) | ((unsigned)(n1 + 512) << 10) | (unsigned)(n2 + 512));
+}
+
+// ELLPACK rows from the same walk as k_export: every pair (i, j, n) is the
+// neighbour (j, n) of row i and (i, -n) of row j. FILL = false counts the
+// rows' entries; FILL = true puts each entry's key at the next free place of
+// its row (row-major n x K; the caller has checked K against the counts), in
+// the order the atomics give; k_ell_sort orders each row afterwards.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_ell(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
+                                             const int2* __restrict__ lj, const int* __restrict__ orig,
+                                             const double4* __restrict__ cpos, const int4* __restrict__ kimg,
+                                             int* __restrict__ rowcnt, int K, unsigned long long* __restrict__ keys) {
+    const int lane = lane_id();
+    const int ic = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ic >= ncl) return;
+    const int a = lane >> 3, b = lane & 7;
+    const int i = orig[(size_t)ic * CL + a];
+    const double4 pi4 = cpos[(size_t)ic * CL + a];
+    const int4 ki = kimg ? kimg[(size_t)ic * CL + a] : make_int4(0, 0, 0, 0);
+    const double wi[3] = {pi4.x, pi4.y, pi4.z};
+    const double rl = kimg ? g.rc : g.rlist;
+    const double rl2 = rl * rl;
+    const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
+    for (size_t e = e0; e < e1; ++e) {
+        int j, n0, n1, n2;
+        if (!export_pair(g, lj, orig, cpos, kimg, i, wi, ki, rl2, b, e, j, n0, n1, n2)) continue;
+        const int si = atomicAdd(&rowcnt[i], 1);
+        const int sj = atomicAdd(&rowcnt[j], 1);
+        if (FILL) {
+            keys[(size_t)i * K + si] = ell_key(j, n0, n1, n2);
+            keys[(size_t)j * K + sj] = ell_key(i, -n0, -n1, -n2);
+        }
+    }
+}
+
+// One workgroup per row: the row's cnt keys are sorted ascending in LDS
+// (bitonic network over the next power of two >= cnt, padded with the
+// largest key) and written out as neighbour indices and image vectors, then
+// -1 (index) and 0 (image) up to K.
+__global__ __launch_bounds__(256) void k_ell_sort(int n, int K, const int* __restrict__ rowcnt,
+                                                  const unsigned long long* __restrict__ keys,
+                                                  int32_t* __restrict__ nbr, int32_t* __restrict__ img) {
+    extern __shared__ unsigned long long sk[];
+    const int row = blockIdx.x;
+    const int cnt = rowcnt[row];
+    int kp = 1;
+    while (kp < cnt) kp <<= 1;
+    const unsigned long long* src = keys + (size_t)row * K;
+    for (int t = threadIdx.x; t < kp; t += blockDim.x) sk[t] = t < cnt ? src[t] : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= kp; k <<= 1) {
+        for (int h = k >> 1; h > 0; h >>= 1) {
+            for (int t = threadIdx.x; t < kp; t += blockDim.x) {
+                const int u = t ^ h;
+                if (u > t) {
+                    const unsigned long long x = sk[t], y = sk[u];
+                    if (((t & k) == 0) == (x > y)) {
+                        sk[t] = y;
+                        sk[u] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < K; t += blockDim.x) {
+        const size_t o = (size_t)row * K + t;
+        int j = -1, n0 = 0, n1 = 0, n2 = 0;
+        if (t < cnt) {
+            const unsigned long long key = sk[t];
+            j = (int)(key >> 32);
+            const unsigned lo = (unsigned)key;
+            n0 = (int)((lo >> 20) & 1023u) - 512;
+            n1 = (int)((lo >> 10) & 1023u) - 512;
+            n2 = (int)(lo & 1023u) - 512;
+        }
+        if (nbr) nbr[o] = j;
+        if (img) {
+            img[3 * o] = n0;
+            img[3 * o + 1] = n1;
+            img[3 * o + 2] = n2;
+        }
     }
 }
 
@@ -1062,6 +1161,40 @@ void nbr_refresh(Ctx& c, const double* pos) {
     PQ_HIP(hipMemcpyAsync(&hv[3], c.jstart.p + ncl, sizeof(int), hipMemcpyDeviceToHost, s));
     PQ_HIP(hipStreamSynchronize(s));
     jlist_fill(c, hv[3]);
+}
+
+int nbr_export_ell(Ctx& c, int K, int32_t* nbr, int32_t* img, int32_t* count) {
+    hipStream_t s = c.stream;
+    const int n = (int)c.n;
+    const double4* cpos = (const double4*)(c.moved ? c.cl_w.p : c.cl_pos.p);
+    const int4* kimg = (const int4*)(c.moved ? c.cl_k.p : nullptr);
+    DBuf<int> rowcnt, mx;
+    rowcnt.ensure((size_t)n);
+    mx.ensure(1);
+    PQ_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int) * (size_t)n, s));
+    PQ_LAUNCH(k_ell<false>, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, cpos, kimg,
+              rowcnt.p, 0, (unsigned long long*)nullptr);
+    PQ_LAUNCH(k_max_int, 1, 1024, 0, s, rowcnt.p, n, mx.p);
+    if (count) PQ_HIP(hipMemcpyAsync(count, rowcnt.p, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    int kmax = 0;
+    PQ_HIP(hipMemcpyAsync(&kmax, mx.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    PQ_HIP(hipStreamSynchronize(s));
+    if (!(nbr || img) || kmax > K || K == 0) return kmax;
+    if (kmax > PQ_ELL_MAX_K)
+        throw Error(PQ_ERR_TOO_LARGE, "ELLPACK rows of " + std::to_string(kmax) + " neighbours exceed the limit of " +
+                                          std::to_string(PQ_ELL_MAX_K));
+    DBuf<unsigned long long> keys;
+    if (kmax > 0) {
+        keys.ensure((size_t)n * K);
+        PQ_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int) * (size_t)n, s));
+        PQ_LAUNCH(k_ell<true>, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, cpos,
+                  kimg, rowcnt.p, K, keys.p);
+    }
+    int kp = 1;
+    while (kp < kmax) kp <<= 1;
+    PQ_LAUNCH(k_ell_sort, n, 256, (size_t)kp * sizeof(unsigned long long), s, n, K, rowcnt.p, keys.p, nbr, img);
+    PQ_HIP(hipStreamSynchronize(s));
+    return kmax;
 }
 
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs) {

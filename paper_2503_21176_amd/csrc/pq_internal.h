@@ -426,6 +426,8 @@ double nbr_max_disp2(Ctx& c, const double* pos);
 // every atom within skin/2 of its build position)
 void nbr_refresh(Ctx& c, const double* pos);
 int64_t nbr_export_pairs(Ctx& c, int64_t cap, int32_t* pairs);
+// ELLPACK export (pq_neighbor_ell); returns the largest row count
+int nbr_export_ell(Ctx& c, int K, int32_t* nbr, int32_t* img, int32_t* count);
 // pair.hip: outputs in original atom order, without KE; force includes q_i
 void stage_charges(Ctx& c, const double* q, hipStream_t s);
 void pair_sum(Ctx& c, bool force, hipStream_t s);   // into c.phi_r, c.f_r

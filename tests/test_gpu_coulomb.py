@@ -6,6 +6,7 @@ with the same alpha, cutoff, grid and order, so only rounding differs:
 and per atom max_i |dphi_i| / rms(phi) <= 1e-5, max_i |dF_i| / rms(|F|) <= 1e-5.
 Neighbour pair sets must match exactly.
 """
+import ctypes
 import math
 import sys
 
@@ -15,7 +16,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from _parity import elem_err
+from _parity import elem_err, ell_from_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -231,6 +232,38 @@ def test_neighbor_pairs_exact(P, case):
     say(f"[pairs-{case}] gpu {len(got)} oracle {len(want)}")
     assert got.shape == want.shape
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("case", ["nacl", "tiny-multi", "small-multi", "ionic-2000", "single"])
+def test_neighbor_ell_exact(P, case):
+    """ELLPACK export (Section "Cell based Neighbor List"): the n x K matrix of
+    every atom's neighbours, bit-exact against the rows built from the oracle's
+    pair set (K = largest row, -1 / zero-image padding)."""
+    if case == "nacl":
+        s, rc, skin = W.nacl(shuffle_seed=3), 5.64, 0.0
+    elif case == "tiny-multi":
+        s, rc, skin = W.small_random(5, 3.0, seed=3, dmin=0.3), 4.0, 0.0
+    elif case == "small-multi":
+        s, rc, skin = W.small_random(64, 8.62, seed=4), 9.0, 0.0
+    elif case == "single":
+        s, rc, skin = W.small_random(1, 12.0, seed=1), 5.0, 0.0     # no neighbours at all
+    else:
+        s, rc, skin = W.random_ionic(n=2000, seed=11, grid=None), 10.0, 1.0
+    want = ell_from_pairs(O.neighbor_pairs(s.pos, s.box, rc + skin), s.n)
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), P.make_params(s.box, rc, 0.3, skin=skin, kmax=1, method="ewald"))
+    nbr, img, cnt = ctx.neighbor_ell()
+    say(f"[ell-{case}] n={s.n} K gpu {nbr.shape[1]} oracle {want[0].shape[1]}")
+    assert np.array_equal(cnt.cpu().numpy(), want[2])
+    assert np.array_equal(nbr.cpu().numpy(), want[0])
+    assert np.array_equal(img.cpu().numpy(), want[1])
+    # too narrow a matrix is refused with the width it needs
+    if nbr.shape[1] > 0:
+        km = ctypes.c_int32()
+        small = torch.empty((s.n, nbr.shape[1] - 1), dtype=torch.int32, device="cuda")
+        st = ctx.lib.pq_neighbor_ell(ctx.h, nbr.shape[1] - 1, small.data_ptr(), None, None, ctypes.byref(km))
+        assert st == -3 and km.value == nbr.shape[1]
+    ctx.close()
 
 
 def test_invalid_arguments_raise(P):

@@ -153,6 +153,12 @@ def test_update_positions_keeps_the_list_and_the_pair_set(P):
     say(f"[update] kept={not rebuilt} pairs {len(got)} vs {len(want)}, {len(near)} atoms crossed the x face")
     assert not rebuilt and len(near) > 0
     assert np.array_equal(got, want)
+    # the ELLPACK form of the kept list: rows at rc with the current images
+    from _parity import ell_from_pairs
+    nbr, img, cnt = ctx.neighbor_ell()
+    e_nbr, e_img, e_cnt = ell_from_pairs(want, n)
+    assert np.array_equal(cnt.cpu().numpy(), e_cnt)
+    assert np.array_equal(nbr.cpu().numpy(), e_nbr) and np.array_equal(img.cpu().numpy(), e_img)
     phi, F, E = ctx.coulomb(gpu(s.q))
     ref = O.spme_full(new, s.q, s.box, a, rc, 32, 5)
     ephi = np.linalg.norm(phi.cpu().numpy() - ref["phi"]) / np.linalg.norm(ref["phi"])
