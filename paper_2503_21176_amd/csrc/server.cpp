@@ -5,55 +5,25 @@
 // budget; each slot owns a context and a HIP stream and runs its request on a
 // worker thread, so admitted solves overlap on the device and new requests
 // start as soon as earlier ones release a slot and memory. Results stay in the
-// server until polled.
+// server until polled. The queue, admission and threads are in pq_sched.h; this
+// file holds what runs on the device.
 #include <hip/hip_runtime.h>
 
-#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <condition_variable>
-#include <deque>
-#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 #include "pmeqeq.h"
 #include "pq_internal.h"
+#include "pq_sched.h"
 
 namespace pq {
 
 void set_error(const std::string& m);
-
-namespace {
-
-struct Req {
-    uint64_t ticket;
-    int64_t n;
-    std::vector<double> pos, chi, eta, q0;
-    bool has_q0;
-    double q_tot, tol;
-    int max_it, restart, solver;
-    pq_params params;
-    double footprint;
-    double t_submit, t_start = 0, t_done = 0;
-    // result
-    std::vector<double> q;
-    double energy = 0;
-    pq_solve_info info{};
-    int status = 0;
-    std::string message;
-    bool done = false;
-};
-
-double now_s(std::chrono::steady_clock::time_point t0) {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-}
-
-}  // namespace
 
 // Estimated device bytes of one request: neighbour lists, per-atom arrays,
 // PME grids and staging, Krylov basis. Bulk arrays take 4 or 8 bytes per real
@@ -94,35 +64,23 @@ double request_footprint(int64_t n, const pq_params& p, int restart) {
 
 struct pq_server {
     pq_server_cfg cfg{};
-    std::chrono::steady_clock::time_point t0;
-    std::mutex mu;
-    std::condition_variable cv_sched, cv_done;
-    std::deque<std::shared_ptr<pq::Req>> queue;
-    std::map<uint64_t, std::shared_ptr<pq::Req>> all;
-    uint64_t next_ticket = 1;
-    double in_use = 0;
-    bool stopping = false;
-    // slots
+    // device resources of each slot
     struct Slot {
         pq_ctx* ctx = nullptr;
         hipStream_t stream = nullptr;
         double* io = nullptr;      // device copies of a request's inputs and outputs; grows, never shrinks
         size_t io_bytes = 0;
-        std::shared_ptr<pq::Req> req;
-        std::thread th;
-        std::condition_variable cv;
-        bool busy = false;
-        bool quit = false;
     };
-    std::vector<std::unique_ptr<Slot>> slots;
-    std::thread sched;
+    std::vector<Slot> slots;
+    // queue, admission and worker threads (declared last: stopped first)
+    std::unique_ptr<pq::Sched> sched;
 };
 
 namespace pq {
 namespace {
 
-void run_request(pq_server* S, pq_server::Slot* sl, Req& r) {
-    (void)S;
+void run_request(const pq_server_cfg& cfg, pq_server::Slot* sl, Req& r) {
+    (void)hipSetDevice(cfg.device);
     pq_ctx* ctx = sl->ctx;
     const int64_t n = r.n;
     r.q.assign(n, 0.0);
@@ -174,60 +132,16 @@ void run_request(pq_server* S, pq_server::Slot* sl, Req& r) {
     if (st < 0) r.message = pq_last_error();
 }
 
-void slot_main(pq_server* S, pq_server::Slot* sl) {
-    (void)hipSetDevice(S->cfg.device);
-    std::unique_lock<std::mutex> lk(S->mu);
-    for (;;) {
-        sl->cv.wait(lk, [&] { return sl->quit || sl->req != nullptr; });
-        if (sl->req == nullptr && sl->quit) return;
-        std::shared_ptr<Req> r = sl->req;
-        lk.unlock();
-        r->t_start = now_s(S->t0);
-        run_request(S, sl, *r);
-        r->t_done = now_s(S->t0);
-        lk.lock();
-        r->done = true;
-        S->in_use -= r->footprint;
-        sl->req = nullptr;
-        sl->busy = false;
-        S->cv_done.notify_all();
-        S->cv_sched.notify_all();
-    }
-}
-
-void sched_main(pq_server* S) {
-    std::unique_lock<std::mutex> lk(S->mu);
-    for (;;) {
-        S->cv_sched.wait(lk, [&] {
-            if (S->stopping && S->queue.empty()) return true;
-            if (S->queue.empty()) return false;
-            const auto& h = S->queue.front();
-            bool free_slot = false;
-            for (auto& sl : S->slots) free_slot = free_slot || !sl->busy;
-            return free_slot && S->in_use + h->footprint <= S->cfg.hbm_budget_bytes;
-        });
-        if (S->queue.empty() && S->stopping) break;
-        // admit as many head requests as fit
-        while (!S->queue.empty()) {
-            auto h = S->queue.front();
-            if (S->in_use + h->footprint > S->cfg.hbm_budget_bytes) break;
-            pq_server::Slot* free_sl = nullptr;
-            for (auto& sl : S->slots)
-                if (!sl->busy) {
-                    free_sl = sl.get();
-                    break;
-                }
-            if (!free_sl) break;
-            S->queue.pop_front();
-            S->in_use += h->footprint;
-            free_sl->busy = true;
-            free_sl->req = h;
-            free_sl->cv.notify_one();
-        }
-    }
-    for (auto& sl : S->slots) {
-        sl->quit = true;
-        sl->cv.notify_one();
+// Contexts, streams and buffers of the slots (the worker threads have ended).
+void release_slots(pq_server& S) {
+    for (auto& sl : S.slots) {
+        if (sl.ctx) pq_destroy(sl.ctx);
+        sl.ctx = nullptr;
+        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
+        if (sl.io) (void)hipFree(sl.io);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        sl.io = nullptr;
+        sl.stream = nullptr;
     }
 }
 
@@ -263,23 +177,27 @@ pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg) {
     PQ_HIP(hipSetDevice(cfg->device));
     auto S = std::make_unique<pq_server>();
     S->cfg = *cfg;
-    S->t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < cfg->slots; ++k) {
-        auto sl = std::make_unique<pq_server::Slot>();
-        PQ_HIP(hipStreamCreateWithFlags(&sl->stream, hipStreamNonBlocking));
-        pq_status st = pq_create(&sl->ctx, cfg->device, sl->stream, nullptr);
-        if (st != PQ_OK) throw Error(st, pq_last_error());
-        // slots launch their kernels directly; Arnoldi-step graphs are kept
-        // for contexts driven from one thread (several slots replaying their
-        // graphs concurrently crashed the process; the cause is not known)
-        reinterpret_cast<Ctx*>(sl->ctx)->graphs = false;
-        // requests overlap across slots, so a slot evaluates on its one
-        // stream: no second stream and no fork/join events per evaluation
-        reinterpret_cast<Ctx*>(sl->ctx)->serial = true;
-        S->slots.push_back(std::move(sl));
+    S->slots.resize(cfg->slots);
+    try {
+        for (auto& sl : S->slots) {
+            PQ_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+            pq_status st = pq_create(&sl.ctx, cfg->device, sl.stream, nullptr);
+            if (st != PQ_OK) throw Error(st, pq_last_error());
+            // slots launch their kernels directly; Arnoldi-step graphs are kept
+            // for contexts driven from one thread (several slots replaying their
+            // graphs concurrently crashed the process; the cause is not known)
+            reinterpret_cast<Ctx*>(sl.ctx)->graphs = false;
+            // requests overlap across slots, so a slot evaluates on its one
+            // stream: no second stream and no fork/join events per evaluation
+            reinterpret_cast<Ctx*>(sl.ctx)->serial = true;
+        }
+    } catch (...) {
+        release_slots(*S);
+        throw;
     }
-    for (auto& sl : S->slots) sl->th = std::thread(slot_main, S.get(), sl.get());
-    S->sched = std::thread(sched_main, S.get());
+    pq_server* raw = S.get();
+    S->sched = std::make_unique<Sched>(cfg->slots, cfg->hbm_budget_bytes,
+                                       [raw](int k, Req& r) { run_request(raw->cfg, &raw->slots[k], r); });
     *out = S.release();
     return PQ_OK;
     PQ_API_END
@@ -307,34 +225,24 @@ pq_status pq_server_submit(pq_server* S, const pq_request* req, uint64_t* ticket
     r->solver = req->solver;
     r->params = req->params;
     r->footprint = request_footprint(n, req->params, req->solver == PQ_SOLVER_MINRES ? 1 : req->restart);
-    if (r->footprint > S->cfg.hbm_budget_bytes) {
-        set_error("request footprint " + std::to_string(r->footprint) + " B exceeds the server budget");
-        return PQ_ERR_TOO_LARGE;
-    }
-    std::lock_guard<std::mutex> lk(S->mu);
-    PQ_REQUIRE(!S->stopping, PQ_ERR_STATE, "server is stopping");
-    r->ticket = S->next_ticket++;
-    r->t_submit = now_s(S->t0);
-    S->all[r->ticket] = r;
-    S->queue.push_back(r);
-    *ticket = r->ticket;
-    S->cv_sched.notify_all();
-    return PQ_OK;
+    std::string msg;
+    const pq_status st = S->sched->submit(r, ticket, &msg);
+    if (st != PQ_OK) set_error(msg);
+    return st;
     PQ_API_END
 }
 
 pq_status pq_server_poll(pq_server* S, uint64_t ticket, pq_result* res, int64_t timeout_us) {
     PQ_API_BEGIN
     PQ_REQUIRE(S && res, PQ_ERR_INVALID, "server and result must not be NULL");
-    std::unique_lock<std::mutex> lk(S->mu);
-    auto it = S->all.find(ticket);
-    PQ_REQUIRE(it != S->all.end(), PQ_ERR_INVALID, "unknown ticket");
-    std::shared_ptr<Req> r = it->second;
-    auto pred = [&] { return r->done; };
-    if (timeout_us < 0)
-        S->cv_done.wait(lk, pred);
-    else if (!S->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), pred))
-        return PQ_ERR_TIMEOUT;
+    std::shared_ptr<Req> r;
+    std::string msg;
+    const pq_status st = S->sched->poll(ticket, timeout_us, &r, &msg);
+    if (st == PQ_ERR_TIMEOUT) return st;
+    if (st != PQ_OK) {
+        set_error(msg);
+        return st;
+    }
     if (res->q && !r->q.empty()) std::memcpy(res->q, r->q.data(), sizeof(double) * r->q.size());
     res->energy = r->energy;
     res->info = r->info;
@@ -343,7 +251,6 @@ pq_status pq_server_poll(pq_server* S, uint64_t ticket, pq_result* res, int64_t 
     res->t_start_s = r->t_start;
     res->t_done_s = r->t_done;
     std::snprintf(res->message, sizeof(res->message), "%s", r->message.c_str());
-    S->all.erase(it);
     return PQ_OK;
     PQ_API_END
 }
@@ -356,19 +263,9 @@ double pq_request_footprint(int64_t n, const pq_params* params, int32_t restart)
 pq_status pq_server_destroy(pq_server* S) {
     PQ_API_BEGIN
     if (!S) return PQ_OK;
-    {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->stopping = true;
-        S->cv_sched.notify_all();
-    }
-    if (S->sched.joinable()) S->sched.join();
-    for (auto& sl : S->slots) {
-        if (sl->th.joinable()) sl->th.join();
-        pq_destroy(sl->ctx);
-        std::lock_guard<std::recursive_mutex> lk(device_mem_lock());
-        if (sl->io) (void)hipFree(sl->io);
-        if (sl->stream) (void)hipStreamDestroy(sl->stream);
-    }
+    // queued requests still run; then the worker threads end
+    if (S->sched) S->sched->stop();
+    release_slots(*S);
     delete S;
     return PQ_OK;
     PQ_API_END
