@@ -219,12 +219,16 @@ __global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* _
                                                       T* __restrict__ stage) {
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
-    __shared__ T lds[SW][R3];
-    __shared__ T tab[SW][SPREAD_BATCH][32];   // per atom: weights x, y, z (8 each), base, charge
+    constexpr int R3P = (R3 + 3) & ~3;          // region copies padded to 4 values (vector clears)
+    __shared__ __align__(32) T lds[SW][R3P];
+    __shared__ __align__(32) T tab[SW][SPREAD_BATCH][32];   // per atom: weights x, y, z (8 each), base, charge
     const int bid = blockIdx.x;
     const int bx = bid % G.nb0, by = (bid / G.nb0) % G.nb1, bz = bid / (G.nb0 * G.nb1);
     const int s0 = brick_start[bid], s1 = brick_start[bid + 1];
-    for (int t = threadIdx.x; t < SW * R3; t += 64 * SW) (&lds[0][0])[t] = T(0);
+    {
+        V4<T>* l4 = reinterpret_cast<V4<T>*>(&lds[0][0]);
+        for (int t = threadIdx.x; t < SW * R3P / 4; t += 64 * SW) l4[t] = mk4<T>(T(0), T(0), T(0), T(0));
+    }
     __syncthreads();
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
     const int lane = threadIdx.x & 63;
@@ -255,16 +259,21 @@ __global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* _
         __builtin_amdgcn_wave_barrier();
         for (int i = 0; i < nb; ++i) {
             const T* at = tb[i];
-            const int pk = unpack_int(at[24]);
+            // x weights, base index and charge as vector reads of the table row
+            const V4<T> w03 = *reinterpret_cast<const V4<T>*>(at);
+            const V4<T> w47 = *reinterpret_cast<const V4<T>*>(at + 4);
+            const V2<T> bq = *reinterpret_cast<const V2<T>*>(at + 24);
+            const T wxs[8] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
+            const int pk = unpack_int(bq.x);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
             if (active) {
-                const T c = at[25] * at[8 + ty] * at[16 + tz];
+                const T c = bq.y * at[8 + ty] * at[16 + tz];
                 T* rowp = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
                 T v[P];
 #pragma unroll
                 for (int tx = 0; tx < P; ++tx) v[tx] = rowp[-tx];
 #pragma unroll
-                for (int tx = 0; tx < P; ++tx) rowp[-tx] = fma(c, at[tx], v[tx]);
+                for (int tx = 0; tx < P; ++tx) rowp[-tx] = fma(c, wxs[tx], v[tx]);
             }
             // the next atom may update the same rows
             __builtin_amdgcn_wave_barrier();
