@@ -676,13 +676,15 @@ __global__ void k_far_entries(V4<T>* __restrict__ out, int n) {
 // Entry e of an i-cluster's list seen from lane (a, b): the pair (i, j, n) of
 // i-atom i (canonical position wi, lattice steps ki) and the entry's atom b.
 // True when it is a pair closer than sqrt(rl2) by the canonical FP64
-// predicate, listed once (i < j, or i == j with n lexicographically positive).
-// With kimg (a list kept across moves, see k_jlist) the positions are the
-// canonical wraps and the image of a pair is n + k_j - k_i.
+// predicate; with half, only if listed once (i < j, or i == j with n
+// lexicographically positive), else for every (j, n) != (i, 0) (each i-atom's
+// list holds all its neighbours). With kimg (a list kept across moves, see
+// k_jlist) the positions are the canonical wraps and the image of a pair is
+// n + k_j - k_i.
 __device__ __forceinline__ bool export_pair(const Geom& g, const int2* __restrict__ lj, const int* __restrict__ orig,
                                             const double4* __restrict__ cpos, const int4* __restrict__ kimg, int i,
                                             const double wi[3], int4 ki, double rl2, int b, size_t e, int& j, int& n0,
-                                            int& n1, int& n2) {
+                                            int& n1, int& n2, bool half = true) {
     const int2 je = lj[e];
     const size_t slot = (size_t)je.x * CL + b;
     j = orig[slot];
@@ -694,7 +696,8 @@ __device__ __forceinline__ bool export_pair(const Geom& g, const int2* __restric
         n1 += kj.y - ki.y;
         n2 += kj.z - ki.z;
     }
-    bool ok = (i >= 0) && (j >= 0) && ((i < j) || (i == j && lex_positive(n0, n1, n2)));
+    bool ok = (i >= 0) && (j >= 0) &&
+              (half ? ((i < j) || (i == j && lex_positive(n0, n1, n2))) : (i != j || n0 != 0 || n1 != 0 || n2 != 0));
     if (ok) {
         const double wj[3] = {pj.x, pj.y, pj.z};
         double sx, sy, sz;
@@ -763,11 +766,12 @@ __device__ __forceinline__ unsigned long long ell_key(int j, int n0, int n1, int
            (unsigned long long)(((unsigned)(n0 + 512) << 20) | ((unsigned)(n1 + 512) << 10) | (unsigned)(n2 + 512));
 }
 
-// ELLPACK rows from the same walk as k_export: every pair (i, j, n) is the
-// neighbour (j, n) of row i and (i, -n) of row j. FILL = false counts the
-// rows' entries; FILL = true puts each entry's key at the next free place of
-// its row (row-major n x K; the caller has checked K against the counts), in
-// the order the atomics give; k_ell_sort orders each row afterwards.
+// ELLPACK rows from each i-cluster's own list, which holds every neighbour
+// (j, n) of each of its atoms, so rows are counted and filled without
+// atomics: FILL = false stores each atom's row count, FILL = true its keys in
+// list order at row-major n x K (a lane's place from the ballot of its
+// i-atom's eight lanes; the caller has checked K against the counts);
+// k_ell_sort orders each row afterwards.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_ell(int ncl, Geom g, const int* __restrict__ lcount, int lcap,
                                              const int2* __restrict__ lj, const int* __restrict__ orig,
@@ -784,16 +788,16 @@ __global__ __launch_bounds__(256) void k_ell(int ncl, Geom g, const int* __restr
     const double rl = kimg ? g.rc : g.rlist;
     const double rl2 = rl * rl;
     const size_t e0 = (size_t)ic * lcap, e1 = e0 + min(lcount[ic], lcap);
+    const unsigned below = (1u << b) - 1u;
+    int pos = 0;   // entries of i-atom a so far (the same in its eight lanes)
     for (size_t e = e0; e < e1; ++e) {
         int j, n0, n1, n2;
-        if (!export_pair(g, lj, orig, cpos, kimg, i, wi, ki, rl2, b, e, j, n0, n1, n2)) continue;
-        const int si = atomicAdd(&rowcnt[i], 1);
-        const int sj = atomicAdd(&rowcnt[j], 1);
-        if (FILL) {
-            keys[(size_t)i * K + si] = ell_key(j, n0, n1, n2);
-            keys[(size_t)j * K + sj] = ell_key(i, -n0, -n1, -n2);
-        }
+        const bool ok = export_pair(g, lj, orig, cpos, kimg, i, wi, ki, rl2, b, e, j, n0, n1, n2, false);
+        const unsigned seg = (unsigned)(__ballot(ok) >> (8 * a)) & 0xffu;
+        if (FILL && ok) keys[(size_t)i * K + pos + __popc(seg & below)] = ell_key(j, n0, n1, n2);
+        pos += __popc(seg);
     }
+    if (!FILL && b == 0 && i >= 0) rowcnt[i] = pos;
 }
 
 // One workgroup per row: the row's cnt keys are sorted ascending in LDS
@@ -1186,9 +1190,8 @@ int nbr_export_ell(Ctx& c, int K, int32_t* nbr, int32_t* img, int32_t* count) {
     DBuf<unsigned long long> keys;
     if (kmax > 0) {
         keys.ensure((size_t)n * K);
-        PQ_HIP(hipMemsetAsync(rowcnt.p, 0, sizeof(int) * (size_t)n, s));
         PQ_LAUNCH(k_ell<true>, cdiv(c.ncl, 4), 256, 0, s, c.ncl, c.g, c.lcount.p, c.lcap, c.lj.p, c.orig.p, cpos,
-                  kimg, rowcnt.p, K, keys.p);
+                  kimg, (int*)nullptr, K, keys.p);
     }
     int kp = 1;
     while (kp < kmax) kp <<= 1;
