@@ -487,7 +487,9 @@ pq_status pq_server_submit(pq_server* s, const pq_request* req, uint64_t* ticket
  * the result out (res->q must hold n doubles) and forgets the ticket. Returns
  * PQ_ERR_TIMEOUT if still pending. Thread safe. */
 pq_status pq_server_poll(pq_server* s, uint64_t ticket, pq_result* res, int64_t timeout_us);
-/* Stops the scheduler after the requests already submitted complete. */
+/* Runs the requests already submitted to completion, stops the scheduler and
+ * the slots and frees the server (results not polled are dropped). No other
+ * call on the same server may run concurrently with it or follow it. */
 pq_status pq_server_destroy(pq_server* s);
 /* The footprint in bytes that admission charges for a request of n atoms with
  * these parameters and GMRES restart length (an estimate of the device memory
