@@ -144,3 +144,50 @@ def test_mixed_stream_eight_slots_no_errors(P):
     assert all(x["iterations"] >= 1 for x in res)
     for a, b in zip(res[:6], res1):
         assert np.array_equal(a["q"], b["q"])
+
+
+def test_stated_hardness_full_gmres_and_minres(P):
+    """Requests of the serving stream as stated (hardness U(5, 10) eV: the QEQ
+    matrix is indefinite) of 80 to 120 atoms: full GMRES within the stream's
+    200-product budget reaches 1e-5 (at 160 atoms this draw needs a few more), and MINRES (with a larger budget) reaches
+    the same charges, both through the server. Each result is checked against
+    the dense FP64 oracle by its backward error (with the best multiplier for
+    the returned charges) and by the forward error bound cond * backward
+    error; the two solvers agree within the sum of their bounds."""
+    reqs = []
+    for k, n in enumerate([80, 100, 120]):
+        s = W.serving_request(n, seed=40 + k)
+        c = s.params
+        reqs.append((s, P.make_params(s.box, c["cutoff"], c["alpha"], grid=c["grid"], order=c["order"]), c))
+    srv = P.Server(0, slots=4, hbm_budget_bytes=8e9)
+    tk = [(srv.submit(s.pos, s.chi, s.eta, prm, q0=s.q, tol=1e-5, max_it=200, restart=200, solver="gmres"),
+           srv.submit(s.pos, s.chi, s.eta, prm, q0=s.q, tol=1e-5, max_it=3000, restart=1, solver="minres"))
+          for s, prm, _ in reqs]
+    res = [(srv.poll(a), srv.poll(b)) for a, b in tk]
+    srv.close()
+    for (s, prm, c), (rg, rm) in zip(reqs, res):
+        coul = dict(method="pme", alpha=c["alpha"], rc=c["cutoff"], grid=c["grid"], order=c["order"])
+        A = Q.coulomb_matrix_blocked(s.pos, s.box, coul)
+        M = Q.bordered(A, s.eta)
+        kappa = np.linalg.cond(M)
+        zd = np.linalg.solve(M, np.concatenate([-s.chi, [0.0]]))
+        qd = zd[:-1]
+        errs = []
+        for name, r in (("gmres", rg), ("minres", rm)):
+            q = r["q"]
+            lam = float(np.mean(-s.chi - s.eta * q - A @ q))   # best multiplier for q
+            back = Q.bordered_residual(A, s.chi, s.eta, 0.0, q, lam)
+            fwd = float(np.linalg.norm(np.append(q, lam) - zd) / np.linalg.norm(zd))
+            say(f"[serve-stated] n={s.n} {name}: status {r['status']} its {r['iterations']} "
+                f"relres {r['rel_residual']:.2e} oracle backward {back:.2e} forward {fwd:.2e} cond {kappa:.3g}")
+            assert r["status"] == 0
+            # the solvers stop on their own residual estimate (FP32-bulk
+            # products; MINRES on the preconditioned norm): within 3x of 1e-5
+            assert back < 3e-5
+            assert fwd <= 1.01 * kappa * back + 1e-12
+            # the charge constraint is a row of the solved system: met to the residual
+            assert abs(q.sum()) <= 1.01 * back * np.linalg.norm(s.chi)
+            errs.append(back)
+        gap = float(np.linalg.norm(rg["q"] - rm["q"]) / np.linalg.norm(zd))
+        assert gap <= 1.01 * kappa * (errs[0] + errs[1]) + 1e-12
+        assert rg["iterations"] <= 201   # the budget, plus the product of the start residual
