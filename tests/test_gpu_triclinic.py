@@ -14,7 +14,7 @@ import torch
 
 import oracle as O
 import workloads as W
-from _parity import elem_err
+from _parity import elem_err, ell_from_pairs
 
 pytestmark = pytest.mark.gpu
 
@@ -85,11 +85,16 @@ def test_triclinic_pairs_exact(P, case):
     ctx = P.Context(0)
     ctx.set_system(gpu(s.pos), P.make_params(s.box, rc, 0.3, skin=skin, kmax=1, method="ewald"))
     got = ctx.neighbor_pairs().cpu().numpy().astype(np.int64)
+    nbr, img, cnt = ctx.neighbor_ell()
     ctx.close()
     got = got[np.lexsort((got[:, 4], got[:, 3], got[:, 2], got[:, 1], got[:, 0]))]
     want = O.neighbor_pairs(s.pos, s.box, rc + skin)
     say(f"[tric-pairs-{case}] gpu {len(got)} oracle {len(want)}")
     assert got.shape == want.shape and np.array_equal(got, want)
+    # the ELLPACK form: both directions of every pair, lattice image vectors
+    e_nbr, e_img, e_cnt = ell_from_pairs(want, n)
+    assert np.array_equal(cnt.cpu().numpy(), e_cnt)
+    assert np.array_equal(nbr.cpu().numpy(), e_nbr) and np.array_equal(img.cpu().numpy(), e_img)
 
 
 @pytest.mark.parametrize("fp64", [False, True])
