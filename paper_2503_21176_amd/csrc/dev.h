@@ -84,6 +84,11 @@ __host__ __device__ __forceinline__ bool lex_positive(int n0, int n1, int n2) {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// Waves of the reciprocal-space chain (the evaluation's critical path while the
+// pair kernel runs beside it) raise their instruction-issue priority, so that on
+// a SIMD shared with pair-kernel waves their few instructions go first.
+__device__ __forceinline__ void chain_priority() { __builtin_amdgcn_s_setprio(3); }
+
 // Vector types of the bulk precision T (float: the production form, double:
 // the same kernels in FP64).
 template <class T>

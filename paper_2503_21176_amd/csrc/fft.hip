@@ -278,6 +278,7 @@ __device__ C* fft_lds(C* a, C* b, const FftDev& pl, const C* __restrict__ tw, in
 template <class T>
 __global__ __launch_bounds__(256) void k_fft_x_r2c(FftDev pl, const V2<T>* __restrict__ tw, int nrows, int np,
                                                    const T* __restrict__ grid, V2<T>* __restrict__ spec) {
+    chain_priority();
     using C = V2<T>;
     extern __shared__ __align__(16) unsigned char smraw[];
     C* sm = reinterpret_cast<C*>(smraw);
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(256) void k_fft_x_r2c(FftDev pl, const V2<T>* __res
 template <class T>
 __global__ __launch_bounds__(256) void k_fft_x_c2r(FftDev pl, const V2<T>* __restrict__ tw, int nrows, int np,
                                                    const V2<T>* __restrict__ spec, T* __restrict__ grid) {
+    chain_priority();
     using C = V2<T>;
     extern __shared__ __align__(16) unsigned char smraw[];
     C* sm = reinterpret_cast<C*>(smraw);
@@ -375,6 +377,7 @@ template <int SIGN, bool CONV, class T>
 __global__ __launch_bounds__(256) void k_fft_col(FftDev pl, const V2<T>* __restrict__ tw, int X, int tx,
                                                  size_t estride, size_t ostride, V2<T>* __restrict__ spec,
                                                  ConvArgs cv, double* __restrict__ epart) {
+    chain_priority();
     // CONV: epart == NULL skips the energy
     using C = V2<T>;
     extern __shared__ __align__(16) unsigned char smraw[];
@@ -459,6 +462,7 @@ __global__ __launch_bounds__(CT*(R1 > R2 ? R1 : R2)) void k_fft_col2(const V2<T>
                                                                      size_t estride, size_t ostride,
                                                                      V2<T>* __restrict__ spec, ConvArgs cv,
                                                                      double* __restrict__ epart) {
+    chain_priority();
     using C = V2<T>;
     constexpr int N = R1 * R2;
     __shared__ C sm[N * CT];   // element (a, b) of a column at (a * R2 + b) * CT + column
@@ -559,6 +563,7 @@ template <int R1, int R2, class T>
 __global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_r2c(const V2<T>* __restrict__ wn, int nrows,
                                                                        const T* __restrict__ grid,
                                                                        V2<T>* __restrict__ spec) {
+    chain_priority();
     using C = V2<T>;
     constexpr int N = R1 * R2, X = N / 2 + 1;
     __shared__ C sm[N * RP];
@@ -611,6 +616,7 @@ template <int R1, int R2, class T>
 __global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_c2r(const V2<T>* __restrict__ wn, int nrows,
                                                                        const V2<T>* __restrict__ spec,
                                                                        T* __restrict__ grid) {
+    chain_priority();
     using C = V2<T>;
     constexpr int N = R1 * R2, X = N / 2 + 1;
     __shared__ C sm[N * RP];

@@ -217,6 +217,7 @@ __global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* _
                                                       const V4<T>* __restrict__ pme_frac,
                                                       const T* __restrict__ pme_w, const T* __restrict__ qbrick,
                                                       T* __restrict__ stage) {
+    chain_priority();
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
     constexpr int R3P = (R3 + 3) & ~3;          // region copies padded to 4 values (vector clears)
@@ -324,6 +325,7 @@ constexpr int REDUCE_ROWS = 4;   // grid rows (wavefronts) per workgroup
 template <int P, class T>
 __global__ __launch_bounds__(64 * REDUCE_ROWS) void k_spread_reduce(PmeGeo G, const T* __restrict__ stage,
                                                                     T* __restrict__ grid) {
+    chain_priority();
     constexpr int R = PME_B + P - 1;
     constexpr int R3 = R * R * R;
     const int row = __builtin_amdgcn_readfirstlane(blockIdx.x * REDUCE_ROWS + (threadIdx.x >> 6));
@@ -388,6 +390,7 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
                                                 const T* __restrict__ grid, const T* __restrict__ qbrick2,
                                                 const T* __restrict__ grid2, T* __restrict__ phi_out,
                                                 V4<T>* __restrict__ f_out) {
+    chain_priority();
     constexpr int R = PME_B + P - 1;
     static_assert(R <= 16, "a region row must fit 16 lanes");
     __shared__ T lds[R * R * R];
