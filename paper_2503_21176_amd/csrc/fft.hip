@@ -557,9 +557,10 @@ __global__ __launch_bounds__(CT*(R1 > R2 ? R1 : R2)) void k_fft_col2(const V2<T>
 // z[m] = H0[m] + i H1[m] (Hermitian halves for m > n/2) from the spectra,
 // R1-point DFT, twiddles, LDS; R2-point DFT; real and imaginary parts are the
 // two rows, stored from registers.
-constexpr int RP = 16;   // row pairs per workgroup
+// RP row pairs per workgroup (16, 8 or 4: from the LDS budget of the FFT
+// tiles, which the autotuner chooses).
 
-template <int R1, int R2, class T>
+template <int R1, int R2, int RP, class T>
 __global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_r2c(const V2<T>* __restrict__ wn, int nrows,
                                                                        const T* __restrict__ grid,
                                                                        V2<T>* __restrict__ spec) {
@@ -612,7 +613,7 @@ __global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_r2c(const V2<
     }
 }
 
-template <int R1, int R2, class T>
+template <int R1, int R2, int RP, class T>
 __global__ __launch_bounds__(RP*(R1 > R2 ? R1 : R2)) void k_fft_x2_c2r(const V2<T>* __restrict__ wn, int nrows,
                                                                        const V2<T>* __restrict__ spec,
                                                                        T* __restrict__ grid) {
@@ -921,15 +922,16 @@ static bool col2_launch(int r1, int r2, dim3 grid, hipStream_t s, const V2<T>* w
 }
 
 // The two-radix x passes for (r1, r2); false if that pair has no instance.
-template <bool FWD, class T>
-static bool x2_launch(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn, int nrows, T* grid, V2<T>* spec) {
+template <bool FWD, int RP, class T>
+static bool x2_launch_rp(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn, int nrows, T* grid,
+                         V2<T>* spec) {
 #define PQ_X2(A, B)                                                                                          \
     if (r1 == A && r2 == B) {                                                                                \
         if (FWD)                                                                                             \
-            PQ_LAUNCH((k_fft_x2_r2c<A, B, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,          \
+            PQ_LAUNCH((k_fft_x2_r2c<A, B, RP, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,      \
                       (const T*)grid, spec);                                                                 \
         else                                                                                                 \
-            PQ_LAUNCH((k_fft_x2_c2r<A, B, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,          \
+            PQ_LAUNCH((k_fft_x2_c2r<A, B, RP, T>), cdiv(npairs, RP), RP*(A > B ? A : B), 0, s, wn, nrows,      \
                       (const V2<T>*)spec, grid);                                                             \
         return true;                                                                                         \
     }
@@ -939,6 +941,15 @@ static bool x2_launch(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn
     PQ_X2(6, 5) PQ_X2(10, 5) PQ_X2(9, 6) PQ_X2(10, 6) PQ_X2(10, 9) PQ_X2(12, 8) PQ_X2(10, 10) PQ_X2(12, 10)
 #undef PQ_X2
     return false;
+}
+// row pairs per workgroup from the LDS budget: RP n complex values
+template <bool FWD, class T>
+static bool x2_launch(int r1, int r2, int npairs, hipStream_t s, const V2<T>* wn, int nrows, T* grid, V2<T>* spec,
+                      int budget) {
+    const size_t row = (size_t)r1 * r2 * sizeof(V2<T>);
+    if ((size_t)budget >= 16 * row) return x2_launch_rp<FWD, 16, T>(r1, r2, npairs, s, wn, nrows, grid, spec);
+    if ((size_t)budget >= 8 * row) return x2_launch_rp<FWD, 8, T>(r1, r2, npairs, s, wn, nrows, grid, spec);
+    return x2_launch_rp<FWD, 4, T>(r1, r2, npairs, s, wn, nrows, grid, spec);
 }
 
 template <class T>
@@ -963,7 +974,7 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
     const C* wn0 = static_cast<const C*>(c.fft[0].wn);
     const int x1 = c.fft[0].r1, x2 = c.fft[0].r2;
     // x forward
-    if (!x2_launch<true, T>(x1, x2, npairs, s, wn0, nrows, grid, spec))
+    if (!x2_launch<true, T>(x1, x2, npairs, s, wn0, nrows, grid, spec, c.fft_budget))
         PQ_LAUNCH(k_fft_x_r2c<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, grid,
                   spec);
     const C* wn1 = static_cast<const C*>(c.fft[1].wn);
@@ -990,7 +1001,7 @@ static void fft_convolve_t(Ctx& c, hipStream_t s) {
         PQ_LAUNCH((k_fft_col<1, false, T>), dim3(cdiv(X, ty), K2), 256, (2 * K1 * ty + py.ntw) * esz, s, py, tw1, X,
                   ty, (size_t)X, (size_t)X * K1, spec, cv, (double*)nullptr);
     // x inverse
-    if (!x2_launch<false, T>(x1, x2, npairs, s, wn0, nrows, grid, spec))
+    if (!x2_launch<false, T>(x1, x2, npairs, s, wn0, nrows, grid, spec, c.fft_budget))
         PQ_LAUNCH(k_fft_x_c2r<T>, cdiv(npairs, np), 256, (2 * np * K0 + px.ntw) * esz, s, px, tw0, nrows, np, spec,
                   grid);
 }
