@@ -366,9 +366,10 @@ typedef struct pq_tune_result {
 /* Times the pair-kernel shapes 0, 1, 2, 3, 4, 6, 8 jointly with FFT buffer
  * sizes of 18432, 9216 and 4608 bytes and (PME) the fork points 0, 1, 2 on
  * `reps` (1..1000) potential + force evaluations each, after one warm-up, of
- * the current system with charges q (device, n), and keeps the fastest for
- * this context (also across later pq_set_system calls). Phase timing must be
- * off. Host-synchronising; out may be NULL. */
+ * the current system with charges q (device, n); the four fastest are timed
+ * again twice, interleaved, on 2 x reps evaluations each, and the fastest mean
+ * is kept for this context (also across later pq_set_system calls; out->ms is
+ * that mean). Phase timing must be off. Host-synchronising; out may be NULL. */
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out);
 /* Applies a stored choice (pair_wg_per_cu in 0..64; fft_lds_bytes 0 or
  * 1024..65536; pair_fork 0..2). */

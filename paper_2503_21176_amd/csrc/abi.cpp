@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "pmeqeq.h"
 #include "pq_internal.h"
@@ -534,28 +535,48 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
     const int nfork = c.prm.method == PQ_METHOD_PME ? 3 : 1;
     int best = 0, best_b = 18432, best_f = 0, ntried = 0;
     double best_ms = 1e300, ms0 = 0.0;
+    struct Cand {
+        double ms;
+        int k, b, f;
+    };
+    std::vector<Cand> tried;
+    // mean time of one evaluation over `r` evaluations after one warm-up
+    auto time_config = [&](int k, int bgt, int fk, int r) {
+        c.pair_grid = k * ncu;
+        c.fft_budget = bgt;
+        c.fork_at = fk;
+        coulomb_eval(c, q, phi.p, f.p, e.p, s);
+        PQ_HIP(hipEventRecord(e0, s));
+        for (int i = 0; i < r; ++i) coulomb_eval(c, q, phi.p, f.p, e.p, s);
+        PQ_HIP(hipEventRecord(e1, s));
+        PQ_HIP(hipEventSynchronize(e1));
+        float el = 0.f;
+        PQ_HIP(hipEventElapsedTime(&el, e0, e1));
+        return (double)el / r;
+    };
     try {
         for (int fk = 0; fk < nfork; ++fk)
         for (int bgt : budgets)
         for (int k : cand) {
-            c.pair_grid = k * ncu;
-            c.fft_budget = bgt;
-            c.fork_at = fk;
             ++ntried;
-            coulomb_eval(c, q, phi.p, f.p, e.p, s);
-            PQ_HIP(hipEventRecord(e0, s));
-            for (int r = 0; r < reps; ++r) coulomb_eval(c, q, phi.p, f.p, e.p, s);
-            PQ_HIP(hipEventRecord(e1, s));
-            PQ_HIP(hipEventSynchronize(e1));
-            float el = 0.f;
-            PQ_HIP(hipEventElapsedTime(&el, e0, e1));
-            const double ms = (double)el / reps;
+            const double ms = time_config(k, bgt, fk, reps);
             if (k == 0 && bgt == 18432 && fk == 0) ms0 = ms;
+            tried.push_back({ms, k, bgt, fk});
+        }
+        // the closest few are timed again, longer and interleaved, so that the
+        // noise of one short measurement does not pick the configuration
+        std::sort(tried.begin(), tried.end(), [](const Cand& x, const Cand& y) { return x.ms < y.ms; });
+        const size_t top = std::min<size_t>(4, tried.size());
+        std::vector<double> acc(top, 0.0);
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = 0; i < top; ++i) acc[i] += time_config(tried[i].k, tried[i].b, tried[i].f, 2 * reps);
+        for (size_t i = 0; i < top; ++i) {
+            const double ms = acc[i] / 2.0;
             if (ms < best_ms) {
                 best_ms = ms;
-                best = k;
-                best_b = bgt;
-                best_f = fk;
+                best = tried[i].k;
+                best_b = tried[i].b;
+                best_f = tried[i].f;
             }
         }
     } catch (...) {
