@@ -208,6 +208,16 @@ __global__ void k_pme_weights(int n, const V4<T>* __restrict__ pme_frac, T* __re
 // base index, charge; one atom per lane) into an LDS table, so its update
 // steps wait on LDS only.
 constexpr int SPREAD_BATCH = 16;
+// value v of lane i (i wave-uniform), through the scalar unit
+__device__ __forceinline__ float lane_value(float v, int i) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+__device__ __forceinline__ double lane_value(double v, int i) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 #ifndef SPREAD_WAVES
 #define SPREAD_WAVES 2
 #endif
@@ -241,34 +251,40 @@ __global__ __launch_bounds__(64 * SW) void k_spread_stage(PmeGeo G, const int* _
     // the wave's atoms are s0 + wv, s0 + wv + SW, ...
     for (int k0 = s0 + wv; k0 < s1; k0 += SW * SPREAD_BATCH) {
         const int nb = min(SPREAD_BATCH, (s1 - k0 + SW - 1) / SW);
+        // lane l < nb holds atom l's x weights, base index and charge in
+        // registers (read by every lane through readlane) and puts its y and z
+        // weights in the LDS table (each lane reads its own row's)
+        V4<T> wxa = mk4<T>(T(0), T(0), T(0), T(0)), wxb = wxa;
+        T base = T(0), qa = T(0);
         if (lane < nb) {
             const int k = k0 + SW * lane;
             const V4<T>* wk = reinterpret_cast<const V4<T>*>(pme_w + (size_t)k * PME_WSTRIDE);
             T* row = tb[lane];
+            wxa = wk[0];
+            wxb = wk[1];
 #pragma unroll
-            for (int u = 0; u < 6; ++u) {
+            for (int u = 2; u < 6; ++u) {
                 const V4<T> w4 = wk[u];
                 row[4 * u + 0] = w4.x;
                 row[4 * u + 1] = w4.y;
                 row[4 * u + 2] = w4.z;
                 row[4 * u + 3] = w4.w;
             }
-            row[24] = pme_frac[k].w;
-            row[25] = qbrick[k];
+            base = pme_frac[k].w;
+            qa = qbrick[k];
         }
         // the table is written and read by different lanes
         __builtin_amdgcn_wave_barrier();
         for (int i = 0; i < nb; ++i) {
             const T* at = tb[i];
-            // x weights, base index and charge as vector reads of the table row
-            const V4<T> w03 = *reinterpret_cast<const V4<T>*>(at);
-            const V4<T> w47 = *reinterpret_cast<const V4<T>*>(at + 4);
-            const V2<T> bq = *reinterpret_cast<const V2<T>*>(at + 24);
-            const T wxs[8] = {w03.x, w03.y, w03.z, w03.w, w47.x, w47.y, w47.z, w47.w};
-            const int pk = unpack_int(bq.x);
+            const T wxs[8] = {lane_value(wxa.x, i), lane_value(wxa.y, i), lane_value(wxa.z, i), lane_value(wxa.w, i),
+                              P > 4 ? lane_value(wxb.x, i) : T(0), P > 5 ? lane_value(wxb.y, i) : T(0),
+                              P > 6 ? lane_value(wxb.z, i) : T(0), P > 7 ? lane_value(wxb.w, i) : T(0)};
+            const int pk = unpack_int(lane_value(base, i));
+            const T qi = lane_value(qa, i);
             const int gx = pk & 1023, gy = (pk >> 10) & 1023, gz = (pk >> 20) & 1023;
             if (active) {
-                const T c = bq.y * at[8 + ty] * at[16 + tz];
+                const T c = qi * at[8 + ty] * at[16 + tz];
                 T* rowp = my + ((gz - tz - z0) * R + (gy - ty - y0)) * R + (gx - x0);
                 T v[P];
 #pragma unroll
