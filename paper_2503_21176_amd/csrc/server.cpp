@@ -196,8 +196,13 @@ pq_status pq_server_create(pq_server** out, const pq_server_cfg* cfg) {
         throw;
     }
     pq_server* raw = S.get();
-    S->sched = std::make_unique<Sched>(cfg->slots, cfg->hbm_budget_bytes,
-                                       [raw](int k, Req& r) { run_request(raw->cfg, &raw->slots[k], r); });
+    try {
+        S->sched = std::make_unique<Sched>(cfg->slots, cfg->hbm_budget_bytes,
+                                           [raw](int k, Req& r) { run_request(raw->cfg, &raw->slots[k], r); });
+    } catch (...) {
+        release_slots(*S);
+        throw;
+    }
     *out = S.release();
     return PQ_OK;
     PQ_API_END
