@@ -57,8 +57,21 @@ public:
     Sched(int slots, double budget, Exec exec) : budget_(budget), exec_(std::move(exec)) {
         t0_ = std::chrono::steady_clock::now();
         for (int k = 0; k < slots; ++k) slots_.push_back(std::make_unique<Slot>());
-        for (int k = 0; k < slots; ++k) slots_[k]->th = std::thread(&Sched::slot_main, this, k);
-        sched_ = std::thread(&Sched::sched_main, this);
+        try {
+            for (int k = 0; k < slots; ++k) slots_[k]->th = std::thread(&Sched::slot_main, this, k);
+            sched_ = std::thread(&Sched::sched_main, this);
+        } catch (...) {
+            // a thread could not start: end the ones that did before unwinding
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                for (auto& sl : slots_) sl->quit = true;
+            }
+            for (auto& sl : slots_) {
+                sl->cv.notify_all();
+                if (sl->th.joinable()) sl->th.join();
+            }
+            throw;
+        }
     }
     ~Sched() { stop(); }
     Sched(const Sched&) = delete;
