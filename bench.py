@@ -403,7 +403,7 @@ def main():
         print(json.dumps(serve(P, W, args)), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library computes one system on one GPU; --gpus must be 1 (the multi-GPU decomposition is not built)"}))
         sys.exit(2)
 
     import torch
