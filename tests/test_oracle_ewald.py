@@ -133,3 +133,35 @@ def test_brute_force_spherical_lattice_sum():
     # the dipole term is about half of the energy here, so a wrong reciprocal
     # normalisation or sign could not reach this agreement
     assert errs[2] < 5e-6 * abs(target)
+
+
+# Madelung constants of two more binary crystals (textbook values, per ion pair,
+# referred to the nearest-neighbour distance): their geometries differ from
+# rock salt, so a wrong image set, k-vector set or self term would not match
+# all three.
+MADELUNG_CSCL = 1.762674773
+MADELUNG_ZINCBLENDE = 1.638055053
+
+
+def _crystal(basis, charges, ncell, a):
+    cells = np.stack(np.meshgrid(*[np.arange(ncell)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = (cells[:, None, :] + np.asarray(basis)[None, :, :]).reshape(-1, 3) * a
+    q = np.tile(np.asarray(charges, dtype=np.float64), len(cells))
+    return pos, q, [ncell * a] * 3
+
+
+@pytest.mark.parametrize("name", ["cscl", "zincblende"])
+def test_madelung_constants_of_other_lattices(name):
+    a = 4.0
+    if name == "cscl":
+        basis, charges, r0, M = [[0, 0, 0], [0.5, 0.5, 0.5]], [1, -1], a * math.sqrt(3) / 2, MADELUNG_CSCL
+    else:
+        fcc = [[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]]
+        basis = fcc + [[x + 0.25, y + 0.25, z + 0.25] for x, y, z in fcc]
+        charges, r0, M = [1] * 4 + [-1] * 4, a * math.sqrt(3) / 4, MADELUNG_ZINCBLENDE
+    pos, q, box = _crystal(basis, charges, 3, a)
+    # rc 11 A, alpha 0.5/A, kmax 12: both truncations far below the tolerance
+    r = O.ewald_direct(pos, q, box, 0.5, 11.0, 12)
+    qphi = q * r["phi"]
+    assert np.ptp(qphi) < 1e-9                  # all ions equivalent
+    assert abs(-qphi.mean() * r0 / O.KE - M) < 1e-9
