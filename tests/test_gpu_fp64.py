@@ -94,6 +94,35 @@ def test_nacl_madelung_fp64(P):
     assert np.abs(F).max() < 1e-9
 
 
+@pytest.mark.parametrize("name", ["cscl", "zincblende"])
+def test_madelung_other_lattices_fp64(P, name):
+    """CsCl and zinc blende (3x3x3 cubic cells of 4 A, box 12 A, rc 11 A: the
+    real-space sum reaches past the nearest image) with the direct Ewald
+    method at truncations far below 1e-9: the oracle to 1e-11 and the
+    textbook Madelung constants to 1e-9."""
+    import math
+    a = 4.0
+    if name == "cscl":
+        basis, charges, r0, M_ref = [[0, 0, 0], [0.5, 0.5, 0.5]], [1, -1], a * math.sqrt(3) / 2, 1.762674773
+    else:
+        fcc = [[0, 0, 0], [0, 0.5, 0.5], [0.5, 0, 0.5], [0.5, 0.5, 0]]
+        basis = fcc + [[x + 0.25, y + 0.25, z + 0.25] for x, y, z in fcc]
+        charges, r0, M_ref = [1] * 4 + [-1] * 4, a * math.sqrt(3) / 4, 1.638055053
+    cells = np.stack(np.meshgrid(*[np.arange(3)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    pos = (cells[:, None, :] + np.asarray(basis, dtype=np.float64)[None]).reshape(-1, 3) * a
+    q = np.tile(np.asarray(charges, dtype=np.float64), len(cells))
+    box = np.array([3 * a] * 3)
+    s = W.System(name, pos, q, box, {})
+    prm = P.make_params(box, 11.0, 0.5, kmax=12, method="ewald", fp64=True)
+    phi, F, E = run(P, s, prm)
+    ref = O.ewald_direct(pos, q, box, 0.5, 11.0, 12)
+    check(name, phi, F, E, ref, forces=False)
+    M = -float(np.mean(q * phi)) * r0 / O.KE
+    say(f"[fp64 {name}] Madelung {M:.12f} (textbook {M_ref})")
+    assert abs(M - M_ref) < 1e-9
+    assert np.abs(F).max() < 1e-9
+
+
 @pytest.mark.parametrize("n,order,K", [(64, 5, 10), (300, 6, 16), (300, 4, 15)])
 def test_small_boxes_pme_fp64(P, n, order, K):
     L = (n / 0.1) ** (1 / 3)
