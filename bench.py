@@ -517,7 +517,7 @@ def main():
     # the implementation's five passes (x, y, z, y, x) move the spectrum three more times
     pme_roof["fft"]["pass_bytes"] = 2 * (4 * ng + 8 * nspec) + 6 * 8 * nspec
 
-    # shadow-MD QEQ step: rebuild + v = phi[n] + shadow force (2 evals) + 8 Krylov products
+    # shadow-MD QEQ step: rebuild + v = phi[n] + the shadow force (one bilinear evaluation) + 8 Krylov products
     n_vec = q
     for _ in range(2):
         ctx.shadow_step(chi, eta, n_vec, n_krylov=8)
