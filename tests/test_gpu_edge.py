@@ -1,7 +1,8 @@
 """Edge cases on the GPU against the FP64 oracle: every FFT path (grid sizes
 with two register radices and sizes that take the Stockham passes, mixed in
 one box), a single charge and a pair in boxes shorter than the cutoff (only
-periodic images interact), and the rejected empty system."""
+periodic images interact), the rejected empty system, and zero and doubled
+charges (exact zeros; exact linear and quadratic scaling)."""
 import sys
 
 import numpy as np
@@ -112,3 +113,31 @@ def test_empty_system_is_rejected(P):
         ctx.set_system(torch.zeros((0, 3), dtype=torch.float64, device="cuda"),
                        P.make_params(10.0, 4.0, 0.5, grid=16, order=4))
     ctx.close()
+
+
+@pytest.mark.parametrize("method,fp64", [("pme", False), ("pme", True), ("ewald", False)])
+def test_zero_and_scaled_charges(P, method, fp64):
+    """The potential is linear and the forces and energy quadratic in the
+    charges (eqs. ewald_real/rec/self): zero charges give exact zeros, and
+    doubling the charges, which every floating-point step carries exactly,
+    doubles phi and quadruples F and E bit for bit, on a 3000-atom system."""
+    s = W.random_ionic(n=3000, seed=17)
+    if method == "pme":
+        prm = P.make_params(s.box, 9.0, W.ALPHA_RC9, grid=32, order=6, fp64=fp64)
+    else:
+        prm = P.make_params(s.box, 9.0, W.ALPHA_RC9, kmax=6, method="ewald", fp64=fp64)
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), prm)
+    outs = []
+    for scale in (0.0, 1.0, 2.0):
+        phi, F, E = ctx.coulomb(gpu(scale * s.q))
+        torch.cuda.synchronize()
+        outs.append((phi.cpu().numpy(), F.cpu().numpy(), E.cpu().numpy()))
+    ctx.close()
+    (p0, f0, e0), (p1, f1, e1), (p2, f2, e2) = outs
+    say(f"[scaling {method} fp64={fp64}] max|phi0| {np.abs(p0).max():.1e}, phi x2 exact "
+        f"{np.array_equal(p2, 2 * p1)}, F x4 exact {np.array_equal(f2, 4 * f1)}")
+    assert not np.any(p0) and not np.any(f0) and not np.any(e0)
+    assert np.array_equal(p2, 2 * p1)
+    assert np.array_equal(f2, 4 * f1)
+    assert np.array_equal(e2, 4 * e1)
