@@ -200,6 +200,20 @@ def test_random_ionic_300k_sampled(P):
     assert abs(E[2] - ref["E_rec"]) <= 1e-5 * abs(ref["E_rec"])
     # total charge is zero, so E = 1/2 sum q phi and the parts must add up
     assert abs(E[0] - E[1:].sum()) <= 1e-12 * abs(E[0])
+    # the autotuned launch configuration (the one the benchmark times) gives
+    # the same bits for every atom, and doubling the charges doubles phi and
+    # quadruples F exactly
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), P.make_params(s.box, 10.0, a, grid=144, order=6))
+    t = ctx.autotune(gpu(s.q), reps=2)
+    say(f"[ionic-300k] autotuned: {t}")
+    phi_t, F_t, _ = ctx.coulomb(gpu(s.q))
+    phi_2, F_2, _ = ctx.coulomb(gpu(2.0 * s.q))
+    torch.cuda.synchronize()
+    phi_t, F_t, phi_2, F_2 = (x.cpu().numpy() for x in (phi_t, F_t, phi_2, F_2))
+    ctx.close()
+    assert np.array_equal(phi_t, phi) and np.array_equal(F_t, F)
+    assert np.array_equal(phi_2, 2 * phi) and np.array_equal(F_2, 4 * F)
 
 
 # ---------------------------------------------------------------------------
