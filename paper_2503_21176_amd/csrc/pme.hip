@@ -399,8 +399,9 @@ __global__ __launch_bounds__(64 * REDUCE_ROWS) void k_spread_reduce(PmeGeo G, co
 // BIL: the two-charge (bilinear) reciprocal force of u (qbrick, convolved
 // grid psi_u in `grid`) and v (qbrick2, psi_v in `grid2`):
 //   F_i = -1/2 (u_i grad_i(theta . psi_v) + v_i grad_i(theta . psi_u)), no potential.
+constexpr int GATHER_THREADS = 256;   // per workgroup: 8 lanes per atom, 16 lanes per staged region row
 template <int P, bool FORCE, bool BIL, class T>
-__global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PmeGeo G, const int* __restrict__ brick_start,
                                                 const int* __restrict__ pme_idx, const V4<T>* __restrict__ pme_frac,
                                                 const T* __restrict__ pme_w, const T* __restrict__ qbrick,
                                                 const T* __restrict__ grid, const T* __restrict__ qbrick2,
@@ -417,12 +418,12 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
     if (s0 == s1) return;
     const int x0 = bx * PME_B - (P - 1), y0 = by * PME_B - (P - 1), z0 = bz * PME_B - (P - 1);
     {
-        // 16 lanes per region row, 16 rows per pass
+        // 16 lanes per region row, GATHER_THREADS / 16 rows per pass
         const int lx = threadIdx.x & 15;
         int X = x0 + lx;
         X += (X < 0) ? G.K0 : 0;
         X -= (X >= G.K0) ? G.K0 : 0;
-        for (int r = threadIdx.x >> 4; r < R * R; r += 16) {
+        for (int r = threadIdx.x >> 4; r < R * R; r += GATHER_THREADS / 16) {
             const int ly = r % R, lz = r / R;
             int Y = y0 + ly, Z = z0 + lz;
             Y += (Y < 0) ? G.K1 : 0;
@@ -440,9 +441,10 @@ __global__ __launch_bounds__(256) void k_gather(PmeGeo G, const int* __restrict_
     const int sub = threadIdx.x & 7, grp = threadIdx.x >> 3;
     const T kx = (T)(G.K0 * G.invL[0]), ky = (T)(G.K1 * G.invL[1]), kz = (T)(G.K2 * G.invL[2]);
     // every group runs the same number of iterations so the shuffles see full groups
-    const int iters = (s1 - s0 + 31) / 32;
+    constexpr int APW = GATHER_THREADS / 8;   // atoms per pass
+    const int iters = (s1 - s0 + APW - 1) / APW;
     for (int it = 0; it < iters; ++it) {
-        const int k = s0 + grp + 32 * it;
+        const int k = s0 + grp + APW * it;
         const bool valid = k < s1;
         T phi = 0, gxs = 0, gys = 0, gzs = 0;
         T hxs = 0, hys = 0, hzs = 0;   // BIL: gradient sums on psi_v
@@ -664,11 +666,11 @@ static void pme_eval_p(Ctx& c, const double* q, bool force, hipEvent_t* ev, hipS
                   as<T>(c.grid2));
     }
     if (force)
-        PQ_LAUNCH((k_gather<P, true, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p,
+        PQ_LAUNCH((k_gather<P, true, false, T>), c.nbrick, GATHER_THREADS, 0, s, G, c.brick_start.p, c.pme_idx.p,
                   as<v4>(c.pme_frac), as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), (const T*)nullptr,
                   (const T*)nullptr, as<T>(c.phi_k), as<v4>(c.f_k));
     else
-        PQ_LAUNCH((k_gather<P, false, false, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p,
+        PQ_LAUNCH((k_gather<P, false, false, T>), c.nbrick, GATHER_THREADS, 0, s, G, c.brick_start.p, c.pme_idx.p,
                   as<v4>(c.pme_frac), as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), (const T*)nullptr,
                   (const T*)nullptr, as<T>(c.phi_k), as<v4>(c.f_k));
     if (ev) PQ_HIP(hipEventRecord(ev[2 * PQ_PHASE_GATHER + 1], s));
@@ -695,7 +697,7 @@ static void pme_bilinear_p(Ctx& c, bool have_psi_v, hipStream_t s) {
                   as<T>(c.grid2));
     }
     chain(as<T>(c.qbrick));
-    PQ_LAUNCH((k_gather<P, true, true, T>), c.nbrick, 256, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
+    PQ_LAUNCH((k_gather<P, true, true, T>), c.nbrick, GATHER_THREADS, 0, s, G, c.brick_start.p, c.pme_idx.p, as<v4>(c.pme_frac),
               as<T>(c.pme_w), as<T>(c.qbrick), as<T>(c.grid), as<T>(c.qbrick2), as<T>(c.grid2), as<T>(c.phi_k),
               as<v4>(c.f_k));
 }
