@@ -22,7 +22,8 @@
  *   passes; the library never keeps a caller pointer after a call returns.
  * - Errors: every call returns a pq_status. Negative values are errors, in
  *   which case outputs are unspecified; pq_last_error() returns a message
- *   for the calling thread. No C++ exception crosses this boundary.
+ *   for the calling thread and pq_ctx_last_error(ctx) the context's last
+ *   one. No C++ exception crosses this boundary.
  * - A context is not thread safe: one thread at a time per context.
  */
 #ifndef PMEQEQ_H
@@ -136,6 +137,10 @@ double pq_coulomb_constant(void);
 /* Message of the last failed call on this thread ("" if none). Valid until
  * the next call on the same thread. */
 const char* pq_last_error(void);
+/* Message of the last failed call on this context ("" if none, or for a NULL
+ * context), whichever thread made it. Owned by the context; valid until the
+ * next call on it or pq_destroy. */
+const char* pq_ctx_last_error(const pq_ctx* ctx);
 
 /* ---- context ------------------------------------------------------------ */
 /* Device-memory allocator for a context's workspaces (the Python binding

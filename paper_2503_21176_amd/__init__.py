@@ -29,7 +29,7 @@ STATUS = {0: "PQ_OK", 1: "PQ_WARN_NOT_CONVERGED", -1: "PQ_ERR_INVALID", -2: "PQ_
 METHOD_PME, METHOD_EWALD, METHOD_AUTO = 0, 1, 2
 SOLVERS = {"gmres": 0, "minres": 1}
 
-EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_create", "pq_set_stream",
+EXPORTS = ["pq_abi_version", "pq_coulomb_constant", "pq_last_error", "pq_ctx_last_error", "pq_create", "pq_set_stream",
            "pq_destroy", "pq_set_system", "pq_neighbor_pairs", "pq_coulomb", "pq_set_timing", "pq_timings",
            "pq_qeq_solve", "pq_shadow_step", "pq_qeq_vjp", "pq_server_create", "pq_server_submit",
            "pq_server_poll", "pq_server_destroy", "pq_request_footprint", "pq_autotune", "pq_set_tuning",
@@ -102,6 +102,7 @@ def load() -> ctypes.CDLL:
         "pq_abi_version": (i32, []),
         "pq_coulomb_constant": (dbl, []),
         "pq_last_error": (ctypes.c_char_p, []),
+        "pq_ctx_last_error": (ctypes.c_char_p, [vp]),
         "pq_create": (i32, [ctypes.POINTER(vp), i32, vp, ctypes.POINTER(Allocator)]),
         "pq_set_stream": (i32, [vp, vp]),
         "pq_destroy": (i32, [vp]),
@@ -286,6 +287,10 @@ class Context:
         if getattr(self, "h", None):
             self.lib.pq_destroy(self.h)
             self.h = None
+
+    def last_error(self) -> str:
+        """Message of the last failed call on this context ("" if none)."""
+        return self.lib.pq_ctx_last_error(self.h).decode() if getattr(self, "h", None) else ""
 
     def __del__(self):  # pragma: no cover
         try:

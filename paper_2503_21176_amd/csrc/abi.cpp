@@ -16,13 +16,22 @@
 namespace pq {
 
 thread_local std::string g_err;
+thread_local Ctx* g_err_ctx = nullptr;   // context of the entry point running on this thread
 
 std::recursive_mutex& device_mem_lock() {
     static std::recursive_mutex m;
     return m;
 }
 
-void set_error(const std::string& m) { g_err = m; }
+void set_error(const std::string& m) {
+    g_err = m;
+    if (g_err_ctx) g_err_ctx->last_err = m;
+}
+
+CtxErrScope::CtxErrScope(pq_ctx* c) : prev(g_err_ctx) {
+    if (c) g_err_ctx = reinterpret_cast<Ctx*>(c);
+}
+CtxErrScope::~CtxErrScope() { g_err_ctx = prev; }
 
 // ---------------------------------------------------------------------------
 // Reduction scratch of pq_coulomb_noalloc: one file-scope device array (each
@@ -374,6 +383,10 @@ double pq_coulomb_constant(void) { return KE; }
 
 const char* pq_last_error(void) { return pq::g_err.c_str(); }
 
+const char* pq_ctx_last_error(const pq_ctx* ctx) {
+    return ctx ? reinterpret_cast<const Ctx*>(ctx)->last_err.c_str() : "";
+}
+
 pq_status pq_create(pq_ctx** out, int device, void* stream, const pq_allocator* alloc) {
     PQ_API_BEGIN
     PQ_REQUIRE(out != nullptr, PQ_ERR_INVALID, "out is NULL");
@@ -402,6 +415,7 @@ pq_status pq_create(pq_ctx** out, int device, void* stream, const pq_allocator* 
 }
 
 pq_status pq_set_stream(pq_ctx* ctx, void* stream) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
     reinterpret_cast<Ctx*>(ctx)->stream = static_cast<hipStream_t>(stream);
@@ -421,6 +435,7 @@ pq_status pq_destroy(pq_ctx* ctx) {
 }
 
 pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && pos != nullptr, PQ_ERR_INVALID, "ctx or pos is NULL");
     validate(n, prm);
@@ -444,6 +459,7 @@ pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_para
 }
 
 pq_status pq_update_positions(pq_ctx* ctx, const double* pos, int32_t* rebuilt) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && pos != nullptr, PQ_ERR_INVALID, "ctx or pos is NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
@@ -475,6 +491,7 @@ pq_status pq_update_positions(pq_ctx* ctx, const double* pos, int32_t* rebuilt) 
 }
 
 pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n_pairs) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && n_pairs != nullptr, PQ_ERR_INVALID, "ctx or n_pairs is NULL");
     PQ_REQUIRE(cap >= 0, PQ_ERR_INVALID, "cap must be >= 0");
@@ -493,6 +510,7 @@ pq_status pq_neighbor_pairs(pq_ctx* ctx, int64_t cap, int32_t* pairs, int64_t* n
 }
 
 pq_status pq_neighbor_ell(pq_ctx* ctx, int32_t K, int32_t* nbr, int32_t* img, int32_t* count, int32_t* k_max) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && k_max != nullptr, PQ_ERR_INVALID, "ctx or k_max is NULL");
     PQ_REQUIRE(K >= 0, PQ_ERR_INVALID, "K must be >= 0");
@@ -511,6 +529,7 @@ pq_status pq_neighbor_ell(pq_ctx* ctx, int32_t K, int32_t* nbr, int32_t* img, in
 }
 
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx and q must not be NULL");
     PQ_REQUIRE(reps >= 1 && reps <= 1000, PQ_ERR_INVALID, "reps must be in 1..1000");
@@ -603,6 +622,7 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
 }
 
 pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && t != nullptr, PQ_ERR_INVALID, "ctx and t must not be NULL");
     PQ_REQUIRE(t->pair_wg_per_cu >= 0 && t->pair_wg_per_cu <= 64, PQ_ERR_INVALID, "pair_wg_per_cu must be in 0..64");
@@ -622,6 +642,7 @@ pq_status pq_set_tuning(pq_ctx* ctx, const pq_tune_result* t) {
 }
 
 pq_status pq_set_timing(pq_ctx* ctx, int on) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
     PQ_REQUIRE(on >= 0 && on <= 2, PQ_ERR_INVALID, "timing mode must be 0, 1 or 2");
@@ -632,6 +653,7 @@ pq_status pq_set_timing(pq_ctx* ctx, int on) {
 }
 
 pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && ms != nullptr && count != nullptr, PQ_ERR_INVALID, "NULL argument");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
@@ -654,6 +676,7 @@ pq_status pq_timings(pq_ctx* ctx, double* ms, int64_t* count) {
 }
 
 pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);
@@ -665,6 +688,7 @@ pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, d
 }
 
 pq_status pq_coulomb_noalloc(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr && q != nullptr, PQ_ERR_INVALID, "ctx or q is NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);

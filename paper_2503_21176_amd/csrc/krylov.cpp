@@ -433,6 +433,7 @@ using namespace pq;
 extern "C" {
 
 pq_status pq_set_solver(pq_ctx* ctx, int32_t solver, int32_t vjp_restart) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx != nullptr, PQ_ERR_INVALID, "ctx is NULL");
     PQ_REQUIRE(solver == PQ_SOLVER_GMRES || solver == PQ_SOLVER_MINRES, PQ_ERR_INVALID, "unknown solver");
@@ -447,6 +448,7 @@ pq_status pq_set_solver(pq_ctx* ctx, int32_t solver, int32_t vjp_restart) {
 
 pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double q_tot, double tol, int max_it,
                        int restart, const double* q0, double* q, double* force, double* energy, pq_solve_info* info) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx && chi && eta && q, PQ_ERR_INVALID, "ctx, chi, eta and q must not be NULL");
     PQ_REQUIRE(tol > 0.0 && max_it >= 1 && restart >= 1 && restart <= PQ_MAX_RESTART, PQ_ERR_INVALID,
@@ -478,6 +480,7 @@ pq_status pq_qeq_solve(pq_ctx* ctx, const double* chi, const double* eta, double
 
 pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, double q_tot, const double* n_vec,
                          int n_krylov, double* q_n, double* force, double* nddot, double* energy) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx && chi && eta && n_vec && q_n, PQ_ERR_INVALID, "ctx, chi, eta, n_vec and q_n must not be NULL");
     PQ_REQUIRE(n_krylov >= 1 && n_krylov <= 512, PQ_ERR_INVALID, "n_krylov must be in 1..512");
@@ -548,6 +551,7 @@ pq_status pq_shadow_step(pq_ctx* ctx, const double* chi, const double* eta, doub
 
 pq_status pq_qeq_vjp(pq_ctx* ctx, const double* chi, const double* eta, const double* q_star, const double* gbar,
                      double tol, int max_it, double* d_pos, double* d_chi, double* d_eta) {
+    pq::CtxErrScope err_scope(ctx);
     PQ_API_BEGIN
     PQ_REQUIRE(ctx && chi && eta && q_star, PQ_ERR_INVALID, "ctx, chi, eta and q_star must not be NULL");
     Ctx& c = *reinterpret_cast<Ctx*>(ctx);

@@ -311,6 +311,7 @@ using namespace pq;
 extern "C" pq_status pq_md_run(pq_ctx* ctx, double* pos, double* vel, const double* mass, const double* chi,
                                const double* eta, double q_tot, double* n_hist, double* pos_ref, int32_t steps,
                                const pq_md_cfg* cfg, double* energies) {
+    pq::CtxErrScope err_scope(ctx);
     try {
         PQ_REQUIRE(ctx && pos && vel && mass && chi && eta && n_hist && cfg, PQ_ERR_INVALID,
                    "ctx, pos, vel, mass, chi, eta, n_hist and cfg must not be NULL");

@@ -256,6 +256,7 @@ struct InfTab {
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    std::string last_err;    // message of the last failed call on this context
     pq_allocator alloc{};    // workspace allocator (pq_create); null members: hipMalloc
     bool have_system = false;
     bool fp64 = false;       // bulk arithmetic in FP64 (PQ_FLAG_FP64) instead of FP32
@@ -477,5 +478,16 @@ void ensure_bilinear(Ctx& c);   // qv, qbrick2, grid2
 // once pq_set_system has sized the per-atom buffers)
 void coulomb_eval_ws(Ctx& c, const double* q, double* phi, double* force, double* energy,
                      hipStream_t s);
+
+// While alive, errors reported on this thread (set_error) are also recorded
+// as the context's last error; entry points that take a context hold one.
+void set_error(const std::string& m);
+struct CtxErrScope {
+    explicit CtxErrScope(pq_ctx* c);
+    ~CtxErrScope();
+    CtxErrScope(const CtxErrScope&) = delete;
+    CtxErrScope& operator=(const CtxErrScope&) = delete;
+    Ctx* prev;
+};
 
 }  // namespace pq

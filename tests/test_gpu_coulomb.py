@@ -298,6 +298,40 @@ def test_invalid_arguments_raise(P):
     ctx.close()
 
 
+def test_errors_are_recorded_per_context(P):
+    """pq_ctx_last_error: each context keeps the message of its own last failed
+    call, also when another thread made it; the thread's message
+    (pq_last_error) is the last failure on that thread."""
+    import threading
+    a, b = P.Context(0), P.Context(0)
+    assert a.last_error() == "" and b.last_error() == ""
+    with pytest.raises(P.PQError):
+        a.set_tuning(65)                                        # pair shape out of range
+    msg_a = a.last_error()
+    assert msg_a != "" and b.last_error() == ""
+
+    s = W.small_random(20, 6.0, seed=5)
+    pos = gpu(s.pos)
+    raised = []
+
+    def fail_b():
+        try:
+            b.set_system(pos, P.make_params(s.box, 3.0, 0.5, grid=14, order=4))   # 14 = 2*7
+        except P.PQError as e:
+            raised.append(e)
+
+    th = threading.Thread(target=fail_b)
+    th.start()
+    th.join()
+    assert len(raised) == 1
+    msg_b = b.last_error()
+    say(f"[errors] ctx a: {msg_a!r}; ctx b: {msg_b!r}")
+    assert msg_b != "" and msg_b != msg_a and a.last_error() == msg_a
+    assert P.load().pq_last_error().decode() == msg_a          # this thread's last failure
+    a.close()
+    b.close()
+
+
 def test_pair_launch_shapes_bitwise_and_autotune(P):
     # the pair kernel's launch shape (one wavefront per cluster, or k
     # workgroups per CU striding over clusters), the FFT tile sizes and the
