@@ -174,7 +174,8 @@ pq_status pq_destroy(pq_ctx* ctx);
  * closer than rc is included, so boxes shorter than 2 rc are supported.
  * Host-synchronising (the list size is read back). Re-call when positions
  * move. 1 <= n; the clustered atom slots (n plus at most 7 padding slots per
- * x-y column) must stay below 2^24, else PQ_ERR_TOO_LARGE. */
+ * x-y column) must stay below 2^24, else PQ_ERR_TOO_LARGE. A non-finite
+ * coordinate is PQ_ERR_NAN. */
 pq_status pq_set_system(pq_ctx* ctx, int64_t n, const double* pos, const pq_params* prm);
 
 /* Moves the system's atoms to pos (device n x 3 FP64, the same atoms in the
@@ -229,7 +230,9 @@ pq_status pq_neighbor_ell(pq_ctx* ctx, int32_t K, int32_t* nbr, int32_t* img, in
  * steps 1-5) or by the direct k-sum, and a neutralising background term
  * (zero for neutral q). Outputs (device, FP64, each may be NULL):
  *   phi[n], force[n*3], energy[4] = {E_Coul, E_real, E_rec, E_self+background}.
- * Bulk arithmetic is FP32; energies and charge sums are reduced in FP64. */
+ * Bulk arithmetic is FP32; energies and charge sums are reduced in FP64.
+ * Charges are not checked: a non-finite charge makes the outputs
+ * non-finite. */
 pq_status pq_coulomb(pq_ctx* ctx, const double* q, double* phi, double* force, double* energy);
 
 /* ---- Coulomb evaluation without device allocation ------------------------ */
