@@ -377,7 +377,8 @@ typedef struct pq_tune_result {
  * the current system with charges q (device, n); the four fastest are timed
  * again twice, interleaved, on 2 x reps evaluations each, and the fastest mean
  * is kept for this context (also across later pq_set_system calls; out->ms is
- * that mean). Phase timing must be off. Host-synchronising; out may be NULL. */
+ * that mean). Phase timing must be off. Host-synchronising; out may be NULL.
+ * If tuning fails, the context keeps the choice it had before the call. */
 pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result* out);
 /* Applies a stored choice (pair_wg_per_cu in 0..64; fft_lds_bytes 0 or
  * 1024..65536; pair_fork 0..2). */

@@ -559,6 +559,8 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
         int k, b, f;
     };
     std::vector<Cand> tried;
+    // the choice in force before tuning, kept if tuning fails
+    const int old_grid = c.pair_grid, old_budget = c.fft_budget, old_fork = c.fork_at;
     // mean time of one evaluation over `r` evaluations after one warm-up
     auto time_config = [&](int k, int bgt, int fk, int r) {
         c.pair_grid = k * ncu;
@@ -599,8 +601,13 @@ pq_status pq_autotune(pq_ctx* ctx, const double* q, int32_t reps, pq_tune_result
             }
         }
     } catch (...) {
+        (void)hipStreamSynchronize(s);
+        if (c.side) (void)hipStreamSynchronize(c.side);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
+        c.pair_grid = old_grid;
+        c.fft_budget = old_budget;
+        c.fork_at = old_fork;
         throw;
     }
     (void)hipEventDestroy(e0);
