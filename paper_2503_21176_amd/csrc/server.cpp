@@ -115,7 +115,11 @@ void run_request(const pq_server_cfg& cfg, pq_server::Slot* sl, Req& r) {
               hipMemcpyAsync(deta, r.eta.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok && r.has_q0)
         ok = hipMemcpyAsync(dq0, r.q0.data(), sizeof(double) * n, hipMemcpyHostToDevice, s) == hipSuccess;
-    if (!ok) st = PQ_ERR_HIP;
+    std::string copy_err;
+    if (!ok) {
+        st = PQ_ERR_HIP;
+        copy_err = "copy of the request's inputs to the device failed";
+    }
     if (st == PQ_OK) st = pq_set_solver(ctx, r.solver, 50);
     if (st == PQ_OK) st = pq_set_system(ctx, n, dpos, &r.params);
     if (st == PQ_OK)
@@ -124,12 +128,14 @@ void run_request(const pq_server_cfg& cfg, pq_server::Slot* sl, Req& r) {
     if (st >= 0) {
         if (hipMemcpyAsync(r.q.data(), dq, sizeof(double) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipMemcpyAsync(&r.energy, den, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
+            hipStreamSynchronize(s) != hipSuccess) {
             st = PQ_ERR_HIP;
+            copy_err = "copy of the result to the host failed";
+        }
     }
     (void)hipStreamSynchronize(s);
     r.status = st;
-    if (st < 0) r.message = pq_last_error();
+    if (st < 0) r.message = copy_err.empty() ? std::string(pq_ctx_last_error(ctx)) : copy_err;
 }
 
 // Contexts, streams and buffers of the slots (the worker threads have ended).

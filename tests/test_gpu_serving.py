@@ -191,3 +191,21 @@ def test_stated_hardness_full_gmres_and_minres(P):
         gap = float(np.linalg.norm(rg["q"] - rm["q"]) / np.linalg.norm(zd))
         assert gap <= 1.01 * kappa * (errs[0] + errs[1]) + 1e-12
         assert rg["iterations"] <= 201   # the budget, plus the product of the start residual
+
+
+def test_failed_request_reports_its_error(P):
+    """A request whose parameters the library rejects (a PME grid of 14 = 2*7
+    points) completes with that error status and the library's message; the
+    requests around it are unaffected."""
+    good = W.serving_request(120, 40_100)
+    bad = W.serving_request(100, 40_101)
+    srv = P.Server(0, slots=2)
+    K = good.params["grid"]
+    t0 = srv.submit(good.pos, good.chi, good.eta, params(P, good, K), tol=1e-6, max_it=300)
+    t1 = srv.submit(bad.pos, bad.chi, bad.eta, params(P, bad, 14), tol=1e-6, max_it=300)
+    t2 = srv.submit(good.pos, good.chi, good.eta + 15.0, params(P, good, K), tol=1e-6, max_it=300)
+    r0, r1, r2 = srv.poll(t0), srv.poll(t1), srv.poll(t2)
+    srv.close()
+    say(f"[serve-error] status {r1['status']}: {r1['message']!r}")
+    assert r1["status"] == -2 and "2^a 3^b 5^c" in r1["message"]
+    assert r0["status"] in (0, 1) and r2["status"] == 0
