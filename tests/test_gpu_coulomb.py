@@ -248,6 +248,30 @@ def test_neighbor_pairs_exact(P, case):
     assert np.array_equal(got, want)
 
 
+def test_many_columns_pair_set(P):
+    """More x-y columns (135 x 135) than the binning kernel's LDS counters hold,
+    which takes the atomic-count binning path: a 582 x 582 x 6.2 A slab of
+    210,008 atoms at 0.1 / A^3. The exported pair set (1.07M pairs within
+    2.9 A) equals scipy's periodic k-d tree enumeration, pair for pair."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(31)
+    L = np.array([582.0, 582.0, 6.2])
+    n = int(L.prod() * 0.1)
+    pos = rng.uniform(0.0, 1.0, (n, 3)) * L
+    rc = 2.9
+    ctx = P.Context(0)
+    ctx.set_system(gpu(pos), P.make_params(L, rc, 0.3, kmax=1, method="ewald"))
+    pr = ctx.neighbor_pairs().cpu().numpy().astype(np.int64)
+    ctx.close()
+    want = cKDTree(pos, boxsize=L).query_pairs(rc, output_type="ndarray").astype(np.int64)
+    say(f"[many-columns] n={n} gpu {len(pr)} pairs, k-d tree {len(want)}")
+    assert len(pr) == len(want)
+    # with rc < L/2 every pair has one image: compare the (i, j) sets
+    got = np.sort(np.minimum(pr[:, 0], pr[:, 1]) * n + np.maximum(pr[:, 0], pr[:, 1]))
+    ref = np.sort(np.minimum(want[:, 0], want[:, 1]) * n + np.maximum(want[:, 0], want[:, 1]))
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("case", ["nacl", "tiny-multi", "small-multi", "ionic-2000", "single"])
 def test_neighbor_ell_exact(P, case):
     """ELLPACK export (Section "Cell based Neighbor List"): the n x K matrix of
