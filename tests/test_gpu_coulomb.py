@@ -272,6 +272,29 @@ def test_many_columns_pair_set(P):
     assert np.array_equal(got, ref)
 
 
+def test_long_columns_pair_set(P):
+    """Columns longer than the rank sort's LDS capacity (2048 atoms): a
+    10 x 10 x 1200 A box of 12,000 atoms has 4 columns of about 3000 atoms,
+    ranked by the global-memory path. The pair set within 4 A equals scipy's
+    periodic k-d tree enumeration, pair for pair."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(32)
+    L = np.array([10.0, 10.0, 1200.0])
+    n = int(L.prod() * 0.1)
+    pos = rng.uniform(0.0, 1.0, (n, 3)) * L
+    rc = 4.0
+    ctx = P.Context(0)
+    ctx.set_system(gpu(pos), P.make_params(L, rc, 0.3, kmax=1, method="ewald"))
+    pr = ctx.neighbor_pairs().cpu().numpy().astype(np.int64)
+    ctx.close()
+    want = cKDTree(pos, boxsize=L).query_pairs(rc, output_type="ndarray").astype(np.int64)
+    say(f"[long-columns] n={n} gpu {len(pr)} pairs, k-d tree {len(want)}")
+    assert len(pr) == len(want)
+    got = np.sort(np.minimum(pr[:, 0], pr[:, 1]) * n + np.maximum(pr[:, 0], pr[:, 1]))
+    ref = np.sort(np.minimum(want[:, 0], want[:, 1]) * n + np.maximum(want[:, 0], want[:, 1]))
+    assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("case", ["nacl", "tiny-multi", "small-multi", "ionic-2000", "single"])
 def test_neighbor_ell_exact(P, case):
     """ELLPACK export (Section "Cell based Neighbor List"): the n x K matrix of
