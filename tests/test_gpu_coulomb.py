@@ -295,7 +295,7 @@ def test_long_columns_pair_set(P):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("case", ["nacl", "tiny-multi", "small-multi", "ionic-2000", "single"])
+@pytest.mark.parametrize("case", ["nacl", "tiny-multi", "small-multi", "ionic-2000", "single", "wide-rows"])
 def test_neighbor_ell_exact(P, case):
     """ELLPACK export (Section "Cell based Neighbor List"): the n x K matrix of
     every atom's neighbours, bit-exact against the rows built from the oracle's
@@ -308,6 +308,10 @@ def test_neighbor_ell_exact(P, case):
         s, rc, skin = W.small_random(64, 8.62, seed=4), 9.0, 0.0
     elif case == "single":
         s, rc, skin = W.small_random(1, 12.0, seed=1), 5.0, 0.0     # no neighbours at all
+    elif case == "wide-rows":
+        # rows of up to 1340 neighbours (more than 1024: a 2048-key row sort),
+        # rc 14.5 A in a 24.7 A box (pairs with several images)
+        s, rc, skin = W.small_random(1500, (1500 / 0.1) ** (1 / 3), seed=8), 14.5, 0.0
     else:
         s, rc, skin = W.random_ionic(n=2000, seed=11, grid=None), 10.0, 1.0
     want = ell_from_pairs(O.neighbor_pairs(s.pos, s.box, rc + skin), s.n)
