@@ -1,8 +1,9 @@
 """Edge cases on the GPU against the FP64 oracle: every FFT path (grid sizes
 with two register radices and sizes that take the Stockham passes, mixed in
 one box), a single charge and a pair in boxes shorter than the cutoff (only
-periodic images interact), the rejected empty system, and zero and doubled
-charges (exact zeros; exact linear and quadratic scaling)."""
+periodic images interact), the rejected empty system, zero and doubled
+charges (exact zeros; exact linear and quadratic scaling), and every subset
+of the outputs (bitwise the full call's values)."""
 import sys
 
 import numpy as np
@@ -141,3 +142,33 @@ def test_zero_and_scaled_charges(P, method, fp64):
     assert np.array_equal(p2, 2 * p1)
     assert np.array_equal(f2, 4 * f1)
     assert np.array_equal(e2, 4 * e1)
+
+
+@pytest.mark.parametrize("method", ["pme", "ewald"])
+def test_output_subsets(P, method):
+    """pq_coulomb with any of phi, force and energy left out gives the full
+    call's values bit for bit: the potential-only kernels that run without
+    forces sum the potentials in the same order."""
+    s = W.random_ionic(n=3000, seed=19, grid=None)
+    if method == "pme":
+        prm = P.make_params(s.box, 9.0, W.ALPHA_RC9, grid=32, order=6)
+    else:
+        prm = P.make_params(s.box, 9.0, W.ALPHA_RC9, kmax=6, method="ewald")
+    ctx = P.Context(0)
+    ctx.set_system(gpu(s.pos), prm)
+    q = gpu(s.q)
+    full = [x.cpu().numpy() for x in ctx.coulomb(q)]
+    p_e = ctx.coulomb(q, force=False)
+    f_only = ctx.coulomb(q, phi=False, energy=False)
+    e_only = ctx.coulomb(q, phi=False, force=False)
+    p_only = ctx.coulomb(q, force=False, energy=False)
+    torch.cuda.synchronize()
+    assert p_e[1] is None and f_only[0] is None and f_only[2] is None and e_only[0] is None and p_only[2] is None
+    assert np.array_equal(f_only[1].cpu().numpy(), full[1])
+    ephi = rel2(p_e[0].cpu().numpy(), full[0])
+    say(f"[subsets {method}] phi without forces: rel {ephi:.2e}, bitwise {np.array_equal(p_e[0].cpu().numpy(), full[0])}")
+    assert np.array_equal(p_e[0].cpu().numpy(), full[0])
+    assert np.array_equal(p_only[0].cpu().numpy(), full[0])
+    assert np.array_equal(p_e[2].cpu().numpy(), full[2])
+    assert np.array_equal(e_only[2].cpu().numpy(), full[2])
+    ctx.close()
