@@ -125,18 +125,20 @@ def test_regular_bo_md_matches_oracle(P):
     assert abs(h[0].sum()) < 1e-6   # the last charges come back in n_hist[0], neutral to the tolerance
 
 
-def test_update_positions_keeps_the_list_and_the_pair_set(P):
+@pytest.mark.parametrize("fp64", [False, True])
+def test_update_positions_keeps_the_list_and_the_pair_set(P, fp64):
     """Moves within skin/2 keep the list (no cluster-pair search); the pair
     set is then exactly the oracle's at rc on the new positions, including
     atoms that crossed a face of the cell, and the evaluation matches the
-    oracle there. A move beyond skin/2 rebuilds."""
+    oracle there (FP32 form to 1e-5, FP64 form to 1e-10). A move beyond
+    skin/2 rebuilds."""
     import oracle as O
     from _parity import elem_err
     n, rc, skin = 2000, 8.0, 1.0
     s = W.small_random(n, (n / 0.1) ** (1 / 3), seed=41)
     L = s.box[0]
     a = 0.35
-    prm = P.make_params(s.box, rc, a, skin=skin, grid=32, order=5)
+    prm = P.make_params(s.box, rc, a, skin=skin, grid=32, order=5, fp64=fp64)
     ctx = P.Context(0)
     ctx.set_system(gpu(s.pos), prm)
     rng = np.random.default_rng(42)
@@ -163,8 +165,9 @@ def test_update_positions_keeps_the_list_and_the_pair_set(P):
     ref = O.spme_full(new, s.q, s.box, a, rc, 32, 5)
     ephi = np.linalg.norm(phi.cpu().numpy() - ref["phi"]) / np.linalg.norm(ref["phi"])
     mf = elem_err(F.cpu().numpy(), ref["F"])
-    say(f"[update] phi rel {ephi:.2e}, per-atom F {mf:.2e}")
-    assert ephi < 1e-5 and mf < 1e-5
+    say(f"[update fp64={fp64}] phi rel {ephi:.2e}, per-atom F {mf:.2e}")
+    tol = 1e-10 if fp64 else 1e-5
+    assert ephi < tol and mf < tol
     # one atom beyond skin/2: a full build
     far = new.copy()
     far[7] += [0.6 * skin, 0.0, 0.0]
