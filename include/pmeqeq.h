@@ -66,7 +66,10 @@ enum { PQ_METHOD_PME = 0, PQ_METHOD_EWALD = 1, PQ_METHOD_AUTO = 2 /* pq_choose_p
  *   FP32 blocks of 8 rounds that are folded into a running sum with an error
  *   term (TwoSum), and the lanes' partial sums are combined the same way, so
  *   the long per-atom sums lose no more than one FP32 rounding per block
- *   (compensated per-cell partial sums). Ignored with PQ_FLAG_FP64. */
+ *   (compensated per-cell partial sums). Applies to the potential and
+ *   force evaluations (pq_coulomb, the QEQ products); the two-charge force
+ *   of pq_shadow_step and pq_qeq_vjp sums plainly. Ignored with
+ *   PQ_FLAG_FP64. */
 #define PQ_FLAG_COMPENSATED 2
 
 /* Parameters of one periodic system. The names follow the paper's problem
